@@ -1,0 +1,148 @@
+"""Throughput of the fused multicomponent LB step on one MI355X.
+
+Workload: neutral binary mixture on a 256^3 periodic D3Q19 lattice, FP32 populations,
+rest density 0.5 per species, 8 seeded concentration modes (amplitude 1e-3, antiphase
+between species) plus a shear wave u_y = 1e-3 sin(2 pi x / 256), tau_visc = 1, Sc = 100
+(synthetic inputs from workloads.binary_multimode, seed 2).  One step = one fused
+stream-collide launch (pull streaming, moments, drag, collision, store, FP64 mass partials).
+
+Prints one JSON line: species-site updates per second (GLUPS), the roofline of the
+stream-collide kernel against MI355X HBM bandwidth, and the FP64 CPU oracle timed on a
+bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+Q = 19
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbmix_kernels.hip", "lbmix_kernels.h"):
+        with open(os.path.join(ROOT, "paper_1507_04891_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(storage: str, n: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"stream_collide_{storage}_binary_{n}cubed_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, target_s: float = 12.0):
+    """The FP64 oracle on the same 256^3 workload, a bounded number of steps."""
+    import oracle
+
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag)
+    for s in range(w.nspecies):
+        o.set_state(s, w.n[s], w.u[s])
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    extra = max(0, min(20, int(target_s / max(t1, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    if extra:
+        o.step(extra)
+    t2 = time.perf_counter() - t0
+    steps = 1 + extra
+    elapsed = t1 + t2
+    sites = w.nspecies * w.nx * w.ny * w.nz
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": sites * steps / elapsed / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{steps} of the 2000 steps of the {w.nx}^3 binary workload, FP64, "
+                      f"{elapsed:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--sc", type=float, default=100.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the lattice would be "
+              "split into slabs with halo exchange; not built). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    w = WL.binary_multimode(n=args.n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=args.sc, seed=2)
+    stream = torch.cuda.current_stream()
+    lat = P.from_workload(w, storage=args.storage, stream=stream)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    lat.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+
+    sites = w.nspecies * w.nx * w.ny * w.nz
+    glups = sites * args.steps / (ms * 1e-3) / 1e9
+    esize = P.ELEMENT_BYTES[P.STORAGE[args.storage]]
+    bytes_per_launch = 2 * Q * esize * sites              # 19 reads + 19 writes per species-site
+    achieved = bytes_per_launch / (ms_per_step * 1e-3) / 1e9
+    totals = lat.mass_totals()
+    assert all(abs(t / (0.5 * args.n ** 3) - 1) < 1e-5 for t in totals), totals
+
+    out = {
+        "metric": "species-site updates/s (GLUPS), %HBM peak",
+        "value": round(glups, 4),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage.startswith("f32") else args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"neutral binary D3Q19 {args.n}^3 periodic, {args.storage} populations, "
+                               f"Sc={args.sc:g}, tau_visc=1, multimode noise + shear wave (seed 2)",
+                   "species": 2, "lattice": [args.n] * 3, "storage": args.storage, "schmidt": args.sc},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile(args.storage, args.n)},
+    }
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * lbmix.h -- C ABI of the MI355X (gfx950) multicomponent lattice-Boltzmann library.
+ *
+ * The library advances a mixture of NS species on a D3Q19 lattice with the modified BGK
+ * update of Monteferrante, Melchionna and Marini Bettolo Marconi, "Lattice Boltzmann Method
+ * for mixtures at variable Schmidt number" (arXiv:1507.04891):
+ *
+ *   f_p(r + c_p, t + 1) = f_p - omega_visc (f_p - phi_perp_p) + g_p          (Sec. IV, eq. latboeq)
+ *
+ * phi_perp_p is the orthogonalised equilibrium (last equation of the Appendix), g_p the
+ * second-order forcing term (Appendix, eq. ourforc) of the total force on the species: the
+ * interspecies drag (Sec. II, F^{alpha,drag}) plus, for charged species, the electrostatic
+ * force of the potential that solves the Poisson equation (Sec. II, eq. Poisson) with
+ * charged walls (the surface-charge condition that follows it) and an applied field.
+ *
+ * Conventions (all of them shared with the documentation of every call below):
+ *   - lattice units: unit spacing and time step, equal masses m = 1, charge unit e = 1,
+ *     k_B T / m = v_T^2 = 1/3;
+ *   - node index i = x + nx * (y + ny * z), x fastest; host arrays cover all nz planes,
+ *     vector fields are planar [3][nz][ny][nx], populations [19][nz][ny][nx];
+ *   - geometry LBMIX_PERIODIC: periodic in x, y, z;  LBMIX_SLIT_Z: periodic in x and y,
+ *     the planes z = 0 and z = nz-1 are solid walls at rest (half-way bounce-back, wall
+ *     surfaces at z = 1/2 and z = nz - 3/2); wall-plane entries of host arrays are ignored
+ *     on input and written as 0 on output;
+ *   - D3Q19 order: p = 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7..18 = (+1,+1,0), (-1,-1,0),
+ *     (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1), (0,+1,+1),
+ *     (0,-1,-1), (0,+1,-1), (0,-1,+1); weights 1/3, 1/18, 1/36;
+ *   - "time t" is the number of completed steps; moments read back are those of the
+ *     pre-collision populations at time t;
+ *   - readings of the paper applied here: the drag acts on the mid-step species velocities
+ *     u^alpha + a^alpha / 2, where a^alpha = z^alpha (E_ext - v_T^2 grad psi~) is the field
+ *     acceleration; grad psi~ by central differences, ghost value psi~ + 4 pi l_B sigma
+ *     across a wall; the collision at step t uses the potential solved from the charge
+ *     density of step t-1 (before the first step: of step 0).
+ *
+ * Status codes: every call returns LBMIX_OK (0) or a negative code; no C++ exception
+ * crosses the ABI.  lbmix_last_error() returns a text for the last failure of a context.
+ * A context is not thread-safe; distinct contexts are independent.  Device work is issued
+ * on the context's HIP stream; calls that return host data synchronise that stream.
+ */
+#ifndef LBMIX_H
+#define LBMIX_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBMIX_Q 19
+#define LBMIX_MAX_SPECIES 4
+
+enum lbmix_status {
+    LBMIX_OK = 0,
+    LBMIX_EINVAL = -1,     /* bad argument; nothing changed */
+    LBMIX_ENOMEM = -2,     /* device or host allocation failed */
+    LBMIX_EDEVICE = -3,    /* HIP runtime error (no GPU, launch failure, fault) */
+    LBMIX_ESTATE = -4,     /* call not allowed in the context's current state */
+    LBMIX_ENOCONV = -5,    /* Poisson solve hit its sweep cap before the tolerance */
+    LBMIX_ENONFINITE = -6  /* a mass total is NaN or Inf; latched until set_state / load */
+};
+
+enum lbmix_geometry { LBMIX_PERIODIC = 0, LBMIX_SLIT_Z = 1 };
+
+/* Population storage.  F64 and F32 store f.  The SHIFTED forms store the deviation
+ * f_p - w_p rho0 (rho0 = the species' rest density given to lbmix_add_species), in FP32,
+ * or in BF16 / FP16 times a power-of-two scale per species and direction; the collision
+ * arithmetic is FP64 for F64 and FP32 for all other forms.  Mass totals and the Poisson
+ * solve are FP64 in every form. */
+enum lbmix_storage {
+    LBMIX_F64 = 0,
+    LBMIX_F32 = 1,
+    LBMIX_F32_SHIFTED = 2,
+    LBMIX_BF16_SHIFTED = 3,
+    LBMIX_F16_SHIFTED = 4
+};
+
+typedef struct lbmix_ctx lbmix_ctx;
+
+typedef struct {
+    long long steps;          /* completed time steps */
+    long long poisson_solves; /* Poisson solves so far */
+    long long total_sweeps;   /* red-black sweeps so far */
+    int last_sweeps;          /* sweeps of the last solve */
+    int last_status;          /* LBMIX_OK or LBMIX_ENOCONV for the last solve */
+    double last_residual;     /* ||b - A psi||_2 / ||b||_2 after the last solve */
+    double fluid_nodes;       /* nx * ny * (nz, or nz - 2 for a slit) */
+    double bytes_per_step;    /* algorithmic HBM bytes of one stream-collide launch */
+} lbmix_stats;
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int lbmix_version(void);
+
+/* Create a lattice of nx * ny * nz nodes (wall planes included for LBMIX_SLIT_Z, which
+ * needs nz >= 3).  `storage` is an lbmix_storage.  `hip_stream` is a hipStream_t to issue
+ * all device work on (borrowed, not destroyed), or NULL for a stream owned by the context.
+ * No device memory is allocated until the first lbmix_set_state.  Defaults: tau_visc = 1,
+ * Schmidt number 1 (tau_drag = tau_visc), no charge, Poisson tolerance 1e-8.
+ * Errors: EINVAL for non-positive extents, nz < 3 for a slit, an unknown geometry or
+ * storage, or a lattice of more than 2^31 - 1 nodes. */
+int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage,
+                 void *hip_stream);
+
+/* Add a species with rest density rho0 > 0 (the storage shift of the SHIFTED forms and
+ * the reference density of the FP16 scale) and integer valence z^alpha (Sec. II; the
+ * ternary electrolyte of Sec. III has z = 0, +1, -1).  Writes its index to *id_out.
+ * Errors: ESTATE after the first set_state; EINVAL beyond LBMIX_MAX_SPECIES or rho0 <= 0. */
+int lbmix_add_species(lbmix_ctx *ctx, double rho0, int valence, int *id_out);
+
+/* omega_visc = 1 / tau_visc; kinematic viscosity nu = v_T^2 (tau_visc - 1/2) (Sec. IV).
+ * Errors: EINVAL unless tau_visc > 1/2; ESTATE after the first step. */
+int lbmix_set_tau_visc(lbmix_ctx *ctx, double tau_visc);
+
+/* omega_drag = 1 / tau_drag; mutual diffusivity D = v_T^2 (tau_drag - 1/2) (Sec. IV).
+ * Overrides a Schmidt number set before.  Errors: EINVAL unless tau_drag > 1/2; ESTATE
+ * after the first step. */
+int lbmix_set_tau_drag(lbmix_ctx *ctx, double tau_drag);
+
+/* Schmidt number Sc = nu / D: tau_drag = 1/2 + (tau_visc - 1/2) / Sc, re-evaluated when
+ * tau_visc changes.  Errors: EINVAL unless Sc > 0; ESTATE after the first step. */
+int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
+
+/* Electrostatics (Sec. II, eq. Poisson and its surface-charge condition): Bjerrum length
+ * l_B >= 0 (0: no Poisson solve), surface charges of the walls z = 0 and z = nz-1 in units
+ * of e per lattice area (used by LBMIX_SLIT_Z only), and the applied field E_ext[3] as an
+ * acceleration per unit valence (may be NULL for zero).  A charged run (l_B > 0 and a
+ * species with z != 0) needs nx and ny even or 1 (nz too for a periodic box) for the
+ * red-black ordering, and a neutral system: |sum z rho0 N + (sigma_lo + sigma_hi) nx ny|
+ * must be small against the charge carried by the species (checked at the first step).
+ * Errors: EINVAL for l_B < 0; ESTATE after the first step. */
+int lbmix_set_electrostatics(lbmix_ctx *ctx, double bjerrum, double sigma_lo,
+                             double sigma_hi, const double *E_ext);
+
+/* Poisson solver: red-black SOR (colour (x + y + z) mod 2, colour 0 first), warm-started
+ * from the previous potential.  rel_tol > 0: sweep until ||b - A psi||_2 / ||b||_2 <=
+ * rel_tol, checking every check_every sweeps, and report ENOCONV from lbmix_step when
+ * max_sweeps is reached first; rel_tol == 0: exactly max_sweeps sweeps per solve, never
+ * ENOCONV.  omega_sor in (0, 2), or <= 0 for 2 / (1 + sin(pi / L)), L the largest fluid
+ * extent.  After each solve psi is shifted to zero mean over the fluid.  Errors: EINVAL
+ * for rel_tol < 0, max_sweeps < 1, check_every < 1 or omega_sor >= 2. */
+int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_every,
+                      double omega_sor);
+
+/* Equilibrium initial state of one species at time 0 (re-initialises a running context,
+ * resetting its step counter and latched error once every species is set again):
+ * f_p = phi_perp_p(n, u^alpha), the pre-collision populations at time 0.  n is a host
+ * array [nz][ny][nx] of number densities, u a host array [3][nz][ny][nx] or NULL for
+ * rest.  Allocates device memory on the first call (ENOMEM, EDEVICE).  Errors: EINVAL for
+ * a bad species index or a NULL n. */
+int lbmix_set_state(lbmix_ctx *ctx, int species, const double *n, const double *u);
+
+/* Advance nsteps >= 0 time steps: per step one fused stream-collide launch (pull
+ * streaming with bounce-back, moments, drag and field forces, collision, store, charge
+ * density and FP64 mass partials) and, for charged runs, one Poisson solve.  Returns
+ * ENOCONV if any solve of this call hit its sweep cap (the steps are still taken), ESTATE
+ * before every species has a state, the latched code after ENONFINITE, EINVAL for a
+ * non-neutral charged system. */
+int lbmix_step(lbmix_ctx *ctx, int nsteps);
+
+/* Moments of the pre-collision populations at the current time into host arrays:
+ * n_out [nz][ny][nx] number density, j_out [3][nz][ny][nx] momentum density (either may
+ * be NULL).  FP64 output whatever the storage.  Synchronises.  Errors: EINVAL, ESTATE. */
+int lbmix_get_moments(lbmix_ctx *ctx, int species, double *n_out, double *j_out);
+
+/* Same as lbmix_get_moments into device memory (FP64, same layout, either may be NULL),
+ * ordered on the context stream, no synchronisation. */
+int lbmix_get_moments_device(lbmix_ctx *ctx, int species, double *n_dev, double *j_dev);
+
+/* Pre-collision populations f_p of one species at the current time, host [19][nz][ny][nx],
+ * FP64 (the shift of the SHIFTED forms added back).  Synchronises. */
+int lbmix_get_populations(lbmix_ctx *ctx, int species, double *f_out);
+
+/* The potential psi~ = e psi / k_B T the next collision will use (solved now if it is not
+ * yet available), host [nz][ny][nx], zero mean over the fluid.  Synchronises. */
+int lbmix_get_potential(lbmix_ctx *ctx, double *psi_out);
+
+/* FP64 totals sum_x n^alpha(x) of every species at the current time, host [nspecies],
+ * summed in a fixed order (bitwise reproducible).  A non-finite total latches ENONFINITE.
+ * Synchronises. */
+int lbmix_get_mass_totals(lbmix_ctx *ctx, double *totals);
+
+/* Plane averages over x and y of the pre-collision moments at the current time, host
+ * [nspecies][4][nz]: n, j_x, j_y, j_z per plane (wall planes 0), FP64 in a fixed order.
+ * These give the channel observables of Sec. IV: mass flow, electric current and its
+ * electro-osmotic part.  Synchronises. */
+int lbmix_get_zprofiles(lbmix_ctx *ctx, double *out);
+
+/* Counters of the context. */
+int lbmix_get_stats(lbmix_ctx *ctx, lbmix_stats *out);
+
+/* Block until all work issued on the context stream has finished. */
+int lbmix_sync(lbmix_ctx *ctx);
+
+/* Checkpoint: the stored populations (native storage), potential, step counter and every
+ * parameter, with a versioned header.  lbmix_load needs a context created with the same
+ * extents, geometry, storage and species; restoring and stepping reproduces an
+ * uninterrupted run bitwise.  Errors: EINVAL (mismatch, bad file), ESTATE, EDEVICE. */
+int lbmix_save(lbmix_ctx *ctx, const char *path);
+int lbmix_load(lbmix_ctx *ctx, const char *path);
+
+/* Text of the last error of this context ("" if none); valid until the next call. */
+const char *lbmix_last_error(const lbmix_ctx *ctx);
+
+/* Free the context and its device memory (ctx may be NULL). */
+void lbmix_destroy(lbmix_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMIX_H */

@@ -1,0 +1,98 @@
+// Internal interface between the C-ABI runtime and the gfx950 kernels of the library.
+// Not installed; the public interface is include/lbmix.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lbmix {
+
+constexpr int Q = 19;
+constexpr int MAXS = 4;
+constexpr int BLOCK = 256;        // threads per workgroup of every node kernel
+
+enum class Store : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
+
+// Arguments of the fused stream-collide launch.  Population arrays are [species][p][node]
+// over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
+// storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
+struct StepArgs {
+    const void *fin;
+    void *fout;
+    uint32_t nx, ny, nzf;
+    uint32_t N;                      // nx * ny * nzf
+    double rho_bar[MAXS];            // storage shift per species (0: plain f)
+    float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
+    float inv_scale[MAXS][Q];
+    double omega_v, omega_d;
+    double valence[MAXS];
+    double E[3];                     // applied field, acceleration per unit valence
+    const double *psi;               // potential on fluid nodes (charged runs)
+    double *q;                       // out: charge density on fluid nodes (charged runs)
+    double q_rest;                   // sum_s valence_s * rho_bar_s
+    double ghost_lo, ghost_hi;       // 4 pi l_B sigma of the walls z = 0 and z = nz-1
+    double *partials;                // out: [species][block] FP64 sums of n - rho_bar
+};
+
+struct PoissonArgs {
+    double *psi;                     // fluid nodes
+    const double *q;                 // fluid nodes
+    uint32_t nx, ny, nzf;
+    uint32_t N;
+    int slit;
+    double K;                        // 4 pi l_B
+    double lump_lo, lump_hi;         // wall charge added to the first / last fluid plane
+    const double *bmean;             // device scalar: mean of b over the fluid
+    double omega;                    // SOR factor
+};
+
+dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
+
+hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
+                                 const StepArgs &a, hipStream_t stream);
+
+// Equilibrium of species s from host-layout device arrays n[N_full], u[3][N_full] (u may
+// be null), scattered into the slots the first pull reads.
+hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n,
+                       const double *u, hipStream_t stream);
+
+// Pull-gathered pre-collision moments of species s into full-lattice arrays (wall planes
+// written as 0); j may be null.
+hipError_t launch_moments(Store st, bool slit, int s, const StepArgs &a, double *n, double *j,
+                          hipStream_t stream);
+
+// Pull-gathered pre-collision populations (shift added back) of species s, [19][N_full].
+hipError_t launch_populations(Store st, bool slit, int s, const StepArgs &a, double *f,
+                              hipStream_t stream);
+
+// Charge density q = q_rest + sum_s valence_s (n_s - rho_bar_s) of the pre-collision state
+// on fluid nodes.
+hipError_t launch_charge(Store st, bool slit, int ns, const StepArgs &a, double *q,
+                         hipStream_t stream);
+
+// Red-black SOR half-sweep of colour 0 or 1.
+hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream);
+
+// Per-block partials of (||b - A psi||^2, ||b||^2, sum psi); nblocks written to *nb.
+hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb,
+                           hipStream_t stream);
+
+// Per-block partials of sum q over the fluid; nblocks written to *nb.
+hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *nb,
+                       hipStream_t stream);
+
+// out[v] = sum_b partials[v * nblocks + b] for v < nv, in a fixed order; then
+// out[nv + k] for the post-processing `mode`:
+//   mode 0: none;  mode 1: out[nv] = -K (out[0] + lumps) / N   (mean of b);
+//   mode 2: out[nv] = out[2] / N                                (mean of psi).
+hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out,
+                           int mode, double K, double lumps, double N, hipStream_t stream);
+
+// psi -= *mean on the fluid nodes.
+hipError_t launch_shift(double *psi, uint32_t N, const double *mean, hipStream_t stream);
+
+// Plane sums over x and y of n and j (full-lattice arrays) into out[4][nz].
+hipError_t launch_plane_sums(const double *n, const double *j, uint32_t nx, uint32_t ny,
+                             uint32_t nz, double *out, hipStream_t stream);
+
+}  // namespace lbmix

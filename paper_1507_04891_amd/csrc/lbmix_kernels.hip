@@ -1,0 +1,669 @@
+// gfx950 kernels of the multicomponent lattice-Boltzmann library.
+//
+// The hot kernel is stream_collide: one thread per fluid node, all species' populations in
+// registers, pull streaming (each stored value is read exactly once, each output written
+// once, both coalesced along x), the moments of Sec. III, the drag of Sec. II and the field
+// force, and the collision of eq. (latboeq), Sec. IV, with the equilibrium of the Appendix
+// (phi_perp_p, which equals the second-order equilibrium at the species velocity) and the
+// forcing g_p of eq. (ourforc).  The step is bound by HBM bandwidth (about 3 flop per byte
+// in FP32), so there are no matrix-core contractions; the design goals are coalesced
+// streams, no re-reads, and no LDS round trips.
+//
+// Work-group shape: 256 threads along x for one (y, z) row (fewer when nx < 256), so y, z
+// and every bounce-back decision are wave-uniform and the x-shifted loads of a row stay in
+// one work-group (and one L2).  All arithmetic is done on deviations d_p = f_p - w_p
+// rho_bar, which makes the shifted storage forms exact in their range and costs nothing
+// for the plain ones (rho_bar = 0).
+#include "lbmix_kernels.h"
+
+#include <hip/hip_fp16.h>
+
+namespace lbmix {
+
+// ---------------------------------------------------------------------------------------
+// D3Q19 (order documented in include/lbmix.h).
+
+__host__ __device__ constexpr int cx(int p) {
+    constexpr int t[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return t[p];
+}
+__host__ __device__ constexpr int cy(int p) {
+    constexpr int t[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return t[p];
+}
+__host__ __device__ constexpr int cz(int p) {
+    constexpr int t[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return t[p];
+}
+__host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+template <class C>
+__host__ __device__ constexpr C wgt(int p) {
+    return p == 0 ? C(1) / C(3) : (p < 7 ? C(1) / C(18) : C(1) / C(36));
+}
+
+// ---------------------------------------------------------------------------------------
+// Storage codecs.  C is the arithmetic type, S the stored element.
+
+struct BF16 {};
+struct F16 {};
+
+template <class T> struct Codec;
+template <> struct Codec<double> {
+    using C = double;
+    using S = double;
+    __device__ static C load(const S *p, uint32_t i, float) { return p[i]; }
+    __device__ static void store(S *p, uint32_t i, C v, float) { p[i] = v; }
+};
+template <> struct Codec<float> {
+    using C = float;
+    using S = float;
+    __device__ static C load(const S *p, uint32_t i, float) { return p[i]; }
+    __device__ static void store(S *p, uint32_t i, C v, float) { p[i] = v; }
+};
+// bfloat16: upper half of an IEEE binary32; round-to-nearest-even written out.
+__device__ inline uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u)                 // Inf, NaN (kept quiet)
+        return (u & 0x007fffffu) ? uint16_t((u >> 16) | 0x0040u) : uint16_t(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+}
+template <> struct Codec<BF16> {
+    using C = float;
+    using S = uint16_t;
+    __device__ static C load(const S *p, uint32_t i, float inv) {
+        return __uint_as_float(uint32_t(p[i]) << 16) * inv;
+    }
+    __device__ static void store(S *p, uint32_t i, C v, float sc) { p[i] = f32_to_bf16_rne(v * sc); }
+};
+template <> struct Codec<F16> {
+    using C = float;
+    using S = uint16_t;
+    __device__ static C load(const S *p, uint32_t i, float inv) {
+        return __half2float(__ushort_as_half(p[i])) * inv;
+    }
+    __device__ static void store(S *p, uint32_t i, C v, float sc) {
+        p[i] = __half_as_ushort(__float2half_rn(v * sc));   // IEEE round-to-nearest-even
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Pull addressing shared by every kernel that reads a pre-collision state: the value of
+// direction p at node (x, y, z) comes from slot (p, node - c_p), or from slot (opp(p),
+// node) when node - c_p is a wall (half-way bounce-back at rest).
+
+struct Pull {
+    uint32_t xs, xm, xp;       // x, x-1, x+1 with periodic wrap (per lane)
+    uint32_t ym, yp, zm, zp;   // wrapped neighbours (uniform)
+    uint32_t y, z;
+    bool bb_lo, bb_hi;         // z - 1 / z + 1 is a wall (slit)
+    uint32_t nx, ny;
+
+    __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx_, uint32_t ny_, uint32_t nzf,
+                    bool slit)
+        : xs(x), y(y_), z(z_), nx(nx_), ny(ny_) {
+        xm = (x == 0) ? nx - 1 : x - 1;
+        xp = (x + 1 == nx) ? 0 : x + 1;
+        ym = (y == 0) ? ny - 1 : y - 1;
+        yp = (y + 1 == ny) ? 0 : y + 1;
+        zm = (z == 0) ? nzf - 1 : z - 1;
+        zp = (z + 1 == nzf) ? 0 : z + 1;
+        bb_lo = slit && z == 0;
+        bb_hi = slit && z + 1 == nzf;
+    }
+    __device__ uint32_t own() const { return (z * ny + y) * nx + xs; }
+    // slot direction and node of the value that direction p pulls
+    template <int p>
+    __device__ void src(int &arr, uint32_t &node) const {
+        constexpr int X = cx(p), Y = cy(p), Z = cz(p);
+        const bool bb = (Z == 1 && bb_lo) || (Z == -1 && bb_hi);
+        const uint32_t sx = X == 1 ? xm : (X == -1 ? xp : xs);
+        const uint32_t sy = Y == 1 ? ym : (Y == -1 ? yp : y);
+        const uint32_t sz = Z == 1 ? zm : (Z == -1 ? zp : z);
+        arr = bb ? opp(p) : p;
+        node = bb ? own() : (sz * ny + sy) * nx + sx;
+    }
+};
+
+template <int P, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (P > 0) {
+        static_for<P - 1>(f);
+        f(std::integral_constant<int, P - 1>{});
+    }
+}
+
+// Deterministic work-group sum of NV doubles (fixed shuffle tree, fixed wave order).
+template <int NV>
+__device__ void block_sum_store(double (&v)[NV], double *partials, uint32_t nblocks, uint32_t bid) {
+    __shared__ double red[NV][BLOCK / 64];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = v[k];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        v[k] = t;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nwaves = (blockDim.x + 63) >> 6;
+    if (lane == 0)
+        for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nwaves; ++w) s += red[threadIdx.x][w];
+        partials[(size_t)threadIdx.x * nblocks + bid] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// The fused step.
+
+template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED>
+__global__ __launch_bounds__(BLOCK) void stream_collide(const StepArgs a) {
+    using CD = Codec<T>;
+    using C = typename CD::C;
+    using S = typename CD::S;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = x < a.nx;
+    const Pull pl(active ? x : 0, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const uint32_t own = pl.own();
+    const S *fin = static_cast<const S *>(a.fin);
+    S *fout = static_cast<S *>(a.fout);
+
+    // 1. pull streaming with bounce-back: 19 loads per species
+    C d[NS][Q];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        static_for<Q>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            int arr;
+            uint32_t node;
+            pl.template src<p>(arr, node);
+            d[s][p] = CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]);
+        });
+    }
+
+    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c
+    C dn[NS], jx[NS], jy[NS], jz[NS], n[NS];
+    C ntot = 0, sjx = 0, sjy = 0, sjz = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        C m0 = 0, mx = 0, my = 0, mz = 0;
+        static_for<Q>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            m0 += d[s][p];
+            if constexpr (cx(p) == 1) mx += d[s][p];
+            if constexpr (cx(p) == -1) mx -= d[s][p];
+            if constexpr (cy(p) == 1) my += d[s][p];
+            if constexpr (cy(p) == -1) my -= d[s][p];
+            if constexpr (cz(p) == 1) mz += d[s][p];
+            if constexpr (cz(p) == -1) mz -= d[s][p];
+        });
+        dn[s] = m0;
+        jx[s] = mx;
+        jy[s] = my;
+        jz[s] = mz;
+        n[s] = C(a.rho_bar[s]) + m0;
+        ntot += n[s];
+        sjx += mx;
+        sjy += my;
+        sjz += mz;
+    }
+    const C inv_ntot = ntot != C(0) ? C(1) / ntot : C(0);
+    const C ux = sjx * inv_ntot, uy = sjy * inv_ntot, uz = sjz * inv_ntot;   // barycentric
+
+    // 3. field acceleration a_s = z_s (E - cs2 grad psi) and its charge-weighted mean
+    C fx = 0, fy = 0, fz = 0, qn = 0;
+    if constexpr (FIELD) {
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+        if constexpr (CHARGED) {
+            const double *psi = a.psi;
+            const uint32_t row = (pl.z * a.ny + pl.y) * a.nx;
+            const double here = psi[row + pl.xs];
+            gx = 0.5 * (psi[row + pl.xp] - psi[row + pl.xm]);
+            gy = 0.5 * (psi[(pl.z * a.ny + pl.yp) * a.nx + pl.xs] - psi[(pl.z * a.ny + pl.ym) * a.nx + pl.xs]);
+            const double up = pl.bb_hi ? here + a.ghost_hi : psi[(pl.zp * a.ny + pl.y) * a.nx + pl.xs];
+            const double dw = pl.bb_lo ? here + a.ghost_lo : psi[(pl.zm * a.ny + pl.y) * a.nx + pl.xs];
+            gz = 0.5 * (up - dw);
+        }
+        constexpr double cs2 = 1.0 / 3.0;
+        fx = C(a.E[0] - cs2 * gx);
+        fy = C(a.E[1] - cs2 * gy);
+        fz = C(a.E[2] - cs2 * gz);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) qn += C(a.valence[s]) * n[s];
+    }
+    if constexpr (CHARGED) {
+        if (active) {
+            double qq = a.q_rest;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) qq += a.valence[s] * double(dn[s]);
+            a.q[own] = qq;
+        }
+    }
+
+    // 4-5. forces and collision per species, pairing each direction with its opposite
+    const C ov = C(a.omega_v), od = C(a.omega_d), keep = C(1) - ov;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const C inv_n = n[s] != C(0) ? C(1) / n[s] : C(0);
+        const C uax = jx[s] * inv_n, uay = jy[s] * inv_n, uaz = jz[s] * inv_n;
+        // drag on mid-step velocities: -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s
+        C Fx = -od * (uax - ux), Fy = -od * (uay - uy), Fz = -od * (uaz - uz);
+        if constexpr (FIELD) {
+            const C k = C(a.valence[s]) * (C(1) - C(0.5) * od) + C(0.5) * od * qn * inv_ntot;
+            Fx += k * fx;
+            Fy += k * fy;
+            Fz += k * fz;
+        }
+        const C ns_ = n[s];
+        const C uu = uax * uax + uay * uay + uaz * uaz;
+        const C Fu = Fx * ux + Fy * uy + Fz * uz;
+        // part of w^-1 (f* - (1 - ov) d) common to p and opp(p)
+        const C base = ov * (dn[s] - C(1.5) * ns_ * uu) - C(3) * ns_ * Fu;
+        const C ov45 = C(4.5) * ov * ns_, n9 = C(9) * ns_, n3 = C(3) * ns_;
+        S *out = fout + (size_t)(s * Q) * a.N;
+        if (active) {
+            CD::store(out, own, keep * d[s][0] + wgt<C>(0) * base, a.scale[s][0]);
+            static_for<9>([&](auto kc) {
+                constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
+                constexpr int pb = p + 1;
+                constexpr C w = wgt<C>(p);
+                const C cu = C(cx(p)) * uax + C(cy(p)) * uay + C(cz(p)) * uaz;
+                const C cub = C(cx(p)) * ux + C(cy(p)) * uy + C(cz(p)) * uz;
+                const C cF = C(cx(p)) * Fx + C(cy(p)) * Fy + C(cz(p)) * Fz;
+                const C sym = w * (base + ov45 * cu * cu + n9 * cF * cub);
+                const C anti = w * n3 * (ov * cu + cF);
+                CD::store(out + (size_t)p * a.N, own, keep * d[s][p] + sym + anti, a.scale[s][p]);
+                CD::store(out + (size_t)pb * a.N, own, keep * d[s][pb] + sym - anti, a.scale[s][pb]);
+            });
+        }
+    }
+
+    // 7. FP64 mass partials of this work-group
+    double v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) v[s] = active ? double(dn[s]) : 0.0;
+    const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t nb = gridDim.x * gridDim.y * gridDim.z;
+    block_sum_store<NS>(v, a.partials, nb, bid);
+}
+
+// ---------------------------------------------------------------------------------------
+// Initial equilibrium, scattered to the slots of the first pull.
+
+template <class T, bool SLIT>
+__global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int s, const double *nf,
+                                                         const double *uf) {
+    using CD = Codec<T>;
+    using S = typename CD::S;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const size_t Nfull = (size_t)a.nx * a.ny * (SLIT ? a.nzf + 2 : a.nzf);
+    const size_t fi = ((size_t)(SLIT ? pl.z + 1 : pl.z) * a.ny + pl.y) * a.nx + x;
+    const double n = nf[fi];
+    const double ux = uf ? uf[fi] : 0.0, uy = uf ? uf[Nfull + fi] : 0.0, uz = uf ? uf[2 * Nfull + fi] : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double dn = n - a.rho_bar[s];
+    S *f = static_cast<S *>(a.fout);
+    static_for<Q>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        const double cu = cx(p) * ux + cy(p) * uy + cz(p) * uz;
+        const double dev = wgt<double>(p) * (dn + n * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        int arr;
+        uint32_t node;
+        pl.template src<p>(arr, node);
+        CD::store(f + (size_t)(s * Q + arr) * a.N, node, typename CD::C(dev), a.scale[s][arr]);
+    });
+}
+
+// Gathers of the pre-collision state at the current time.
+template <class T, bool SLIT, int MODE>   // MODE 0: moments, 1: populations
+__global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double *out0, double *out1) {
+    using CD = Codec<T>;
+    using S = typename CD::S;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const uint32_t zfull = blockIdx.z;
+    const uint32_t nzfull = SLIT ? a.nzf + 2 : a.nzf;
+    const size_t Nfull = (size_t)a.nx * a.ny * nzfull;
+    const size_t fi = ((size_t)zfull * a.ny + blockIdx.y) * a.nx + x;
+    if (SLIT && (zfull == 0 || zfull == nzfull - 1)) {
+        if constexpr (MODE == 0) {
+            out0[fi] = 0.0;
+            if (out1) out1[fi] = out1[Nfull + fi] = out1[2 * Nfull + fi] = 0.0;
+        } else {
+            for (int p = 0; p < Q; ++p) out0[(size_t)p * Nfull + fi] = 0.0;
+        }
+        return;
+    }
+    const Pull pl(x, blockIdx.y, SLIT ? zfull - 1 : zfull, a.nx, a.ny, a.nzf, SLIT);
+    const S *fin = static_cast<const S *>(a.fin);
+    double m0 = 0, mx = 0, my = 0, mz = 0;
+    static_for<Q>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        int arr;
+        uint32_t node;
+        pl.template src<p>(arr, node);
+        const double dv = double(CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]));
+        if constexpr (MODE == 1) {
+            out0[(size_t)p * Nfull + fi] = dv + wgt<double>(p) * a.rho_bar[s];
+        } else {
+            m0 += dv;
+            mx += cx(p) * dv;
+            my += cy(p) * dv;
+            mz += cz(p) * dv;
+        }
+    });
+    if constexpr (MODE == 0) {
+        out0[fi] = a.rho_bar[s] + m0;
+        if (out1) {
+            out1[fi] = mx;
+            out1[Nfull + fi] = my;
+            out1[2 * Nfull + fi] = mz;
+        }
+    }
+}
+
+template <class T, bool SLIT>
+__global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double *q) {
+    using CD = Codec<T>;
+    using S = typename CD::S;
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const S *fin = static_cast<const S *>(a.fin);
+    double qq = a.q_rest;
+    for (int s = 0; s < ns; ++s) {
+        double m0 = 0.0;
+        static_for<Q>([&](auto pc) {
+            constexpr int p = decltype(pc)::value;
+            int arr;
+            uint32_t node;
+            pl.template src<p>(arr, node);
+            m0 += double(CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]));
+        });
+        qq += a.valence[s] * m0;
+    }
+    q[pl.own()] = qq;
+}
+
+// ---------------------------------------------------------------------------------------
+// Poisson: 7-point finite-volume operator on fluid nodes (eq. Poisson, Sec. II), periodic in
+// x, y (and z for the box); no neighbour across a wall, whose charge sits in the first
+// fluid layer.  b = -K (q + lump) - mean(b).
+
+struct Stencil {
+    double sum;
+    int deg;
+};
+
+__device__ inline Stencil neighbours(const PoissonArgs &a, const double *psi, uint32_t x, uint32_t y,
+                                     uint32_t z) {
+    const uint32_t xm = x == 0 ? a.nx - 1 : x - 1, xp = x + 1 == a.nx ? 0 : x + 1;
+    const uint32_t ym = y == 0 ? a.ny - 1 : y - 1, yp = y + 1 == a.ny ? 0 : y + 1;
+    const uint32_t row = (z * a.ny + y) * a.nx;
+    double s = psi[row + xp];
+    s += psi[row + xm];
+    s += psi[(z * a.ny + yp) * a.nx + x];
+    s += psi[(z * a.ny + ym) * a.nx + x];
+    int deg = 4;
+    if (a.slit) {
+        if (z + 1 < a.nzf) { s += psi[((z + 1) * a.ny + y) * a.nx + x]; ++deg; }
+        if (z > 0) { s += psi[((z - 1) * a.ny + y) * a.nx + x]; ++deg; }
+    } else {
+        const uint32_t zp = z + 1 == a.nzf ? 0 : z + 1, zm = z == 0 ? a.nzf - 1 : z - 1;
+        s += psi[(zp * a.ny + y) * a.nx + x];
+        s += psi[(zm * a.ny + y) * a.nx + x];
+        deg = 6;
+    }
+    return {s, deg};
+}
+
+__device__ inline double rhs(const PoissonArgs &a, uint32_t i, uint32_t z) {
+    double lump = 0.0;
+    if (a.slit) {
+        if (z == 0) lump += a.lump_lo;
+        if (z + 1 == a.nzf) lump += a.lump_hi;
+    }
+    return -a.K * (a.q[i] + lump) - *a.bmean;
+}
+
+__global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colour) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t zfull = a.slit ? z + 1 : z;
+    if (((x + y + zfull) & 1u) != (uint32_t)colour) return;
+    const uint32_t i = (z * a.ny + y) * a.nx + x;
+    const Stencil st = neighbours(a, a.psi, x, y, z);
+    const double b = rhs(a, i, z);
+    const double gs = (st.sum - b) / (double)st.deg;
+    a.psi[i] = a.psi[i] + a.omega * (gs - a.psi[i]);
+}
+
+__global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *partials) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (x < a.nx) {
+        const uint32_t y = blockIdx.y, z = blockIdx.z;
+        const uint32_t i = (z * a.ny + y) * a.nx + x;
+        const Stencil st = neighbours(a, a.psi, x, y, z);
+        const double b = rhs(a, i, z);
+        const double r = b - (st.sum - st.deg * a.psi[i]);
+        v[0] = r * r;
+        v[1] = b * b;
+        v[2] = a.psi[i];
+    }
+    const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<3>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
+}
+
+__global__ __launch_bounds__(BLOCK) void qsum(const double *q, uint32_t N, double *partials) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {i < N ? q[i] : 0.0};
+    block_sum_store<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+__global__ __launch_bounds__(BLOCK) void finalize(const double *partials, uint32_t nb, int nv, double *out,
+                                                 int mode, double K, double lumps, double N) {
+    __shared__ double red[BLOCK];
+    for (int v = 0; v < nv; ++v) {
+        double s = 0.0;
+        for (uint32_t b = threadIdx.x; b < nb; b += BLOCK) s += partials[(size_t)v * nb + b];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[v] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (mode == 1) out[nv] = -K * (out[0] + lumps) / N;
+        if (mode == 2) out[nv] = out[2] / N;
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void shift(double *psi, uint32_t N, const double *mean) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) psi[i] -= *mean;
+}
+
+__global__ __launch_bounds__(BLOCK) void plane_sums(const double *n, const double *j, uint32_t nx, uint32_t ny,
+                                                   uint32_t nz, double *out) {
+    __shared__ double red[4][BLOCK];
+    const uint32_t z = blockIdx.x;
+    const size_t plane = (size_t)nx * ny, Nfull = plane * nz;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t k = threadIdx.x; k < plane; k += BLOCK) {
+        const size_t i = z * plane + k;
+        s[0] += n[i];
+        s[1] += j[i];
+        s[2] += j[Nfull + i];
+        s[3] += j[2 * Nfull + i];
+    }
+    for (int v = 0; v < 4; ++v) red[v][threadIdx.x] = s[v];
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) out[(size_t)threadIdx.x * nz + z] = red[threadIdx.x][0];
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers.
+
+dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block) {
+    uint32_t bx = ((nx + 63) / 64) * 64;
+    if (bx > BLOCK) bx = BLOCK;
+    *block = dim3(bx, 1, 1);
+    return dim3((nx + bx - 1) / bx, ny, nz);
+}
+
+template <int NS, class T, bool SLIT>
+static hipError_t sc_fields(bool field, bool charged, const StepArgs &a, dim3 g, dim3 b, hipStream_t st) {
+    if (charged)
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, true>), g, b, 0, st, a);
+    else if (field)
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, false>), g, b, 0, st, a);
+    else
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, false, false>), g, b, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int NS, class T>
+static hipError_t sc_geom(bool slit, bool field, bool charged, const StepArgs &a, dim3 g, dim3 b, hipStream_t st) {
+    return slit ? sc_fields<NS, T, true>(field, charged, a, g, b, st)
+                : sc_fields<NS, T, false>(field, charged, a, g, b, st);
+}
+
+template <class T>
+static hipError_t sc_ns(int ns, bool slit, bool field, bool charged, const StepArgs &a, dim3 g, dim3 b,
+                        hipStream_t st) {
+    switch (ns) {
+        case 1: return sc_geom<1, T>(slit, field, charged, a, g, b, st);
+        case 2: return sc_geom<2, T>(slit, field, charged, a, g, b, st);
+        case 3: return sc_geom<3, T>(slit, field, charged, a, g, b, st);
+        case 4: return sc_geom<4, T>(slit, field, charged, a, g, b, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged, const StepArgs &a,
+                                 hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    switch (st) {
+        case Store::F64: return sc_ns<double>(ns, slit, field, charged, a, g, b, stream);
+        case Store::F32: return sc_ns<float>(ns, slit, field, charged, a, g, b, stream);
+        case Store::BF16: return sc_ns<BF16>(ns, slit, field, charged, a, g, b, stream);
+        case Store::F16: return sc_ns<F16>(ns, slit, field, charged, a, g, b, stream);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Dispatch of the per-storage, per-geometry helper kernels.
+template <template <class, bool> class K, class... A>
+static hipError_t by_store(Store st, bool slit, A &&...args) {
+    switch (st) {
+        case Store::F64: return slit ? K<double, true>::go(args...) : K<double, false>::go(args...);
+        case Store::F32: return slit ? K<float, true>::go(args...) : K<float, false>::go(args...);
+        case Store::BF16: return slit ? K<BF16, true>::go(args...) : K<BF16, false>::go(args...);
+        case Store::F16: return slit ? K<F16, true>::go(args...) : K<F16, false>::go(args...);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class T, bool SLIT> struct InitK {
+    static hipError_t go(int s, const StepArgs &a, const double *n, const double *u, hipStream_t st) {
+        dim3 b;
+        const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+        hipLaunchKernelGGL((init_equilibrium<T, SLIT>), g, b, 0, st, a, s, n, u);
+        return hipGetLastError();
+    }
+};
+template <class T, bool SLIT> struct MomK {
+    static hipError_t go(int s, const StepArgs &a, double *n, double *j, hipStream_t st) {
+        dim3 b;
+        const dim3 g = node_grid(a.nx, a.ny, SLIT ? a.nzf + 2 : a.nzf, &b);
+        hipLaunchKernelGGL((gather<T, SLIT, 0>), g, b, 0, st, a, s, n, j);
+        return hipGetLastError();
+    }
+};
+template <class T, bool SLIT> struct PopK {
+    static hipError_t go(int s, const StepArgs &a, double *f, hipStream_t st) {
+        dim3 b;
+        const dim3 g = node_grid(a.nx, a.ny, SLIT ? a.nzf + 2 : a.nzf, &b);
+        hipLaunchKernelGGL((gather<T, SLIT, 1>), g, b, 0, st, a, s, f, (double *)nullptr);
+        return hipGetLastError();
+    }
+};
+template <class T, bool SLIT> struct ChargeK {
+    static hipError_t go(int ns, const StepArgs &a, double *q, hipStream_t st) {
+        dim3 b;
+        const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+        hipLaunchKernelGGL((charge<T, SLIT>), g, b, 0, st, a, ns, q);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n, const double *u,
+                       hipStream_t stream) {
+    return by_store<InitK>(st, slit, s, a, n, u, stream);
+}
+hipError_t launch_moments(Store st, bool slit, int s, const StepArgs &a, double *n, double *j,
+                          hipStream_t stream) {
+    return by_store<MomK>(st, slit, s, a, n, j, stream);
+}
+hipError_t launch_populations(Store st, bool slit, int s, const StepArgs &a, double *f, hipStream_t stream) {
+    return by_store<PopK>(st, slit, s, a, f, stream);
+}
+hipError_t launch_charge(Store st, bool slit, int ns, const StepArgs &a, double *q, hipStream_t stream) {
+    return by_store<ChargeK>(st, slit, ns, a, q, stream);
+}
+
+hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    hipLaunchKernelGGL(sor_half, g, b, 0, stream, a, colour);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    *nb = g.x * g.y * g.z;
+    hipLaunchKernelGGL(residual, g, b, 0, stream, a, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *nb, hipStream_t stream) {
+    *nb = (N + BLOCK - 1) / BLOCK;
+    hipLaunchKernelGGL(qsum, dim3(*nb), dim3(BLOCK), 0, stream, q, N, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out, int mode, double K,
+                           double lumps, double N, hipStream_t stream) {
+    hipLaunchKernelGGL(finalize, dim3(1), dim3(BLOCK), 0, stream, partials, nblocks, nv, out, mode, K, lumps, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift(double *psi, uint32_t N, const double *mean, hipStream_t stream) {
+    hipLaunchKernelGGL(shift, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, psi, N, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_sums(const double *n, const double *j, uint32_t nx, uint32_t ny, uint32_t nz,
+                             double *out, hipStream_t stream) {
+    hipLaunchKernelGGL(plane_sums, dim3(nz), dim3(BLOCK), 0, stream, n, j, nx, ny, nz, out);
+    return hipGetLastError();
+}
+
+}  // namespace lbmix

@@ -1,0 +1,799 @@
+// Host runtime of the multicomponent lattice-Boltzmann library: the context behind the C ABI
+// of include/lbmix.h.  It owns the device memory (double-buffered populations over the
+// fluid nodes, potential, charge density, reduction scratch), maps the physical parameters
+// to relaxation frequencies (Sec. IV: nu = v_T^2 (1/omega_visc - 1/2),
+// D = v_T^2 (1/omega_drag - 1/2)) and sequences a time step: one fused stream-collide
+// launch, then for charged runs the Poisson solve of the new charge density, used by the
+// next collision.
+#include "lbmix.h"
+#include "lbmix_kernels.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace lbmix;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kW[Q] = {1.0 / 3, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                          1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+constexpr char kMagic[8] = {'L', 'B', 'M', 'X', 'C', 'K', '0', '1'};
+
+}  // namespace
+
+struct lbmix_ctx {
+    // lattice
+    int nx = 0, ny = 0, nz = 0, nzf = 0, geometry = 0, storage = 0;
+    Store st = Store::F64;
+    size_t esize = 8;
+    uint32_t Nf = 0;
+    size_t Nfull = 0;
+    bool slit = false;
+    // species and parameters
+    int ns = 0;
+    double rho0[MAXS] = {};
+    int valence[MAXS] = {};
+    double host_total[MAXS] = {};     // FP64 sum of the initial densities (neutrality check)
+    double rel_range[MAXS] = {};      // FP16 scale: bound of |f - w rho0| / (w rho0)
+    double tau_v = 1.0, tau_d = 1.0, sc = 1.0;
+    bool drag_from_sc = true;
+    double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
+    double sor_tol = 1e-8, sor_omega = -1.0;
+    int sor_max = 200000, sor_check = 10;
+    // device
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    void *f[2] = {nullptr, nullptr};
+    int cur = 0;
+    double *psi = nullptr, *q = nullptr;
+    double *partials = nullptr;       // per-block partial sums
+    size_t partials_cap = 0;
+    double *step_partials = nullptr;  // mass partials of the last stream-collide
+    uint32_t step_nb = 0;
+    double *dred = nullptr;           // device results of reductions (16 doubles)
+    double *hred = nullptr;           // pinned host mirror
+    double *scratch = nullptr;        // readback staging
+    size_t scratch_cap = 0;
+    float scale[MAXS][Q], inv_scale[MAXS][Q];
+    // state
+    bool allocated = false, started = false, psi_valid = false;
+    bool set[MAXS] = {};
+    long long steps = 0, solves = 0, total_sweeps = 0;
+    int last_sweeps = 0, last_status = 0;
+    double last_resid = 0.0;
+    bool resid_on_device = false;     // fixed-sweep solves leave the residual in dred
+    int latched = 0;
+    std::string err;
+
+    int fail(int code, const char *fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip(hipError_t e, const char *what) {
+        if (e == hipSuccess) return LBMIX_OK;
+        return fail(e == hipErrorOutOfMemory ? LBMIX_ENOMEM : LBMIX_EDEVICE, "%s: %s", what,
+                    hipGetErrorString(e));
+    }
+    bool charged() const {
+        if (!(lB > 0.0)) return false;
+        for (int s = 0; s < ns; ++s)
+            if (valence[s] != 0) return true;
+        return false;
+    }
+    bool field() const { return charged() || E[0] != 0.0 || E[1] != 0.0 || E[2] != 0.0; }
+    double omega_drag() const { return drag_from_sc ? 1.0 / (0.5 + (tau_v - 0.5) / sc) : 1.0 / tau_d; }
+    double sor_w() const {
+        if (sor_omega > 0.0) return sor_omega;
+        const int L = std::max(nx, std::max(ny, nzf));
+        return 2.0 / (1.0 + std::sin(kPi / L));
+    }
+    double rho_bar(int s) const {
+        return (storage == LBMIX_F64 || storage == LBMIX_F32) ? 0.0 : rho0[s];
+    }
+    uint32_t node_blocks() const {
+        dim3 b;
+        const dim3 g = node_grid(nx, ny, nzf, &b);
+        return g.x * g.y * g.z;
+    }
+    StepArgs args() const {
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.fin = f[cur];
+        a.fout = f[cur ^ 1];
+        a.nx = nx;
+        a.ny = ny;
+        a.nzf = nzf;
+        a.N = Nf;
+        a.q_rest = 0.0;
+        for (int s = 0; s < MAXS; ++s) {
+            a.rho_bar[s] = s < ns ? rho_bar(s) : 0.0;
+            a.valence[s] = s < ns ? valence[s] : 0;
+            for (int p = 0; p < Q; ++p) {
+                a.scale[s][p] = scale[s][p];
+                a.inv_scale[s][p] = inv_scale[s][p];
+            }
+            if (s < ns) a.q_rest += valence[s] * a.rho_bar[s];
+        }
+        a.omega_v = 1.0 / tau_v;
+        a.omega_d = omega_drag();
+        for (int d = 0; d < 3; ++d) a.E[d] = E[d];
+        a.psi = psi;
+        a.q = q;
+        a.ghost_lo = 4.0 * kPi * lB * sig_lo;
+        a.ghost_hi = 4.0 * kPi * lB * sig_hi;
+        a.partials = step_partials;
+        return a;
+    }
+    PoissonArgs pargs() const {
+        PoissonArgs p;
+        p.psi = psi;
+        p.q = q;
+        p.nx = nx;
+        p.ny = ny;
+        p.nzf = nzf;
+        p.N = Nf;
+        p.slit = slit ? 1 : 0;
+        p.K = 4.0 * kPi * lB;
+        p.lump_lo = slit ? sig_lo : 0.0;
+        p.lump_hi = slit ? sig_hi : 0.0;
+        p.bmean = dred + 1;
+        p.omega = sor_w();
+        return p;
+    }
+    void compute_scales() {
+        for (int s = 0; s < MAXS; ++s)
+            for (int p = 0; p < Q; ++p) {
+                float sc_ = 1.0f;
+                if (storage == LBMIX_F16_SHIFTED && s < ns) {
+                    // largest |f - w rho0| expected: w rho0 rel_range; map it near 2^12 so
+                    // FP16 keeps 11 significant bits over eight more binary decades
+                    const double dmax = kW[p] * rho0[s] * rel_range[s];
+                    const int e = (int)std::floor(std::log2(4096.0 / dmax));
+                    sc_ = std::ldexp(1.0f, std::max(-60, std::min(60, e)));
+                }
+                scale[s][p] = sc_;
+                inv_scale[s][p] = 1.0f / sc_;
+            }
+    }
+};
+
+namespace {
+
+int ensure_scratch(lbmix_ctx *c, size_t bytes) {
+    if (c->scratch_cap >= bytes) return LBMIX_OK;
+    if (c->scratch) (void)hipFree(c->scratch);
+    c->scratch = nullptr;
+    c->scratch_cap = 0;
+    int rc = c->hip(hipMalloc((void **)&c->scratch, bytes), "hipMalloc(readback scratch)");
+    if (rc) return rc;
+    c->scratch_cap = bytes;
+    return LBMIX_OK;
+}
+
+int allocate(lbmix_ctx *c) {
+    if (c->allocated) return LBMIX_OK;
+    int rc = c->hip(hipGetDevice(&c->device), "hipGetDevice");
+    if (rc) return rc;
+    if (!c->stream) {
+        rc = c->hip(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
+        if (rc) return rc;
+        c->own_stream = true;
+    }
+    const size_t pop = (size_t)c->ns * Q * c->Nf * c->esize;
+    for (int k = 0; k < 2; ++k) {
+        rc = c->hip(hipMalloc(&c->f[k], pop), "hipMalloc(populations)");
+        if (rc) return rc;
+        rc = c->hip(hipMemsetAsync(c->f[k], 0, pop, c->stream), "hipMemset(populations)");
+        if (rc) return rc;
+    }
+    const uint32_t nb = c->node_blocks();
+    const uint32_t qb = (c->Nf + BLOCK - 1) / BLOCK;
+    c->step_nb = nb;
+    c->partials_cap = (size_t)4 * std::max(nb, qb);
+    rc = c->hip(hipMalloc((void **)&c->partials, c->partials_cap * sizeof(double)), "hipMalloc(partials)");
+    if (rc) return rc;
+    rc = c->hip(hipMalloc((void **)&c->step_partials, (size_t)MAXS * nb * sizeof(double)), "hipMalloc(partials)");
+    if (rc) return rc;
+    rc = c->hip(hipMemsetAsync(c->step_partials, 0, (size_t)MAXS * nb * sizeof(double), c->stream), "hipMemset");
+    if (rc) return rc;
+    rc = c->hip(hipMalloc((void **)&c->dred, 16 * sizeof(double)), "hipMalloc(reduction)");
+    if (rc) return rc;
+    rc = c->hip(hipMemsetAsync(c->dred, 0, 16 * sizeof(double), c->stream), "hipMemset");
+    if (rc) return rc;
+    rc = c->hip(hipHostMalloc((void **)&c->hred, 16 * sizeof(double), hipHostMallocDefault), "hipHostMalloc");
+    if (rc) return rc;
+    c->allocated = true;
+    return LBMIX_OK;
+}
+
+int ensure_field_buffers(lbmix_ctx *c) {
+    if (c->psi) return LBMIX_OK;
+    int rc = c->hip(hipMalloc((void **)&c->psi, (size_t)c->Nf * sizeof(double)), "hipMalloc(psi)");
+    if (rc) return rc;
+    rc = c->hip(hipMalloc((void **)&c->q, (size_t)c->Nf * sizeof(double)), "hipMalloc(q)");
+    if (rc) return rc;
+    rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
+    if (rc) return rc;
+    return c->hip(hipMemsetAsync(c->q, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(q)");
+}
+
+int fetch(lbmix_ctx *c, int count) {
+    int rc = c->hip(hipMemcpyAsync(c->hred, c->dred, count * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                    "hipMemcpy(reduction)");
+    if (rc) return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+// dred[0] = sum q, dred[1] = mean b; dred[4..7] = (r2, b2, sum psi, mean psi).
+int residual(lbmix_ctx *c, const PoissonArgs &pa) {
+    uint32_t nb = 0;
+    int rc = c->hip(launch_residual(pa, c->partials, &nb, c->stream), "residual");
+    if (rc) return rc;
+    return c->hip(launch_finalize(c->partials, nb, 3, c->dred + 4, 2, 0.0, 0.0, (double)c->Nf, c->stream),
+                  "finalize(residual)");
+}
+
+// Poisson solve of the charge in c->q into c->psi (warm start), then zero-mean gauge.
+int solve(lbmix_ctx *c) {
+    uint32_t nb = 0;
+    const double lumps = c->slit ? (c->sig_lo + c->sig_hi) * (double)c->nx * c->ny : 0.0;
+    int rc = c->hip(launch_qsum(c->q, c->Nf, c->partials, &nb, c->stream), "qsum");
+    if (rc) return rc;
+    rc = c->hip(launch_finalize(c->partials, nb, 1, c->dred, 1, 4.0 * kPi * c->lB, lumps, (double)c->Nf, c->stream),
+                "finalize(qsum)");
+    if (rc) return rc;
+    const PoissonArgs pa = c->pargs();
+    int sweeps = 0, status = LBMIX_OK;
+    auto sweep = [&](int count) -> int {
+        for (int k = 0; k < count; ++k) {
+            int r = c->hip(launch_sor(pa, 0, c->stream), "sor(red)");
+            if (r) return r;
+            r = c->hip(launch_sor(pa, 1, c->stream), "sor(black)");
+            if (r) return r;
+        }
+        return LBMIX_OK;
+    };
+    if (c->sor_tol > 0.0) {
+        for (;;) {
+            if ((rc = residual(c, pa))) return rc;
+            if ((rc = fetch(c, 8))) return rc;
+            const double r2 = c->hred[4], b2 = c->hred[5];
+            if (b2 == 0.0) {
+                rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
+                if (rc) return rc;
+                c->last_resid = 0.0;
+                c->last_sweeps = 0;
+                c->last_status = LBMIX_OK;
+                c->resid_on_device = false;
+                c->solves++;
+                c->psi_valid = true;
+                return LBMIX_OK;
+            }
+            c->last_resid = std::sqrt(r2 / b2);
+            if (c->last_resid <= c->sor_tol) break;
+            if (sweeps >= c->sor_max) {
+                status = LBMIX_ENOCONV;
+                break;
+            }
+            const int todo = std::min(c->sor_check, c->sor_max - sweeps);
+            if ((rc = sweep(todo))) return rc;
+            sweeps += todo;
+        }
+        c->resid_on_device = false;
+    } else {
+        if ((rc = sweep(c->sor_max))) return rc;
+        sweeps = c->sor_max;
+        if ((rc = residual(c, pa))) return rc;
+        c->resid_on_device = true;
+    }
+    // zero-mean gauge with the mean of the final psi (dred[7])
+    rc = c->hip(launch_shift(c->psi, c->Nf, c->dred + 7, c->stream), "shift(psi)");
+    if (rc) return rc;
+    c->last_sweeps = sweeps;
+    c->last_status = status;
+    c->total_sweeps += sweeps;
+    c->solves++;
+    c->psi_valid = true;
+    return status;
+}
+
+int initial_potential(lbmix_ctx *c) {
+    int rc = ensure_field_buffers(c);
+    if (rc) return rc;
+    const StepArgs a = c->args();
+    rc = c->hip(launch_charge(c->st, c->slit, c->ns, a, c->q, c->stream), "charge");
+    if (rc) return rc;
+    rc = solve(c);
+    return rc == LBMIX_ENOCONV ? LBMIX_OK : rc;
+}
+
+int check_ready(lbmix_ctx *c) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->ns == 0) return c->fail(LBMIX_ESTATE, "no species");
+    for (int s = 0; s < c->ns; ++s)
+        if (!c->set[s]) return c->fail(LBMIX_ESTATE, "species %d has no state (lbmix_set_state)", s);
+    return LBMIX_OK;
+}
+
+int validate_start(lbmix_ctx *c) {
+    if (!c->charged()) return LBMIX_OK;
+    auto bad_extent = [](int n) { return n > 1 && (n % 2) != 0; };
+    if (bad_extent(c->nx) || bad_extent(c->ny) || (!c->slit && bad_extent(c->nz)))
+        return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR");
+    double qtot = 0.0, scale = 0.0;
+    for (int s = 0; s < c->ns; ++s) {
+        qtot += c->valence[s] * c->host_total[s];
+        scale += std::fabs((double)c->valence[s]) * c->host_total[s];
+    }
+    const double wall = c->slit ? (c->sig_lo + c->sig_hi) * (double)c->nx * c->ny : 0.0;
+    scale = std::max(scale, std::fabs(c->sig_lo * c->nx * c->ny) + std::fabs(c->sig_hi * c->nx * c->ny));
+    if (std::fabs(qtot + wall) > 1e-9 * scale)
+        return c->fail(LBMIX_EINVAL, "system is not neutral: fluid charge %.17g, wall charge %.17g", qtot, wall);
+    return LBMIX_OK;
+}
+
+struct Guard {   // make the context's device current for the duration of a call
+    int prev = -1;
+    explicit Guard(const lbmix_ctx *c) {
+        if (c && c->allocated && hipGetDevice(&prev) == hipSuccess && prev != c->device)
+            (void)hipSetDevice(c->device);
+        else
+            prev = -1;
+    }
+    ~Guard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+struct Header {
+    char magic[8];
+    int32_t version, nx, ny, nz, geometry, storage, ns, valence[MAXS];
+    double rho0[MAXS], rel_range[MAXS], host_total[MAXS];
+    double tau_v, tau_d, sc;
+    int32_t drag_from_sc, sor_max, sor_check, psi_valid;
+    double lB, sig_lo, sig_hi, E[3], sor_tol, sor_omega;
+    int64_t steps;
+};
+
+}  // namespace
+
+// =======================================================================================
+// C ABI
+
+extern "C" {
+
+int lbmix_version(void) { return 10000; }
+
+int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage, void *hip_stream) {
+    if (!out) return LBMIX_EINVAL;
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return LBMIX_EINVAL;
+    if (geometry != LBMIX_PERIODIC && geometry != LBMIX_SLIT_Z) return LBMIX_EINVAL;
+    if (geometry == LBMIX_SLIT_Z && nz < 3) return LBMIX_EINVAL;
+    if (storage < LBMIX_F64 || storage > LBMIX_F16_SHIFTED) return LBMIX_EINVAL;
+    const int nzf = geometry == LBMIX_SLIT_Z ? nz - 2 : nz;
+    const double nodes = (double)nx * ny * nz;
+    if (nodes > 2147483647.0) return LBMIX_EINVAL;
+    lbmix_ctx *c = new (std::nothrow) lbmix_ctx();
+    if (!c) return LBMIX_ENOMEM;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->nzf = nzf;
+    c->geometry = geometry;
+    c->slit = geometry == LBMIX_SLIT_Z;
+    c->storage = storage;
+    switch (storage) {
+        case LBMIX_F64: c->st = Store::F64; c->esize = 8; break;
+        case LBMIX_F32:
+        case LBMIX_F32_SHIFTED: c->st = Store::F32; c->esize = 4; break;
+        case LBMIX_BF16_SHIFTED: c->st = Store::BF16; c->esize = 2; break;
+        default: c->st = Store::F16; c->esize = 2; break;
+    }
+    c->Nf = (uint32_t)((size_t)nx * ny * nzf);
+    c->Nfull = (size_t)nx * ny * nz;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    for (int s = 0; s < MAXS; ++s) c->rel_range[s] = 0.1;
+    c->compute_scales();
+    *out = c;
+    return LBMIX_OK;
+}
+
+int lbmix_add_species(lbmix_ctx *c, double rho0, int valence, int *id_out) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->allocated) return c->fail(LBMIX_ESTATE, "species must be added before the first set_state");
+    if (c->ns >= MAXS) return c->fail(LBMIX_EINVAL, "at most %d species", MAXS);
+    if (!(rho0 > 0.0) || !std::isfinite(rho0)) return c->fail(LBMIX_EINVAL, "rho0 must be positive");
+    c->rho0[c->ns] = rho0;
+    c->valence[c->ns] = valence;
+    if (id_out) *id_out = c->ns;
+    c->ns++;
+    c->compute_scales();
+    return LBMIX_OK;
+}
+
+int lbmix_set_tau_visc(lbmix_ctx *c, double tau) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (!(tau > 0.5) || !std::isfinite(tau)) return c->fail(LBMIX_EINVAL, "tau_visc must exceed 1/2");
+    c->tau_v = tau;
+    return LBMIX_OK;
+}
+
+int lbmix_set_tau_drag(lbmix_ctx *c, double tau) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (!(tau > 0.5) || !std::isfinite(tau)) return c->fail(LBMIX_EINVAL, "tau_drag must exceed 1/2");
+    c->tau_d = tau;
+    c->drag_from_sc = false;
+    return LBMIX_OK;
+}
+
+int lbmix_set_schmidt(lbmix_ctx *c, double sc) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (!(sc > 0.0) || !std::isfinite(sc)) return c->fail(LBMIX_EINVAL, "Schmidt number must be positive");
+    c->sc = sc;
+    c->drag_from_sc = true;
+    return LBMIX_OK;
+}
+
+int lbmix_set_electrostatics(lbmix_ctx *c, double bjerrum, double sigma_lo, double sigma_hi, const double *E) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (!(bjerrum >= 0.0) || !std::isfinite(bjerrum) || !std::isfinite(sigma_lo) || !std::isfinite(sigma_hi))
+        return c->fail(LBMIX_EINVAL, "bad electrostatic parameters");
+    if (E)
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(E[d])) return c->fail(LBMIX_EINVAL, "bad field");
+    c->lB = bjerrum;
+    c->sig_lo = sigma_lo;
+    c->sig_hi = sigma_hi;
+    for (int d = 0; d < 3; ++d) c->E[d] = E ? E[d] : 0.0;
+    c->psi_valid = false;
+    return LBMIX_OK;
+}
+
+int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_every, double omega_sor) {
+    if (!c) return LBMIX_EINVAL;
+    if (!(rel_tol >= 0.0) || max_sweeps < 1 || check_every < 1 || !(omega_sor < 2.0))
+        return c->fail(LBMIX_EINVAL, "bad Poisson parameters");
+    c->sor_tol = rel_tol;
+    c->sor_max = max_sweeps;
+    c->sor_check = check_every;
+    c->sor_omega = omega_sor;
+    return LBMIX_OK;
+}
+
+int lbmix_set_state(lbmix_ctx *c, int s, const double *n, const double *u) {
+    if (!c) return LBMIX_EINVAL;
+    if (s < 0 || s >= c->ns || !n) return c->fail(LBMIX_EINVAL, "bad species index or null density");
+    int rc = allocate(c);
+    if (rc) return rc;
+    Guard g(c);
+    double tot = 0.0;
+    for (size_t i = 0; i < c->Nfull; ++i) {
+        const int z = (int)(i / ((size_t)c->nx * c->ny));
+        if (c->slit && (z == 0 || z == c->nz - 1)) continue;
+        tot += n[i];
+    }
+    double *dn = nullptr, *du = nullptr;
+    rc = c->hip(hipMalloc((void **)&dn, c->Nfull * sizeof(double)), "hipMalloc(staging)");
+    if (rc) return rc;
+    if (u) {
+        rc = c->hip(hipMalloc((void **)&du, 3 * c->Nfull * sizeof(double)), "hipMalloc(staging)");
+        if (rc) { (void)hipFree(dn); return rc; }
+    }
+    rc = c->hip(hipMemcpyAsync(dn, n, c->Nfull * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy n");
+    if (!rc && u)
+        rc = c->hip(hipMemcpyAsync(du, u, 3 * c->Nfull * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy u");
+    if (!rc) {
+        StepArgs a = c->args();
+        a.fout = c->f[c->cur];
+        rc = c->hip(launch_init(c->st, c->slit, s, a, dn, du, c->stream), "init_equilibrium");
+    }
+    if (!rc) rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    (void)hipFree(dn);
+    if (du) (void)hipFree(du);
+    if (rc) return rc;
+    c->host_total[s] = tot;
+    c->set[s] = true;
+    c->started = false;
+    c->psi_valid = false;
+    c->steps = 0;
+    c->latched = 0;
+    return LBMIX_OK;
+}
+
+int lbmix_step(lbmix_ctx *c, int nsteps) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (nsteps < 0) return c->fail(LBMIX_EINVAL, "negative step count");
+    if (c->latched) return c->fail(c->latched, "context latched an earlier error (%d)", c->latched);
+    Guard g(c);
+    if (!c->started) {
+        if ((rc = validate_start(c))) return rc;
+        c->started = true;
+    }
+    const bool charged = c->charged();
+    if (charged && !c->psi_valid) {
+        if ((rc = initial_potential(c))) return rc;
+    }
+    int status = LBMIX_OK;
+    const bool field = c->field();
+    for (int k = 0; k < nsteps; ++k) {
+        const StepArgs a = c->args();
+        rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
+        if (rc) return rc;
+        c->cur ^= 1;
+        c->steps++;
+        if (charged) {
+            rc = solve(c);
+            if (rc == LBMIX_ENOCONV)
+                status = LBMIX_ENOCONV;
+            else if (rc)
+                return rc;
+        }
+    }
+    if (status == LBMIX_ENOCONV)
+        return c->fail(LBMIX_ENOCONV, "Poisson solve reached %d sweeps at residual %.3e", c->sor_max, c->last_resid);
+    return LBMIX_OK;
+}
+
+int lbmix_get_moments_device(lbmix_ctx *c, int s, double *n_dev, double *j_dev) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (s < 0 || s >= c->ns) return c->fail(LBMIX_EINVAL, "bad species index");
+    Guard g(c);
+    const StepArgs a = c->args();
+    if (!n_dev) {
+        if (!j_dev) return LBMIX_OK;
+        if ((rc = ensure_scratch(c, c->Nfull * sizeof(double)))) return rc;
+        n_dev = c->scratch;
+    }
+    return c->hip(launch_moments(c->st, c->slit, s, a, n_dev, j_dev, c->stream), "moments");
+}
+
+int lbmix_get_moments(lbmix_ctx *c, int s, double *n_out, double *j_out) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (s < 0 || s >= c->ns) return c->fail(LBMIX_EINVAL, "bad species index");
+    Guard g(c);
+    if ((rc = ensure_scratch(c, 4 * c->Nfull * sizeof(double)))) return rc;
+    double *dn = c->scratch, *dj = c->scratch + c->Nfull;
+    const StepArgs a = c->args();
+    if ((rc = c->hip(launch_moments(c->st, c->slit, s, a, dn, dj, c->stream), "moments"))) return rc;
+    if (n_out && (rc = c->hip(hipMemcpyAsync(n_out, dn, c->Nfull * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy n")))
+        return rc;
+    if (j_out && (rc = c->hip(hipMemcpyAsync(j_out, dj, 3 * c->Nfull * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy j")))
+        return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+int lbmix_get_populations(lbmix_ctx *c, int s, double *f_out) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (s < 0 || s >= c->ns || !f_out) return c->fail(LBMIX_EINVAL, "bad species index or null output");
+    Guard g(c);
+    if ((rc = ensure_scratch(c, (size_t)Q * c->Nfull * sizeof(double)))) return rc;
+    const StepArgs a = c->args();
+    if ((rc = c->hip(launch_populations(c->st, c->slit, s, a, c->scratch, c->stream), "populations"))) return rc;
+    if ((rc = c->hip(hipMemcpyAsync(f_out, c->scratch, (size_t)Q * c->Nfull * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy f")))
+        return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+int lbmix_get_potential(lbmix_ctx *c, double *psi_out) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!psi_out) return c->fail(LBMIX_EINVAL, "null output");
+    Guard g(c);
+    std::memset(psi_out, 0, c->Nfull * sizeof(double));
+    if (!c->charged()) return LBMIX_OK;
+    if (!c->psi_valid) {
+        if (!c->started) {
+            if ((rc = validate_start(c))) return rc;
+        }
+        if ((rc = initial_potential(c))) return rc;
+    }
+    const size_t off = c->slit ? (size_t)c->nx * c->ny : 0;
+    if ((rc = c->hip(hipMemcpyAsync(psi_out + off, c->psi, (size_t)c->Nf * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy psi")))
+        return rc;
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+int lbmix_get_mass_totals(lbmix_ctx *c, double *totals) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!totals) return c->fail(LBMIX_EINVAL, "null output");
+    Guard g(c);
+    if ((rc = ensure_scratch(c, c->Nfull * sizeof(double)))) return rc;
+    const StepArgs a = c->args();
+    for (int s = 0; s < c->ns; ++s) {
+        uint32_t nb = 0;
+        if ((rc = c->hip(launch_moments(c->st, c->slit, s, a, c->scratch, nullptr, c->stream), "moments"))) return rc;
+        if ((rc = c->hip(launch_qsum(c->scratch, (uint32_t)c->Nfull, c->partials, &nb, c->stream), "sum"))) return rc;
+        if ((rc = c->hip(launch_finalize(c->partials, nb, 1, c->dred + 8 + s, 0, 0, 0, 1, c->stream), "finalize")))
+            return rc;
+    }
+    if ((rc = c->hip(hipMemcpyAsync(c->hred, c->dred + 8, c->ns * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy")))
+        return rc;
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    bool finite = true;
+    for (int s = 0; s < c->ns; ++s) {
+        totals[s] = c->hred[s];
+        finite = finite && std::isfinite(totals[s]);
+    }
+    if (!finite) {
+        c->latched = LBMIX_ENONFINITE;
+        return c->fail(LBMIX_ENONFINITE, "non-finite mass total");
+    }
+    return LBMIX_OK;
+}
+
+int lbmix_get_zprofiles(lbmix_ctx *c, double *out) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!out) return c->fail(LBMIX_EINVAL, "null output");
+    Guard g(c);
+    if ((rc = ensure_scratch(c, (4 * c->Nfull + 4 * (size_t)c->nz * MAXS) * sizeof(double)))) return rc;
+    double *dn = c->scratch, *dj = c->scratch + c->Nfull, *dp = c->scratch + 4 * c->Nfull;
+    const StepArgs a = c->args();
+    for (int s = 0; s < c->ns; ++s) {
+        if ((rc = c->hip(launch_moments(c->st, c->slit, s, a, dn, dj, c->stream), "moments"))) return rc;
+        if ((rc = c->hip(launch_plane_sums(dn, dj, c->nx, c->ny, c->nz, dp + (size_t)s * 4 * c->nz, c->stream), "plane sums")))
+            return rc;
+    }
+    if ((rc = c->hip(hipMemcpyAsync(out, dp, (size_t)c->ns * 4 * c->nz * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy")))
+        return rc;
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    const double area = (double)c->nx * c->ny;
+    for (size_t i = 0; i < (size_t)c->ns * 4 * c->nz; ++i) out[i] /= area;
+    return LBMIX_OK;
+}
+
+int lbmix_get_stats(lbmix_ctx *c, lbmix_stats *out) {
+    if (!c || !out) return LBMIX_EINVAL;
+    Guard g(c);
+    if (c->allocated && c->resid_on_device) {
+        int rc = fetch(c, 8);
+        if (rc) return rc;
+        c->last_resid = c->hred[5] > 0.0 ? std::sqrt(c->hred[4] / c->hred[5]) : 0.0;
+        c->resid_on_device = false;
+    }
+    out->steps = c->steps;
+    out->poisson_solves = c->solves;
+    out->total_sweeps = c->total_sweeps;
+    out->last_sweeps = c->last_sweeps;
+    out->last_status = c->last_status;
+    out->last_residual = c->last_resid;
+    out->fluid_nodes = (double)c->Nf;
+    out->bytes_per_step = 2.0 * Q * c->ns * (double)c->esize * c->Nf;
+    return LBMIX_OK;
+}
+
+int lbmix_sync(lbmix_ctx *c) {
+    if (!c) return LBMIX_EINVAL;
+    if (!c->allocated) return LBMIX_OK;
+    Guard g(c);
+    return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+int lbmix_save(lbmix_ctx *c, const char *path) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!path) return c->fail(LBMIX_EINVAL, "null path");
+    Guard g(c);
+    Header h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kMagic, 8);
+    h.version = 1;
+    h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
+    for (int s = 0; s < MAXS; ++s) {
+        h.valence[s] = c->valence[s];
+        h.rho0[s] = c->rho0[s];
+        h.rel_range[s] = c->rel_range[s];
+        h.host_total[s] = c->host_total[s];
+    }
+    h.tau_v = c->tau_v; h.tau_d = c->tau_d; h.sc = c->sc; h.drag_from_sc = c->drag_from_sc;
+    h.sor_max = c->sor_max; h.sor_check = c->sor_check; h.psi_valid = c->psi_valid && c->psi;
+    h.lB = c->lB; h.sig_lo = c->sig_lo; h.sig_hi = c->sig_hi;
+    for (int d = 0; d < 3; ++d) h.E[d] = c->E[d];
+    h.sor_tol = c->sor_tol; h.sor_omega = c->sor_omega; h.steps = c->steps;
+    const size_t pop = (size_t)c->ns * Q * c->Nf * c->esize;
+    std::vector<char> buf(pop);
+    if ((rc = c->hip(hipMemcpyAsync(buf.data(), c->f[c->cur], pop, hipMemcpyDeviceToHost, c->stream), "copy f"))) return rc;
+    std::vector<double> ps(h.psi_valid ? c->Nf : 0);
+    if (h.psi_valid &&
+        (rc = c->hip(hipMemcpyAsync(ps.data(), c->psi, c->Nf * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy psi")))
+        return rc;
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    FILE *fp = std::fopen(path, "wb");
+    if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(buf.data(), 1, pop, fp) == pop;
+    if (ok && h.psi_valid) ok = std::fwrite(ps.data(), sizeof(double), ps.size(), fp) == ps.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    return ok ? LBMIX_OK : c->fail(LBMIX_EINVAL, "write to %s failed", path);
+}
+
+int lbmix_load(lbmix_ctx *c, const char *path) {
+    if (!c || !path) return LBMIX_EINVAL;
+    FILE *fp = std::fopen(path, "rb");
+    if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
+    Header h;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 1;
+    ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
+         h.storage == c->storage && h.ns == c->ns;
+    for (int s = 0; ok && s < c->ns; ++s) ok = h.valence[s] == c->valence[s] && h.rho0[s] == c->rho0[s];
+    if (!ok) {
+        std::fclose(fp);
+        return c->fail(LBMIX_EINVAL, "%s: not a checkpoint of this lattice", path);
+    }
+    const size_t pop = (size_t)c->ns * Q * c->Nf * c->esize;
+    std::vector<char> buf(pop);
+    std::vector<double> ps(h.psi_valid ? c->Nf : 0);
+    ok = std::fread(buf.data(), 1, pop, fp) == pop;
+    if (ok && h.psi_valid) ok = std::fread(ps.data(), sizeof(double), ps.size(), fp) == ps.size();
+    std::fclose(fp);
+    if (!ok) return c->fail(LBMIX_EINVAL, "%s: truncated checkpoint", path);
+    int rc = allocate(c);
+    if (rc) return rc;
+    Guard g(c);
+    for (int s = 0; s < MAXS; ++s) {
+        c->rel_range[s] = h.rel_range[s];
+        c->host_total[s] = h.host_total[s];
+    }
+    c->compute_scales();
+    c->tau_v = h.tau_v; c->tau_d = h.tau_d; c->sc = h.sc; c->drag_from_sc = h.drag_from_sc != 0;
+    c->sor_max = h.sor_max; c->sor_check = h.sor_check; c->sor_tol = h.sor_tol; c->sor_omega = h.sor_omega;
+    c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
+    for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
+    if ((rc = c->hip(hipMemcpyAsync(c->f[c->cur], buf.data(), pop, hipMemcpyHostToDevice, c->stream), "copy f"))) return rc;
+    if (h.psi_valid) {
+        if ((rc = ensure_field_buffers(c))) return rc;
+        if ((rc = c->hip(hipMemcpyAsync(c->psi, ps.data(), c->Nf * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy psi")))
+            return rc;
+    }
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    for (int s = 0; s < c->ns; ++s) c->set[s] = true;
+    c->psi_valid = h.psi_valid != 0;
+    c->steps = h.steps;
+    c->started = h.steps > 0;
+    c->latched = 0;
+    return LBMIX_OK;
+}
+
+const char *lbmix_last_error(const lbmix_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void lbmix_destroy(lbmix_ctx *c) {
+    if (!c) return;
+    if (c->allocated) {
+        Guard g(c);
+        (void)hipStreamSynchronize(c->stream);
+        for (int k = 0; k < 2; ++k)
+            if (c->f[k]) (void)hipFree(c->f[k]);
+        if (c->psi) (void)hipFree(c->psi);
+        if (c->q) (void)hipFree(c->q);
+        if (c->partials) (void)hipFree(c->partials);
+        if (c->step_partials) (void)hipFree(c->step_partials);
+        if (c->dred) (void)hipFree(c->dred);
+        if (c->hred) (void)hipHostFree(c->hred);
+        if (c->scratch) (void)hipFree(c->scratch);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,263 @@
+"""Thin ctypes binding of liblbmix.so (the C ABI of include/lbmix.h).
+
+Marshalling only: every step of the method runs in the library's gfx950 kernels.  There is
+no CPU fallback; constructing a :class:`Lattice` raises if the library or a GPU is missing.
+Host arrays are numpy float64 in [z][y][x] order (vector fields [3][z][y][x]); the device
+read-back takes torch CUDA tensors (float64, contiguous).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbmix.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+PERIODIC, SLIT_Z = 0, 1
+F64, F32, F32_SHIFTED, BF16_SHIFTED, F16_SHIFTED = 0, 1, 2, 3, 4
+STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "f16s": F16_SHIFTED}
+GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z}
+ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
+Q = 19
+MAX_SPECIES = 4
+EXPORTS = (
+    "lbmix_version", "lbmix_create", "lbmix_add_species", "lbmix_set_tau_visc",
+    "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics", "lbmix_set_poisson",
+    "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
+    "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
+    "lbmix_last_error", "lbmix_destroy",
+)
+
+
+class LbmixError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbmix error {code}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_longlong), ("poisson_solves", ctypes.c_longlong),
+                ("total_sweeps", ctypes.c_longlong), ("last_sweeps", ctypes.c_int),
+                ("last_status", ctypes.c_int), ("last_residual", ctypes.c_double),
+                ("fluid_nodes", ctypes.c_double), ("bytes_per_step", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblbmix.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1507_04891_amd/build.py "
+                           "(or __graft_entry__.build()); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "lbmix_version": ([], ctypes.c_int),
+        "lbmix_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, vp], ctypes.c_int),
+        "lbmix_add_species": ([vp, ctypes.c_double, ctypes.c_int, ip], ctypes.c_int),
+        "lbmix_set_tau_visc": ([vp, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_tau_drag": ([vp, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_schmidt": ([vp, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_electrostatics": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
+        "lbmix_set_poisson": ([vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
+        "lbmix_step": ([vp, ctypes.c_int], ctypes.c_int),
+        "lbmix_get_moments": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
+        "lbmix_get_moments_device": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
+        "lbmix_get_populations": ([vp, ctypes.c_int, dp], ctypes.c_int),
+        "lbmix_get_potential": ([vp, dp], ctypes.c_int),
+        "lbmix_get_mass_totals": ([vp, dp], ctypes.c_int),
+        "lbmix_get_zprofiles": ([vp, dp], ctypes.c_int),
+        "lbmix_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
+        "lbmix_sync": ([vp], ctypes.c_int),
+        "lbmix_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "lbmix_load": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "lbmix_last_error": ([vp], ctypes.c_char_p),
+        "lbmix_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.shape != shape:
+        a = a.reshape(shape)
+    return a
+
+
+class Lattice:
+    """A lattice of the GPU library.
+
+    geometry: "periodic" or "slit" (solid planes z = 0 and z = nz-1).
+    storage: "f64", "f32", "f32s", "bf16s", "f16s" (see lbmix_storage).
+    stream: a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's current stream.
+    """
+
+    def __init__(self, nx, ny, nz, geometry="periodic", storage="f64", stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbmix library has no CPU path")
+        self._L = load_library()
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self.stream_handle = handle
+        self.shape = (nz, ny, nx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.geometry = geometry
+        self.storage = storage
+        h = ctypes.c_void_p()
+        rc = self._L.lbmix_create(ctypes.byref(h), nx, ny, nz, GEOMETRY[geometry], STORAGE[storage],
+                                  ctypes.c_void_p(handle))
+        if rc:
+            raise LbmixError(rc, "lbmix_create rejected the lattice")
+        self._h = h
+        self.nspecies = 0
+
+    def _check(self, rc):
+        if rc:
+            msg = self._L.lbmix_last_error(self._h)
+            raise LbmixError(rc, msg.decode() if msg else "")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lbmix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- set-up -------------------------------------------------------------------------
+    def add_species(self, rho0, valence=0):
+        i = ctypes.c_int(-1)
+        self._check(self._L.lbmix_add_species(self._h, float(rho0), int(valence), ctypes.byref(i)))
+        self.nspecies += 1
+        return i.value
+
+    def set_tau_visc(self, tau):
+        self._check(self._L.lbmix_set_tau_visc(self._h, float(tau)))
+
+    def set_tau_drag(self, tau):
+        self._check(self._L.lbmix_set_tau_drag(self._h, float(tau)))
+
+    def set_schmidt(self, sc):
+        self._check(self._L.lbmix_set_schmidt(self._h, float(sc)))
+
+    def set_electrostatics(self, bjerrum, sigma_lo=0.0, sigma_hi=0.0, E=(0.0, 0.0, 0.0)):
+        e = (ctypes.c_double * 3)(*[float(v) for v in E])
+        self._check(self._L.lbmix_set_electrostatics(self._h, float(bjerrum), float(sigma_lo),
+                                                     float(sigma_hi), e))
+
+    def set_poisson(self, rel_tol=1e-8, max_sweeps=200000, check_every=10, omega=-1.0):
+        self._check(self._L.lbmix_set_poisson(self._h, float(rel_tol), int(max_sweeps),
+                                              int(check_every), float(omega)))
+
+    def set_state(self, s, n, u=None):
+        n = _f64(n, self.shape)
+        uu = None if u is None else _f64(u, (3,) + self.shape)
+        self._check(self._L.lbmix_set_state(self._h, int(s), _dp(n), _dp(uu)))
+
+    # -- stepping -------------------------------------------------------------------------
+    def step(self, n=1):
+        return self._check(self._L.lbmix_step(self._h, int(n)))
+
+    def step_status(self, n=1):
+        """Like step() but returns the status code instead of raising on ENOCONV."""
+        rc = self._L.lbmix_step(self._h, int(n))
+        if rc not in (OK, ENOCONV):
+            self._check(rc)
+        return rc
+
+    def sync(self):
+        self._check(self._L.lbmix_sync(self._h))
+
+    # -- read-back ------------------------------------------------------------------------
+    def moments(self, s):
+        n = np.empty(self.shape)
+        j = np.empty((3,) + self.shape)
+        self._check(self._L.lbmix_get_moments(self._h, int(s), _dp(n), _dp(j)))
+        return n, j
+
+    def moments_device(self, s, n_dev, j_dev=None):
+        """Write the moments of species s into torch float64 CUDA tensors (stream-ordered)."""
+        for t in (n_dev, j_dev):
+            if t is not None and (not t.is_cuda or not t.is_contiguous() or str(t.dtype) != "torch.float64"):
+                raise ValueError("device outputs must be contiguous float64 CUDA tensors")
+        if n_dev is not None and n_dev.numel() != self.nx * self.ny * self.nz:
+            raise ValueError("n_dev has the wrong size")
+        if j_dev is not None and j_dev.numel() != 3 * self.nx * self.ny * self.nz:
+            raise ValueError("j_dev has the wrong size")
+        self._check(self._L.lbmix_get_moments_device(
+            self._h, int(s), ctypes.c_void_p(n_dev.data_ptr() if n_dev is not None else 0),
+            ctypes.c_void_p(j_dev.data_ptr() if j_dev is not None else 0)))
+
+    def populations(self, s):
+        f = np.empty((19,) + self.shape)
+        self._check(self._L.lbmix_get_populations(self._h, int(s), _dp(f)))
+        return f
+
+    def potential(self):
+        p = np.empty(self.shape)
+        self._check(self._L.lbmix_get_potential(self._h, _dp(p)))
+        return p
+
+    def mass_totals(self):
+        out = np.empty(self.nspecies)
+        self._check(self._L.lbmix_get_mass_totals(self._h, _dp(out)))
+        return out
+
+    def zprofiles(self):
+        out = np.empty((self.nspecies, 4, self.nz))
+        self._check(self._L.lbmix_get_zprofiles(self._h, _dp(out)))
+        return out
+
+    def stats(self):
+        st = Stats()
+        self._check(self._L.lbmix_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def save(self, path):
+        self._check(self._L.lbmix_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        self._check(self._L.lbmix_load(self._h, str(path).encode()))
+
+
+def from_workload(w, storage="f64", stream=None, poisson=None):
+    """Build a Lattice from a workloads.Workload description (parameters and initial fields)."""
+    lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream)
+    for s in range(w.nspecies):
+        lat.add_species(w.rho0[s], w.valence[s])
+    lat.set_tau_visc(w.tau_visc)
+    lat.set_tau_drag(w.tau_drag)
+    if w.bjerrum > 0 or any(w.E):
+        lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
+    if poisson:
+        lat.set_poisson(**poisson)
+    for s in range(w.nspecies):
+        lat.set_state(s, w.n[s], w.u[s])
+    return lat

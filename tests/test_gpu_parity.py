@@ -1,0 +1,297 @@
+"""GPU <-> oracle parity through the C ABI (liblbmix.so on gfx950).
+
+Tolerances (derived from the arithmetic):
+* FP64 storage: two independent FP64 implementations of the step (the C oracle and the NumPy
+  brute force) differ after 500 steps of the 32^3 binary run by 3e-13 of the density
+  perturbation and by 3e-16 absolute (1.2e-12 of max|j|) in the momentum, the rounding floor
+  of sums of populations of size ~0.1.  The bar is 1e-12 relative to the deviation from rest
+  for densities and populations, and 1e-11 of max|j| for momenta.
+* FP32 storage: 1e-5 relative, populations and densities against max |f| and max |n|
+  (unit roundoff 6e-8 per operation, ~10 operations per step, errors damped by the
+  collision).  Momenta are checked against the population scale for plain FP32 (they are
+  differences of populations that FP32 resolves to ~1e-8 absolute) and against max|j| for
+  the shifted form, which stores deviations from rest.
+"""
+import math
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from parity_util import W as WQ, fluid, oracle_for, patch_workload, rel_max, rel_to_deviation
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1507_04891_amd as P
+    P.load_library()
+    return P
+
+
+def gpu_for(P, w, storage="f64", poisson=None):
+    return P.from_workload(w, storage=storage, poisson=poisson)
+
+
+def compare_fp64(lat, o, w, pop_tol=1e-12, n_tol=1e-12, j_tol=1e-11):
+    m = fluid(w)
+    for s in range(w.nspecies):
+        ng, jg = lat.moments(s)
+        no, jo = o.moments(s)
+        assert rel_to_deviation(ng, no, w.rho0[s], m) <= n_tol, (s, rel_to_deviation(ng, no, w.rho0[s], m))
+        assert rel_max(jg, jo, m) <= j_tol, (s, rel_max(jg, jo, m))
+        fg, fo = lat.populations(s), o.populations(s)
+        rest = (WQ * w.rho0[s])[:, None, None, None]
+        assert rel_to_deviation(fg, fo, rest, m) <= pop_tol, (s, rel_to_deviation(fg, fo, rest, m))
+        assert np.all(ng[~m] == 0) and np.all(jg[:, ~m] == 0)
+
+
+def test_config1_binary_32cubed_fp64_500_steps(P, oracle_mod):
+    """Neutral binary 32^3 periodic FP64, 0.01 sin(2 pi x / 32) antiphase, tau 1, Sc 10."""
+    w = WL.binary_sine(32, 32, 32, amp=0.01, tau_visc=1.0, sc=10.0)
+    lat = gpu_for(P, w, "f64")
+    o = oracle_for(oracle_mod, w)
+    lat.step(500)
+    o.step(500)
+    compare_fp64(lat, o, w)
+    st = lat.stats()
+    assert st["steps"] == 500
+
+
+CASES = [
+    # nx, ny, nz, geometry, ns, charged, E
+    (70, 6, 10, "periodic", 2, False, (0, 0, 0)),
+    (130, 3, 5, "periodic", 3, False, (1e-3, 0, -2e-4)),
+    (1, 1, 9, "periodic", 2, False, (0, 0, 0)),
+    (300, 2, 3, "slit", 1, False, (2e-4, 0, 0)),
+    (64, 4, 12, "slit", 3, True, (1e-3, 0, 0)),
+    (66, 2, 6, "slit", 4, True, (0, 5e-4, 0)),
+    (8, 8, 8, "periodic", 3, True, (0, 0, 1e-3)),
+    (2, 2, 3, "slit", 3, True, (1e-4, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}x{c[1]}x{c[2]}-{c[3]}-s{c[4]}{'-q' if c[5] else ''}")
+def test_random_state_fp64(P, oracle_mod, case):
+    nx, ny, nz, geo, ns, charged, E = case
+    val = [0, 1, -1, 2][:ns] if charged else [0] * ns
+    rho0 = [1.0, 0.02, 0.02, 0.01][:ns] if charged else [1.0 / ns] * ns
+    if charged and ns == 4:
+        rho0 = [1.0, 0.02, 0.04, 0.01]     # z = (0, 1, -1, 2): 0.02 - 0.04 + 0.02 = 0
+    w = WL.random_state(nx, ny, nz, ns, geometry=geo, seed=nx * 7 + nz, rho0=rho0, valence=val,
+                        bjerrum=0.5 if charged else 0.0, sigma=(0.0, 0.0), E=E, dn=0.0 if charged else 0.05,
+                        du=0.02, tau_visc=0.8, tau_drag=0.6)
+    sweeps = 30
+    lat = gpu_for(P, w, "f64", poisson=dict(rel_tol=0.0, max_sweeps=sweeps))
+    o = oracle_for(oracle_mod, w, poisson="sor", sor_tol=0.0, sor_max=sweeps)
+    lat.step(25)
+    o.step(25)
+    compare_fp64(lat, o, w)
+    if charged:
+        pg, po = lat.potential(), o.potential()
+        assert rel_max(pg, po, fluid(w)) <= 1e-12
+
+
+def test_charged_slit_converged_poisson_fp64(P, oracle_mod):
+    """Residual-controlled SOR: both sides take the same number of sweeps."""
+    w = WL.charged_slit(nx=8, ny=6, nz=18, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+    lat = gpu_for(P, w, "f64", poisson=dict(rel_tol=1e-10, max_sweeps=20000, check_every=5))
+    o = oracle_for(oracle_mod, w, poisson="sor", sor_tol=1e-10, sor_max=20000, sor_check=5)
+    lat.step(40)
+    o.step(40)
+    compare_fp64(lat, o, w)
+    st, so = lat.stats(), o.stats()
+    assert st["last_sweeps"] == so["sweeps"]
+    assert st["last_residual"] <= 1e-10
+    assert rel_max(lat.potential(), o.potential(), fluid(w)) <= 1e-11
+    # against the direct solve, the iterative potential is good to the SOR tolerance
+    od = oracle_for(oracle_mod, w, poisson="direct")
+    od.step(40)
+    assert rel_max(lat.potential(), od.potential(), fluid(w)) <= 1e-6
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32s"])
+def test_fp32_binary(P, oracle_mod, storage):
+    w = WL.binary_multimode(n=48, amp=1e-3, shear=1e-3, sc=100.0, seed=2)
+    lat = gpu_for(P, w, storage)
+    o = oracle_for(oracle_mod, w)
+    lat.step(60)
+    o.step(60)
+    for s in range(2):
+        ng, jg = lat.moments(s)
+        no, jo = o.moments(s)
+        assert rel_max(ng, no) <= 1e-5
+        fg, fo = lat.populations(s), o.populations(s)
+        assert rel_max(fg, fo) <= 1e-5
+        if storage == "f32s":
+            assert rel_max(jg, jo) <= 1e-5
+            assert rel_to_deviation(ng, no, 0.5) <= 1e-4
+        else:
+            assert np.abs(jg - jo).max() <= 1e-5 * np.abs(no).max()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f32s"])
+def test_fp32_charged_slit(P, oracle_mod, storage):
+    w = WL.charged_slit(nx=16, ny=8, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-3, Ex=1e-4, sc=100.0)
+    lat = gpu_for(P, w, storage, poisson=dict(rel_tol=0.0, max_sweeps=40))
+    o = oracle_for(oracle_mod, w, poisson="sor", sor_tol=0.0, sor_max=40)
+    lat.step(50)
+    o.step(50)
+    m = fluid(w)
+    for s in range(3):
+        ng, _ = lat.moments(s)
+        no, _ = o.moments(s)
+        assert rel_max(ng, no, m) <= 1e-5
+        assert rel_max(lat.populations(s), o.populations(s), m) <= 1e-5
+    assert rel_max(lat.potential(), o.potential(), m) <= 1e-5
+
+
+def test_determinism_and_mass_conservation(P):
+    w = WL.random_state(40, 12, 10, 3, geometry="slit", seed=4, rho0=[1.0, 0.01, 0.01],
+                        valence=[0, 1, -1], bjerrum=0.7, sigma=(0.0, 0.0), E=(1e-4, 0, 0), dn=0.0)
+    runs = []
+    for _ in range(2):
+        lat = gpu_for(P, w, "f64", poisson=dict(rel_tol=1e-9, max_sweeps=5000))
+        m0 = lat.mass_totals()
+        lat.step(300)
+        runs.append((lat.populations(1), lat.potential(), lat.mass_totals(), m0))
+    np.testing.assert_array_equal(runs[0][0], runs[1][0])
+    np.testing.assert_array_equal(runs[0][1], runs[1][1])
+    np.testing.assert_array_equal(runs[0][2], runs[1][2])
+    np.testing.assert_allclose(runs[0][2], runs[0][3], rtol=1e-13)
+
+
+def test_checkpoint_restart_is_bitwise(P):
+    w = WL.charged_slit(nx=8, ny=4, nz=14, debye_length=3.0, sigma=-2e-4, Ex=1e-4, sc=10.0)
+    pp = dict(rel_tol=1e-9, max_sweeps=5000)
+    a = gpu_for(P, w, "f32s", poisson=pp)
+    a.step(20)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        a.save(path)
+        a.step(30)
+        b = P.Lattice(w.nx, w.ny, w.nz, geometry="slit", storage="f32s")
+        for s in range(3):
+            b.add_species(w.rho0[s], w.valence[s])
+        b.load(path)
+        b.step(30)
+    for s in range(3):
+        np.testing.assert_array_equal(a.populations(s), b.populations(s))
+    np.testing.assert_array_equal(a.potential(), b.potential())
+    assert b.stats()["steps"] == 50
+
+
+def test_error_paths(P):
+    w = WL.binary_sine(8, 4, 4, amp=0.01)
+    # non-finite state latches ENONFINITE until set_state
+    lat = gpu_for(P, w, "f64")
+    bad = w.n[0].copy()
+    bad[1, 2, 3] = np.nan
+    lat.set_state(0, bad)
+    lat.step(2)
+    with pytest.raises(P.LbmixError) as e:
+        lat.mass_totals()
+    assert e.value.code == P.ENONFINITE
+    with pytest.raises(P.LbmixError) as e:
+        lat.step(1)
+    assert e.value.code == P.ENONFINITE
+    lat.set_state(0, w.n[0])
+    lat.set_state(1, w.n[1])
+    lat.step(1)
+    assert np.isfinite(lat.mass_totals()).all()
+    # sweep cap below need -> ENOCONV, steps still taken
+    ws = WL.charged_slit(nx=4, ny=4, nz=18, debye_length=3.0, sigma=-3e-4, Ex=0.0, sc=1.0)
+    lat = gpu_for(P, ws, "f64", poisson=dict(rel_tol=1e-12, max_sweeps=3, check_every=1))
+    assert lat.step_status(2) == P.ENOCONV
+    assert lat.stats()["steps"] == 2
+    # non-neutral charged system -> EINVAL at the first step
+    wn = WL.charged_slit(nx=4, ny=4, nz=10, sigma=-1e-3)
+    lat = P.from_workload(wn, storage="f64")
+    lat.set_electrostatics(wn.bjerrum, -2e-3, -2e-3, wn.E)
+    with pytest.raises(P.LbmixError) as e:
+        lat.step(1)
+    assert e.value.code == P.EINVAL
+    # odd periodic extent in a charged run -> EINVAL
+    wo = WL.random_state(5, 4, 4, 3, seed=1, rho0=[1.0, 0.01, 0.01], valence=[0, 1, -1], bjerrum=0.5, dn=0.0)
+    lat = P.from_workload(wo, storage="f64")
+    with pytest.raises(P.LbmixError) as e:
+        lat.step(1)
+    assert e.value.code == P.EINVAL
+
+
+def test_zprofiles_and_observables(P, oracle_mod):
+    w = WL.charged_slit(nx=6, ny=4, nz=20, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+    lat = gpu_for(P, w, "f64", poisson=dict(rel_tol=0.0, max_sweeps=20))
+    o = oracle_for(oracle_mod, w, poisson="sor", sor_tol=0.0, sor_max=20)
+    lat.step(30)
+    o.step(30)
+    prof = lat.zprofiles()
+    for s in range(3):
+        n, j = o.moments(s)
+        np.testing.assert_allclose(prof[s, 0], n.mean(axis=(1, 2)), rtol=1e-12, atol=1e-300)
+        for d in range(3):
+            np.testing.assert_allclose(prof[s, 1 + d], j[d].mean(axis=(1, 2)), rtol=0,
+                                       atol=1e-11 * np.abs(j[d]).max() + 1e-300)
+
+
+def test_moments_device_matches_host(P):
+    import torch
+    w = WL.binary_multimode(n=16, sc=10.0, seed=3)
+    lat = gpu_for(P, w, "f32")
+    lat.step(3)
+    n_dev = torch.empty(w.nx * w.ny * w.nz, dtype=torch.float64, device="cuda")
+    j_dev = torch.empty(3 * w.nx * w.ny * w.nz, dtype=torch.float64, device="cuda")
+    lat.moments_device(1, n_dev, j_dev)
+    torch.cuda.synchronize()
+    n, j = lat.moments(1)
+    np.testing.assert_array_equal(n_dev.cpu().numpy().reshape(n.shape), n)
+    np.testing.assert_array_equal(j_dev.cpu().numpy().reshape(j.shape), j)
+
+
+# --------------------------------------------------------------------------------------
+# Full sizes, in the launch configuration the benchmark times.
+
+def test_full_size_binary_256cubed_fp32_sampled(P, oracle_mod):
+    """256^3 periodic binary FP32 (multimode noise + shear wave, Sc = 100): after k steps the
+    GPU populations at sampled nodes equal the oracle's on light-cone patches."""
+    w = WL.binary_multimode(n=256, amp=1e-3, shear=1e-3, sc=100.0, seed=2)
+    k = 6
+    lat = gpu_for(P, w, "f32")
+    lat.step(k)
+    rng = np.random.default_rng(0)
+    centres = [(0, 0, 0), (255, 255, 255), (128, 0, 255)] + [tuple(rng.integers(0, 256, 3)) for _ in range(9)]
+    fg = [lat.populations(s) for s in range(2)]
+    for c in centres:
+        pw, h = patch_workload(w, c, k)
+        o = oracle_for(oracle_mod, pw)
+        o.step(k)
+        for s in range(2):
+            got = fg[s][:, c[0], c[1], c[2]]
+            want = o.populations(s)[:, h, h, h]
+            assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max(), (c, s)
+    # whole-lattice properties: mass conservation in FP64 totals
+    m = lat.mass_totals()
+    np.testing.assert_allclose(m, [0.5 * 256 ** 3] * 2, rtol=1e-6)
+
+
+def test_full_size_charged_slit_64x64x130_fp32(P, oracle_mod):
+    """The charged-slit configuration at full size (64 x 64 x 130, FP32, Sc 100, lambda_D 8):
+    a few steps against the oracle run on the whole lattice with the same SOR sweeps."""
+    w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    sweeps = 12
+    lat = gpu_for(P, w, "f32s", poisson=dict(rel_tol=0.0, max_sweeps=sweeps))
+    o = oracle_for(oracle_mod, w, poisson="sor", sor_tol=0.0, sor_max=sweeps)
+    lat.step(3)
+    o.step(3)
+    m = fluid(w)
+    for s in range(3):
+        ng, jg = lat.moments(s)
+        no, jo = o.moments(s)
+        assert rel_max(ng, no, m) <= 1e-5
+        assert rel_to_deviation(ng, no, w.rho0[s], m) <= 1e-3
+    assert rel_max(lat.potential(), o.potential(), m) <= 1e-5
