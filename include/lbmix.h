@@ -90,8 +90,8 @@ typedef struct {
 int lbmix_version(void);
 
 /* Create a lattice of nx * ny * nz nodes (wall planes included for LBMIX_SLIT_Z, which
- * needs nz >= 3).  `storage` is an lbmix_storage.  `hip_stream` is a hipStream_t to issue
- * all device work on (borrowed, not destroyed), or NULL for a stream owned by the context.
+ * needs nz >= 3).  `storage` is an lbmix_storage.  `hip_stream` is the hipStream_t to issue
+ * all device work on (borrowed, never destroyed); NULL is the HIP null stream.
  * No device memory is allocated until the first lbmix_set_state.  Defaults: tau_visc = 1,
  * Schmidt number 1 (tau_drag = tau_visc), no charge, Poisson tolerance 1e-8.
  * Errors: EINVAL for non-positive extents, nz < 3 for a slit, an unknown geometry or

@@ -47,8 +47,7 @@ struct lbmix_ctx {
     double sor_tol = 1e-8, sor_omega = -1.0;
     int sor_max = 200000, sor_check = 10;
     // device
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
+    hipStream_t stream = nullptr;     // borrowed; nullptr is the HIP null stream
     int device = 0;
     void *f[2] = {nullptr, nullptr};
     int cur = 0;
@@ -186,11 +185,6 @@ int allocate(lbmix_ctx *c) {
     if (c->allocated) return LBMIX_OK;
     int rc = c->hip(hipGetDevice(&c->device), "hipGetDevice");
     if (rc) return rc;
-    if (!c->stream) {
-        rc = c->hip(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking), "hipStreamCreate");
-        if (rc) return rc;
-        c->own_stream = true;
-    }
     const size_t pop = (size_t)c->ns * Q * c->Nf * c->esize;
     for (int k = 0; k < 2; ++k) {
         rc = c->hip(hipMalloc(&c->f[k], pop), "hipMalloc(populations)");
@@ -791,7 +785,6 @@ void lbmix_destroy(lbmix_ctx *c) {
         if (c->dred) (void)hipFree(c->dred);
         if (c->hred) (void)hipHostFree(c->hred);
         if (c->scratch) (void)hipFree(c->scratch);
-        if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
 }

@@ -37,11 +37,20 @@ def fluid(w):
 
 def rel_to_deviation(a, b, rest, mask=None):
     """max |a - b| / max |b - rest| over the mask."""
+    rest = np.broadcast_to(rest, b.shape)
     if mask is not None:
-        a, b = a[..., mask], b[..., mask]
-        rest = rest if np.isscalar(rest) else rest[..., mask]
+        a, b, rest = a[..., mask], b[..., mask], rest[..., mask]
     den = np.abs(b - rest).max()
     return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def within(a, b, rel, scale, floor, mask=None):
+    """max |a - b| <= rel * scale + floor over the mask; returns (ok, max |a - b|, bound)."""
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    err = float(np.abs(a - b).max())
+    bound = rel * scale + floor
+    return err <= bound, err, bound
 
 
 def rel_max(a, b, mask=None):
