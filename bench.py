@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--storage", default="f32")
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="also run a plain device copy of this many GiB (3 times), the reference "
+                         "kernel for scaling HBM counters")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -139,6 +142,15 @@ def main():
     }
     del lat
     torch.cuda.empty_cache()
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe * 2 ** 30)
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nbytes
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -9,11 +9,12 @@ namespace lbmix {
 
 constexpr int Q = 19;
 constexpr int MAXS = 4;
-constexpr int BLOCK = 256;        // threads per workgroup of every node kernel
+constexpr int BLOCK = 256;        // threads per work-group row of the node kernels
+constexpr int STEP_BLOCK = 512;   // threads per work-group of stream_collide (two rows)
 
 enum class Store : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
-// Arguments of the fused stream-collide launch.  Population arrays are [species][p][node]
+// Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
 // over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
 // storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
 struct StepArgs {
@@ -21,6 +22,7 @@ struct StepArgs {
     void *fout;
     uint32_t nx, ny, nzf;
     uint32_t N;                      // nx * ny * nzf
+    int ns;                          // species count (element stride of the layout)
     double rho_bar[MAXS];            // storage shift per species (0: plain f)
     float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
     float inv_scale[MAXS][Q];
@@ -47,6 +49,7 @@ struct PoissonArgs {
 };
 
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
+dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
 
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
                                  const StepArgs &a, hipStream_t stream);

@@ -9,9 +9,10 @@
 // in FP32), so there are no matrix-core contractions; the design goals are coalesced
 // streams, no re-reads, and no LDS round trips.
 //
-// Work-group shape: 256 threads along x for one (y, z) row (fewer when nx < 256), so y, z
-// and every bounce-back decision are wave-uniform and the x-shifted loads of a row stay in
-// one work-group (and one L2).  All arithmetic is done on deviations d_p = f_p - w_p
+// Work-group shape: 256 threads along x (fewer when nx < 256) times two rows, so y, z and
+// every bounce-back decision are wave-uniform and the x-shifted loads of a row stay in one
+// work-group (and one L2).  Populations are interleaved by species, so each direction is one
+// non-temporal vector load and one vector store of all species.  All arithmetic is done on deviations d_p = f_p - w_p
 // rho_bar, which makes the shifted storage forms exact in their range and costs nothing
 // for the plain ones (rho_bar = 0).
 #include "lbmix_kernels.h"
@@ -42,7 +43,8 @@ __host__ __device__ constexpr C wgt(int p) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Storage codecs.  C is the arithmetic type, S the stored element.
+// Storage codecs.  C is the arithmetic type, S the stored element; a stored element is
+// (f - w rho_bar) * scale.
 
 struct BF16 {};
 struct F16 {};
@@ -51,14 +53,14 @@ template <class T> struct Codec;
 template <> struct Codec<double> {
     using C = double;
     using S = double;
-    __device__ static C load(const S *p, uint32_t i, float) { return p[i]; }
-    __device__ static void store(S *p, uint32_t i, C v, float) { p[i] = v; }
+    __device__ static C decode(S v, float) { return v; }
+    __device__ static S encode(C v, float) { return v; }
 };
 template <> struct Codec<float> {
     using C = float;
     using S = float;
-    __device__ static C load(const S *p, uint32_t i, float) { return p[i]; }
-    __device__ static void store(S *p, uint32_t i, C v, float) { p[i] = v; }
+    __device__ static C decode(S v, float) { return v; }
+    __device__ static S encode(C v, float) { return v; }
 };
 // bfloat16: upper half of an IEEE binary32; round-to-nearest-even written out.
 __device__ inline uint16_t f32_to_bf16_rne(float f) {
@@ -71,21 +73,62 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 template <> struct Codec<BF16> {
     using C = float;
     using S = uint16_t;
-    __device__ static C load(const S *p, uint32_t i, float inv) {
-        return __uint_as_float(uint32_t(p[i]) << 16) * inv;
-    }
-    __device__ static void store(S *p, uint32_t i, C v, float sc) { p[i] = f32_to_bf16_rne(v * sc); }
+    __device__ static C decode(S v, float inv) { return __uint_as_float(uint32_t(v) << 16) * inv; }
+    __device__ static S encode(C v, float sc) { return f32_to_bf16_rne(v * sc); }
 };
 template <> struct Codec<F16> {
     using C = float;
     using S = uint16_t;
-    __device__ static C load(const S *p, uint32_t i, float inv) {
-        return __half2float(__ushort_as_half(p[i])) * inv;
+    __device__ static C decode(S v, float inv) { return __half2float(__ushort_as_half(v)) * inv; }
+    __device__ static S encode(C v, float sc) { return __half_as_ushort(__float2half_rn(v * sc)); }  // RNE
+};
+
+// Species-interleaved layout: the NS values of one direction at one node are contiguous,
+// element (s, p, node) at ((p * N) + node) * NS + s.  One vector access per direction and
+// node; non-temporal, since each element is touched once per step.  Three-element vectors
+// are only used where the ISA access has exactly their size (FP32: dwordx3).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x3 __attribute__((ext_vector_type(3), aligned(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+
+template <class S, int NS> struct VecIO {
+    __device__ static void load(const S *p, S (&o)[NS]) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) o[s] = __builtin_nontemporal_load(p + s);
     }
-    __device__ static void store(S *p, uint32_t i, C v, float sc) {
-        p[i] = __half_as_ushort(__float2half_rn(v * sc));   // IEEE round-to-nearest-even
+    __device__ static void store(S *p, const S (&v)[NS]) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) __builtin_nontemporal_store(v[s], p + s);
     }
 };
+template <class S, class V, int NS> struct VecIOv {
+    __device__ static void load(const S *p, S (&o)[NS]) {
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) o[s] = v[s];
+    }
+    __device__ static void store(S *p, const S (&o)[NS]) {
+        V v;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) v[s] = o[s];
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    }
+};
+template <> struct VecIO<float, 2> : VecIOv<float, f32x2, 2> {};
+template <> struct VecIO<float, 3> : VecIOv<float, f32x3, 3> {};
+template <> struct VecIO<float, 4> : VecIOv<float, f32x4, 4> {};
+template <> struct VecIO<double, 2> : VecIOv<double, f64x2, 2> {};
+template <> struct VecIO<double, 4> : VecIOv<double, f64x4, 4> {};
+template <> struct VecIO<uint16_t, 2> : VecIOv<uint16_t, u16x2, 2> {};
+template <> struct VecIO<uint16_t, 4> : VecIOv<uint16_t, u16x4, 4> {};
+
+__device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int ns) {
+    return ((size_t)arr * N + node) * ns;
+}
 
 // ---------------------------------------------------------------------------------------
 // Pull addressing shared by every kernel that reads a pre-collision state: the value of
@@ -136,7 +179,7 @@ __device__ __forceinline__ void static_for(F &&f) {
 // Deterministic work-group sum of NV doubles (fixed shuffle tree, fixed wave order).
 template <int NV>
 __device__ void block_sum_store(double (&v)[NV], double *partials, uint32_t nblocks, uint32_t bid) {
-    __shared__ double red[NV][BLOCK / 64];
+    __shared__ double red[NV][STEP_BLOCK / 64];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double t = v[k];
@@ -144,15 +187,16 @@ __device__ void block_sum_store(double (&v)[NV], double *partials, uint32_t nblo
         for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
         v[k] = t;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nwaves = (blockDim.x + 63) >> 6;
+    const int tid = threadIdx.x + blockDim.x * threadIdx.y;     // blockDim.x is a multiple of 64
+    const int lane = tid & 63, wave = tid >> 6;
+    const int nwaves = (blockDim.x * blockDim.y + 63) >> 6;
     if (lane == 0)
         for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
     __syncthreads();
-    if (threadIdx.x < NV) {
+    if (tid < NV) {
         double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += red[threadIdx.x][w];
-        partials[(size_t)threadIdx.x * nblocks + bid] = s;
+        for (int w = 0; w < nwaves; ++w) s += red[tid][w];
+        partials[(size_t)tid * nblocks + bid] = s;
     }
 }
 
@@ -160,29 +204,30 @@ __device__ void block_sum_store(double (&v)[NV], double *partials, uint32_t nblo
 // The fused step.
 
 template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED>
-__global__ __launch_bounds__(BLOCK) void stream_collide(const StepArgs a) {
+__global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     using CD = Codec<T>;
     using C = typename CD::C;
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = x < a.nx;
-    const Pull pl(active ? x : 0, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;   // uniform per wave
+    const bool active = x < a.nx && y < a.ny;
+    const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
     const uint32_t own = pl.own();
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
 
-    // 1. pull streaming with bounce-back: 19 loads per species
+    // 1. pull streaming with bounce-back: one vector load of all species per direction
     C d[NS][Q];
+    static_for<Q>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        int arr;
+        uint32_t node;
+        pl.template src<p>(arr, node);
+        S raw[NS];
+        VecIO<S, NS>::load(fin + elem(arr, node, a.N, NS), raw);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        static_for<Q>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            int arr;
-            uint32_t node;
-            pl.template src<p>(arr, node);
-            d[s][p] = CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]);
-        });
-    }
+        for (int s = 0; s < NS; ++s) d[s][p] = CD::decode(raw[s], a.inv_scale[s][arr]);
+    });
 
     // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c
     C dn[NS], jx[NS], jy[NS], jz[NS], n[NS];
@@ -243,42 +288,59 @@ __global__ __launch_bounds__(BLOCK) void stream_collide(const StepArgs a) {
         }
     }
 
-    // 4-5. forces and collision per species, pairing each direction with its opposite
+    // 4. forces per species: drag on mid-step velocities plus the field force,
+    //    F_s = -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s, then the coefficients of the
+    //    collision that are common to every direction
     const C ov = C(a.omega_v), od = C(a.omega_d), keep = C(1) - ov;
+    C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS], base[NS], ov45[NS], n9[NS], n3[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const C inv_n = n[s] != C(0) ? C(1) / n[s] : C(0);
-        const C uax = jx[s] * inv_n, uay = jy[s] * inv_n, uaz = jz[s] * inv_n;
-        // drag on mid-step velocities: -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s
-        C Fx = -od * (uax - ux), Fy = -od * (uay - uy), Fz = -od * (uaz - uz);
+        uax[s] = jx[s] * inv_n;
+        uay[s] = jy[s] * inv_n;
+        uaz[s] = jz[s] * inv_n;
+        Fx[s] = -od * (uax[s] - ux);
+        Fy[s] = -od * (uay[s] - uy);
+        Fz[s] = -od * (uaz[s] - uz);
         if constexpr (FIELD) {
             const C k = C(a.valence[s]) * (C(1) - C(0.5) * od) + C(0.5) * od * qn * inv_ntot;
-            Fx += k * fx;
-            Fy += k * fy;
-            Fz += k * fz;
+            Fx[s] += k * fx;
+            Fy[s] += k * fy;
+            Fz[s] += k * fz;
         }
-        const C ns_ = n[s];
-        const C uu = uax * uax + uay * uay + uaz * uaz;
-        const C Fu = Fx * ux + Fy * uy + Fz * uz;
-        // part of w^-1 (f* - (1 - ov) d) common to p and opp(p)
-        const C base = ov * (dn[s] - C(1.5) * ns_ * uu) - C(3) * ns_ * Fu;
-        const C ov45 = C(4.5) * ov * ns_, n9 = C(9) * ns_, n3 = C(3) * ns_;
-        S *out = fout + (size_t)(s * Q) * a.N;
-        if (active) {
-            CD::store(out, own, keep * d[s][0] + wgt<C>(0) * base, a.scale[s][0]);
-            static_for<9>([&](auto kc) {
-                constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
-                constexpr int pb = p + 1;
-                constexpr C w = wgt<C>(p);
-                const C cu = C(cx(p)) * uax + C(cy(p)) * uay + C(cz(p)) * uaz;
+        const C uu = uax[s] * uax[s] + uay[s] * uay[s] + uaz[s] * uaz[s];
+        const C Fu = Fx[s] * ux + Fy[s] * uy + Fz[s] * uz;
+        // w^-1 (f*_p - (1 - ov) d_p) = base + ov45 (c.u_s)^2 + n9 (c.F)(c.u) +- n3 (ov c.u_s + c.F)
+        base[s] = ov * (dn[s] - C(1.5) * n[s] * uu) - C(3) * n[s] * Fu;
+        ov45[s] = C(4.5) * ov * n[s];
+        n9[s] = C(9) * n[s];
+        n3[s] = C(3) * n[s];
+    }
+
+    // 5. collision and store, one direction pair at a time, all species per vector store
+    if (active) {
+        S o0[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) o0[s] = CD::encode(keep * d[s][0] + wgt<C>(0) * base[s], a.scale[s][0]);
+        VecIO<S, NS>::store(fout + elem(0, own, a.N, NS), o0);
+        static_for<9>([&](auto kc) {
+            constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
+            constexpr int pb = p + 1;
+            constexpr C w = wgt<C>(p);
+            S op[NS], ob[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const C cu = C(cx(p)) * uax[s] + C(cy(p)) * uay[s] + C(cz(p)) * uaz[s];
                 const C cub = C(cx(p)) * ux + C(cy(p)) * uy + C(cz(p)) * uz;
-                const C cF = C(cx(p)) * Fx + C(cy(p)) * Fy + C(cz(p)) * Fz;
-                const C sym = w * (base + ov45 * cu * cu + n9 * cF * cub);
-                const C anti = w * n3 * (ov * cu + cF);
-                CD::store(out + (size_t)p * a.N, own, keep * d[s][p] + sym + anti, a.scale[s][p]);
-                CD::store(out + (size_t)pb * a.N, own, keep * d[s][pb] + sym - anti, a.scale[s][pb]);
-            });
-        }
+                const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
+                const C sym = w * (base[s] + ov45[s] * cu * cu + n9[s] * cF * cub);
+                const C anti = w * n3[s] * (ov * cu + cF);
+                op[s] = CD::encode(keep * d[s][p] + sym + anti, a.scale[s][p]);
+                ob[s] = CD::encode(keep * d[s][pb] + sym - anti, a.scale[s][pb]);
+            }
+            VecIO<S, NS>::store(fout + elem(p, own, a.N, NS), op);
+            VecIO<S, NS>::store(fout + elem(pb, own, a.N, NS), ob);
+        });
     }
 
     // 7. FP64 mass partials of this work-group
@@ -315,7 +377,7 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
         int arr;
         uint32_t node;
         pl.template src<p>(arr, node);
-        CD::store(f + (size_t)(s * Q + arr) * a.N, node, typename CD::C(dev), a.scale[s][arr]);
+        f[elem(arr, node, a.N, a.ns) + s] = CD::encode(typename CD::C(dev), a.scale[s][arr]);
     });
 }
 
@@ -347,7 +409,7 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
         int arr;
         uint32_t node;
         pl.template src<p>(arr, node);
-        const double dv = double(CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]));
+        const double dv = double(CD::decode(fin[elem(arr, node, a.N, a.ns) + s], a.inv_scale[s][arr]));
         if constexpr (MODE == 1) {
             out0[(size_t)p * Nfull + fi] = dv + wgt<double>(p) * a.rho_bar[s];
         } else {
@@ -383,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
             int arr;
             uint32_t node;
             pl.template src<p>(arr, node);
-            m0 += double(CD::load(fin + (size_t)(s * Q + arr) * a.N, node, a.inv_scale[s][arr]));
+            m0 += double(CD::decode(fin[elem(arr, node, a.N, a.ns) + s], a.inv_scale[s][arr]));
         });
         qq += a.valence[s] * m0;
     }
@@ -555,10 +617,18 @@ static hipError_t sc_ns(int ns, bool slit, bool field, bool charged, const StepA
     }
 }
 
+dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block) {
+    uint32_t bx = ((nx + 63) / 64) * 64;
+    if (bx > BLOCK) bx = BLOCK;
+    const uint32_t by = STEP_BLOCK / BLOCK;   // rows per work-group (two rows of 256 measured best)
+    *block = dim3(bx, by, 1);
+    return dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nzf);
+}
+
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged, const StepArgs &a,
                                  hipStream_t stream) {
     dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b);
     switch (st) {
         case Store::F64: return sc_ns<double>(ns, slit, field, charged, a, g, b, stream);
         case Store::F32: return sc_ns<float>(ns, slit, field, charged, a, g, b, stream);

@@ -1,6 +1,6 @@
 // Host runtime of the multicomponent lattice-Boltzmann library: the context behind the C ABI
 // of include/lbmix.h.  It owns the device memory (double-buffered populations over the
-// fluid nodes, potential, charge density, reduction scratch), maps the physical parameters
+// fluid nodes, stored [p][node][species], potential, charge density, reduction scratch), maps the physical parameters
 // to relaxation frequencies (Sec. IV: nu = v_T^2 (1/omega_visc - 1/2),
 // D = v_T^2 (1/omega_drag - 1/2)) and sequences a time step: one fused stream-collide
 // launch, then for charged runs the Poisson solve of the new charge density, used by the
@@ -106,6 +106,11 @@ struct lbmix_ctx {
         const dim3 g = node_grid(nx, ny, nzf, &b);
         return g.x * g.y * g.z;
     }
+    uint32_t step_blocks() const {
+        dim3 b;
+        const dim3 g = step_grid(nx, ny, nzf, &b);
+        return g.x * g.y * g.z;
+    }
     StepArgs args() const {
         StepArgs a;
         std::memset(&a, 0, sizeof a);
@@ -115,6 +120,7 @@ struct lbmix_ctx {
         a.ny = ny;
         a.nzf = nzf;
         a.N = Nf;
+        a.ns = ns;
         a.q_rest = 0.0;
         for (int s = 0; s < MAXS; ++s) {
             a.rho_bar[s] = s < ns ? rho_bar(s) : 0.0;
@@ -194,13 +200,13 @@ int allocate(lbmix_ctx *c) {
     }
     const uint32_t nb = c->node_blocks();
     const uint32_t qb = (c->Nf + BLOCK - 1) / BLOCK;
-    c->step_nb = nb;
+    c->step_nb = c->step_blocks();
     c->partials_cap = (size_t)4 * std::max(nb, qb);
     rc = c->hip(hipMalloc((void **)&c->partials, c->partials_cap * sizeof(double)), "hipMalloc(partials)");
     if (rc) return rc;
-    rc = c->hip(hipMalloc((void **)&c->step_partials, (size_t)MAXS * nb * sizeof(double)), "hipMalloc(partials)");
+    rc = c->hip(hipMalloc((void **)&c->step_partials, (size_t)MAXS * c->step_nb * sizeof(double)), "hipMalloc(partials)");
     if (rc) return rc;
-    rc = c->hip(hipMemsetAsync(c->step_partials, 0, (size_t)MAXS * nb * sizeof(double), c->stream), "hipMemset");
+    rc = c->hip(hipMemsetAsync(c->step_partials, 0, (size_t)MAXS * c->step_nb * sizeof(double), c->stream), "hipMemset");
     if (rc) return rc;
     rc = c->hip(hipMalloc((void **)&c->dred, 16 * sizeof(double)), "hipMalloc(reduction)");
     if (rc) return rc;
