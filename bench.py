@@ -1,10 +1,12 @@
 """Throughput of the fused multicomponent LB step on one MI355X.
 
-Workload: neutral binary mixture on a 256^3 periodic D3Q19 lattice, FP32 populations,
-rest density 0.5 per species, 8 seeded concentration modes (amplitude 1e-3, antiphase
-between species) plus a shear wave u_y = 1e-3 sin(2 pi x / 256), tau_visc = 1, Sc = 100
-(synthetic inputs from workloads.binary_multimode, seed 2).  One step = one fused
-stream-collide launch (pull streaming, moments, drag, collision, store, FP64 mass partials).
+Workload: neutral binary mixture on a 256^3 periodic D3Q19 lattice, FP32 populations
+stored as deviations from rest (f - w rho0), rest density 0.5 per species, 8 seeded
+concentration modes (amplitude 1e-3, antiphase between species) plus a shear wave
+u_y = 1e-3 sin(2 pi x / 256), tau_visc = 1, Sc = 100 (synthetic inputs from
+workloads.binary_multimode, seed 2).  One step = one fused stream-collide launch (pull
+streaming, moments, drag, collision, store, FP64 mass partials).  The same workload is also
+timed with plain FP32, FP16 and BF16 storage ("variants").
 
 Prints one JSON line: species-site updates per second (GLUPS), the roofline of the
 stream-collide kernel against MI355X HBM bandwidth, and the FP64 CPU oracle timed on a
@@ -71,15 +73,48 @@ def cpu_baseline(w, target_s: float = 12.0):
                       f"{elapsed:.1f} s on {threads} OpenMP threads"}
 
 
+def time_storage(P, w, storage, steps, warmup):
+    """Time `steps` steps of the workload with one storage form; one fused launch per step."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    lat = P.from_workload(w, storage=storage, stream=stream)
+    lat.step(warmup)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    lat.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end)
+    totals = lat.mass_totals()
+    nodes = w.nx * w.ny * w.nz
+    assert all(abs(t / (0.5 * nodes) - 1) < 1e-5 for t in totals), (storage, totals)
+    del lat
+    torch.cuda.empty_cache()
+    sites = w.nspecies * nodes
+    esize = P.ELEMENT_BYTES[P.STORAGE[storage]]
+    ms_per_step = ms / steps
+    achieved = 2 * Q * esize * sites / (ms_per_step * 1e-3) / 1e9   # 19 reads + 19 writes
+    return {"glups": sites * steps / (ms * 1e-3) / 1e9, "ms_per_step": ms_per_step,
+            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS}
+
+
+DTYPE = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f16", "bf16s": "bf16"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--storage", default="f32")
+    ap.add_argument("--storage", default="f32s",
+                    help="f32s (FP32 deviations from rest, the default), f32, f16s, bf16s, f64")
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (3 times), the reference "
                          "kernel for scaling HBM counters")
@@ -97,51 +132,37 @@ def main():
 
     torch.cuda.set_device(0)
     w = WL.binary_multimode(n=args.n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=args.sc, seed=2)
-    stream = torch.cuda.current_stream()
-    lat = P.from_workload(w, storage=args.storage, stream=stream)
-    lat.step(args.warmup)
-    torch.cuda.synchronize()
-
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    lat.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
-    ms_per_step = ms / args.steps
-
-    sites = w.nspecies * w.nx * w.ny * w.nz
-    glups = sites * args.steps / (ms * 1e-3) / 1e9
-    esize = P.ELEMENT_BYTES[P.STORAGE[args.storage]]
-    bytes_per_launch = 2 * Q * esize * sites              # 19 reads + 19 writes per species-site
-    achieved = bytes_per_launch / (ms_per_step * 1e-3) / 1e9
-    totals = lat.mass_totals()
-    assert all(abs(t / (0.5 * args.n ** 3) - 1) < 1e-5 for t in totals), totals
-
+    head = time_storage(P, w, args.storage, args.steps, args.warmup)
     out = {
         "metric": "species-site updates/s (GLUPS), %HBM peak",
-        "value": round(glups, 4),
+        "value": round(head["glups"], 4),
         "unit": "GLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": round(head["ms_per_step"], 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.storage.startswith("f32") else args.storage,
+        "dtype": DTYPE[args.storage],
         "data": "synthetic",
         "config": {"workload": f"neutral binary D3Q19 {args.n}^3 periodic, {args.storage} populations, "
                                f"Sc={args.sc:g}, tau_visc=1, multimode noise + shear wave (seed 2)",
                    "species": 2, "lattice": [args.n] * 3, "storage": args.storage, "schmidt": args.sc},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": traffic_from_profile(args.storage, args.n)},
     }
-    del lat
-    torch.cuda.empty_cache()
+    if not args.no_variants:
+        var = {}
+        for st in ("f32", "f16s", "bf16s"):
+            if st == args.storage:
+                continue
+            r = time_storage(P, w, st, args.steps, args.warmup)
+            var[st] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
+                       "hbm_frac": round(r["frac"], 4),
+                       "speedup_vs_headline": round(r["glups"] / head["glups"], 3)}
+        out["variants"] = var
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 2 ** 30)
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")

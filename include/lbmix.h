@@ -139,6 +139,24 @@ int lbmix_set_electrostatics(lbmix_ctx *ctx, double bjerrum, double sigma_lo,
 int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_every,
                       double omega_sor);
 
+/* Rounding of the 16-bit storage forms (LBMIX_BF16_SHIFTED, LBMIX_F16_SHIFTED): mode 0
+ * rounds to nearest-even (default); mode 1 rounds stochastically, each stored value going
+ * up or down with the probabilities that make its expectation exact, the random bits drawn
+ * from a counter-based hash of (seed, step, node, direction, species), so runs are
+ * reproducible and a restored checkpoint continues bitwise.  Nearest rounding of a 16-bit
+ * deviation has fixed points: a slow mode whose change per step is below half a unit in
+ * the last place (relative 2.4e-4 for FP16) stops evolving; stochastic rounding removes
+ * this bias at the price of noise that averages out over nodes.  Errors: EINVAL for
+ * another mode, or mode 1 with a storage form that is not 16-bit. */
+int lbmix_set_rounding(lbmix_ctx *ctx, int mode, unsigned long long seed);
+
+/* FP16 storage scale of one species: the bound `rel_range` of |f_p - w_p rho0| / (w_p rho0)
+ * the lattice is expected to reach (default 0.1).  The power-of-two scale per direction
+ * maps that bound near 2^12, leaving a factor 16 of headroom below the FP16 maximum and
+ * about eight binary decades above its normal minimum.  Errors: EINVAL; ESTATE after the
+ * first set_state. */
+int lbmix_set_storage_range(lbmix_ctx *ctx, int species, double rel_range);
+
 /* Equilibrium initial state of one species at time 0 (re-initialises a running context,
  * resetting its step counter and latched error once every species is set again):
  * f_p = phi_perp_p(n, u^alpha), the pre-collision populations at time 0.  n is a host

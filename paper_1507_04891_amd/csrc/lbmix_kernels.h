@@ -34,6 +34,8 @@ struct StepArgs {
     double q_rest;                   // sum_s valence_s * rho_bar_s
     double ghost_lo, ghost_hi;       // 4 pi l_B sigma of the walls z = 0 and z = nz-1
     double *partials;                // out: [species][block] FP64 sums of n - rho_bar
+    int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
+    uint32_t seed;                   // per-step seed of the rounding hash
 };
 
 struct PoissonArgs {

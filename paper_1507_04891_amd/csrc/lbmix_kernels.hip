@@ -53,34 +53,73 @@ template <class T> struct Codec;
 template <> struct Codec<double> {
     using C = double;
     using S = double;
+    static constexpr bool kRounds = false;
     __device__ static C decode(S v, float) { return v; }
-    __device__ static S encode(C v, float) { return v; }
+    __device__ static S encode(C v, float, bool = false, uint32_t = 0) { return v; }
 };
 template <> struct Codec<float> {
     using C = float;
     using S = float;
+    static constexpr bool kRounds = false;
     __device__ static C decode(S v, float) { return v; }
-    __device__ static S encode(C v, float) { return v; }
+    __device__ static S encode(C v, float, bool = false, uint32_t = 0) { return v; }
 };
-// bfloat16: upper half of an IEEE binary32; round-to-nearest-even written out.
-__device__ inline uint16_t f32_to_bf16_rne(float f) {
+// Counter-based 32-bit hash (the "lowbias32" integer mixer: xor-shift / multiply rounds
+// with the published constants 0x7feb352d and 0x846ca68b), used to draw the random bits of
+// stochastic rounding from (seed, node, direction, species).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// bfloat16: upper half of an IEEE binary32.  Nearest-even, or stochastic: add 16 random
+// bits below the kept mantissa and truncate, which rounds the magnitude up with probability
+// equal to the dropped fraction (unbiased: the expected stored value is the exact one).
+__device__ inline uint16_t f32_to_bf16(float f, bool stochastic, uint32_t rnd) {
     uint32_t u = __float_as_uint(f);
     if ((u & 0x7f800000u) == 0x7f800000u)                 // Inf, NaN (kept quiet)
         return (u & 0x007fffffu) ? uint16_t((u >> 16) | 0x0040u) : uint16_t(u >> 16);
-    u += 0x7fffu + ((u >> 16) & 1u);
+    u += stochastic ? (rnd & 0xffffu) : 0x7fffu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
 }
+// binary16 from binary32.  Nearest-even by the hardware conversion, or stochastic: in the
+// binary16 normal range the 13 low mantissa bits of the binary32 value are the ones
+// binary16 drops, so adding 13 random bits and clearing them rounds stochastically and the
+// conversion of the result is exact (values below the binary16 normal range, far under the
+// scaled range, fall back to nearest-even).
+__device__ inline uint16_t f32_to_f16(float f, bool stochastic, uint32_t rnd) {
+    if (stochastic) {
+        uint32_t u = __float_as_uint(f);
+        const uint32_t e = (u >> 23) & 0xffu;
+        if (e >= 113u && e < 255u) {                      // |f| >= 2^-14
+            u = (u + (rnd & 0x1fffu)) & ~0x1fffu;
+            f = __uint_as_float(u);
+        }
+    }
+    return __half_as_ushort(__float2half_rn(f));
+}
+
 template <> struct Codec<BF16> {
     using C = float;
     using S = uint16_t;
+    static constexpr bool kRounds = true;
     __device__ static C decode(S v, float inv) { return __uint_as_float(uint32_t(v) << 16) * inv; }
-    __device__ static S encode(C v, float sc) { return f32_to_bf16_rne(v * sc); }
+    __device__ static S encode(C v, float sc, bool sr = false, uint32_t rnd = 0) {
+        return f32_to_bf16(v * sc, sr, rnd);
+    }
 };
 template <> struct Codec<F16> {
     using C = float;
     using S = uint16_t;
+    static constexpr bool kRounds = true;
     __device__ static C decode(S v, float inv) { return __half2float(__ushort_as_half(v)) * inv; }
-    __device__ static S encode(C v, float sc) { return __half_as_ushort(__float2half_rn(v * sc)); }  // RNE
+    __device__ static S encode(C v, float sc, bool sr = false, uint32_t rnd = 0) {
+        return f32_to_f16(v * sc, sr, rnd);
+    }
 };
 
 // Species-interleaved layout: the NS values of one direction at one node are contiguous,
@@ -229,15 +268,21 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         for (int s = 0; s < NS; ++s) d[s][p] = CD::decode(raw[s], a.inv_scale[s][arr]);
     });
 
-    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c
+    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c.  The density deviation is
+    //    also summed in FP64 (dnh): with deviations stored, the update of a direction is
+    //    w dn + (flux and force terms), and FP32 rounding at the scale of w dn would be about
+    //    1 % of the per-step change of a slow diffusion mode at Sc = 100.
     C dn[NS], jx[NS], jy[NS], jz[NS], n[NS];
+    double dnh[NS];
     C ntot = 0, sjx = 0, sjy = 0, sjz = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         C m0 = 0, mx = 0, my = 0, mz = 0;
+        double m0h = 0.0;
         static_for<Q>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             m0 += d[s][p];
+            m0h += double(d[s][p]);
             if constexpr (cx(p) == 1) mx += d[s][p];
             if constexpr (cx(p) == -1) mx -= d[s][p];
             if constexpr (cy(p) == 1) my += d[s][p];
@@ -246,6 +291,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             if constexpr (cz(p) == -1) mz -= d[s][p];
         });
         dn[s] = m0;
+        dnh[s] = m0h;
         jx[s] = mx;
         jy[s] = my;
         jz[s] = mz;
@@ -283,7 +329,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         if (active) {
             double qq = a.q_rest;
 #pragma unroll
-            for (int s = 0; s < NS; ++s) qq += a.valence[s] * double(dn[s]);
+            for (int s = 0; s < NS; ++s) qq += a.valence[s] * dnh[s];
             a.q[own] = qq;
         }
     }
@@ -291,8 +337,9 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     // 4. forces per species: drag on mid-step velocities plus the field force,
     //    F_s = -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s, then the coefficients of the
     //    collision that are common to every direction
-    const C ov = C(a.omega_v), od = C(a.omega_d), keep = C(1) - ov;
+    const C ov = C(a.omega_v), od = C(a.omega_d);
     C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS], base[NS], ov45[NS], n9[NS], n3[NS];
+    double big[NS][3];   // w ov dn in FP64 for the three weight classes
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const C inv_n = n[s] != C(0) ? C(1) / n[s] : C(0);
@@ -310,23 +357,36 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         }
         const C uu = uax[s] * uax[s] + uay[s] * uay[s] + uaz[s] * uaz[s];
         const C Fu = Fx[s] * ux + Fy[s] * uy + Fz[s] * uz;
-        // w^-1 (f*_p - (1 - ov) d_p) = base + ov45 (c.u_s)^2 + n9 (c.F)(c.u) +- n3 (ov c.u_s + c.F)
-        base[s] = ov * (dn[s] - C(1.5) * n[s] * uu) - C(3) * n[s] * Fu;
+        // f*_p = [(1 - ov) d_p + w (base + ov45 (c.u_s)^2 + n9 (c.F)(c.u)) +- w n3 (ov c.u_s + c.F)]
+        //        + w ov dn, the last term and the final sum in FP64
+        base[s] = -C(1.5) * ov * n[s] * uu - C(3) * n[s] * Fu;
+        big[s][0] = wgt<double>(0) * a.omega_v * dnh[s];
+        big[s][1] = wgt<double>(1) * a.omega_v * dnh[s];
+        big[s][2] = wgt<double>(7) * a.omega_v * dnh[s];
         ov45[s] = C(4.5) * ov * n[s];
         n9[s] = C(9) * n[s];
         n3[s] = C(3) * n[s];
     }
 
     // 5. collision and store, one direction pair at a time, all species per vector store
+    const bool sr = CD::kRounds && a.stochastic;
+    const uint32_t hnode = sr ? mix32(own ^ a.seed) : 0u;
+    auto rnd = [&](int p, int s) -> uint32_t {
+        return sr ? mix32(hnode + uint32_t(p * MAXS + s) * 0x9e3779b9u) : 0u;
+    };
+    const C keep = C(1) - ov;
     if (active) {
         S o0[NS];
 #pragma unroll
-        for (int s = 0; s < NS; ++s) o0[s] = CD::encode(keep * d[s][0] + wgt<C>(0) * base[s], a.scale[s][0]);
+        for (int s = 0; s < NS; ++s)
+            o0[s] = CD::encode(C(double(keep * d[s][0] + wgt<C>(0) * base[s]) + big[s][0]), a.scale[s][0], sr,
+                               rnd(0, s));
         VecIO<S, NS>::store(fout + elem(0, own, a.N, NS), o0);
         static_for<9>([&](auto kc) {
             constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
             constexpr int pb = p + 1;
             constexpr C w = wgt<C>(p);
+            constexpr int cls = p < 7 ? 1 : 2;
             S op[NS], ob[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -335,8 +395,10 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
                 const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
                 const C sym = w * (base[s] + ov45[s] * cu * cu + n9[s] * cF * cub);
                 const C anti = w * n3[s] * (ov * cu + cF);
-                op[s] = CD::encode(keep * d[s][p] + sym + anti, a.scale[s][p]);
-                ob[s] = CD::encode(keep * d[s][pb] + sym - anti, a.scale[s][pb]);
+                op[s] = CD::encode(C(double(keep * d[s][p] + sym + anti) + big[s][cls]), a.scale[s][p], sr,
+                                   rnd(p, s));
+                ob[s] = CD::encode(C(double(keep * d[s][pb] + sym - anti) + big[s][cls]), a.scale[s][pb], sr,
+                                   rnd(pb, s));
             }
             VecIO<S, NS>::store(fout + elem(p, own, a.N, NS), op);
             VecIO<S, NS>::store(fout + elem(pb, own, a.N, NS), ob);
@@ -346,7 +408,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     // 7. FP64 mass partials of this work-group
     double v[NS];
 #pragma unroll
-    for (int s = 0; s < NS; ++s) v[s] = active ? double(dn[s]) : 0.0;
+    for (int s = 0; s < NS; ++s) v[s] = active ? dnh[s] : 0.0;
     const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     const uint32_t nb = gridDim.x * gridDim.y * gridDim.z;
     block_sum_store<NS>(v, a.partials, nb, bid);

@@ -45,6 +45,8 @@ struct lbmix_ctx {
     bool drag_from_sc = true;
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
+    int rounding = 0;                 // 16-bit forms: 0 nearest-even, 1 stochastic
+    unsigned long long round_seed = 0;
     int sor_max = 200000, sor_check = 10;
     // device
     hipStream_t stream = nullptr;     // borrowed; nullptr is the HIP null stream
@@ -139,6 +141,14 @@ struct lbmix_ctx {
         a.ghost_lo = 4.0 * kPi * lB * sig_lo;
         a.ghost_hi = 4.0 * kPi * lB * sig_hi;
         a.partials = step_partials;
+        a.stochastic = rounding;
+        {   // per-step seed: a splitmix64 finaliser of (seed, step), folded to 32 bits
+            unsigned long long z = round_seed + 0x9e3779b97f4a7c15ull * (unsigned long long)(steps + 1);
+            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+            z ^= z >> 31;
+            a.seed = (uint32_t)(z ^ (z >> 32));
+        }
         return a;
     }
     PoissonArgs pargs() const {
@@ -362,7 +372,8 @@ struct Header {
     int32_t version, nx, ny, nz, geometry, storage, ns, valence[MAXS];
     double rho0[MAXS], rel_range[MAXS], host_total[MAXS];
     double tau_v, tau_d, sc;
-    int32_t drag_from_sc, sor_max, sor_check, psi_valid;
+    int32_t drag_from_sc, sor_max, sor_check, psi_valid, rounding, pad_;
+    uint64_t round_seed;
     double lB, sig_lo, sig_hi, E[3], sor_tol, sor_omega;
     int64_t steps;
 };
@@ -474,6 +485,26 @@ int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_ev
     c->sor_max = max_sweeps;
     c->sor_check = check_every;
     c->sor_omega = omega_sor;
+    return LBMIX_OK;
+}
+
+int lbmix_set_rounding(lbmix_ctx *c, int mode, unsigned long long seed) {
+    if (!c) return LBMIX_EINVAL;
+    if (mode != 0 && mode != 1) return c->fail(LBMIX_EINVAL, "rounding mode is 0 or 1");
+    if (mode == 1 && c->storage != LBMIX_BF16_SHIFTED && c->storage != LBMIX_F16_SHIFTED)
+        return c->fail(LBMIX_EINVAL, "stochastic rounding applies to the 16-bit storage forms");
+    c->rounding = mode;
+    c->round_seed = seed;
+    return LBMIX_OK;
+}
+
+int lbmix_set_storage_range(lbmix_ctx *c, int species, double rel_range) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->allocated) return c->fail(LBMIX_ESTATE, "the storage range is fixed at the first set_state");
+    if (species < 0 || species >= c->ns || !(rel_range > 0.0) || !std::isfinite(rel_range))
+        return c->fail(LBMIX_EINVAL, "bad species or range");
+    c->rel_range[species] = rel_range;
+    c->compute_scales();
     return LBMIX_OK;
 }
 
@@ -709,6 +740,7 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     }
     h.tau_v = c->tau_v; h.tau_d = c->tau_d; h.sc = c->sc; h.drag_from_sc = c->drag_from_sc;
     h.sor_max = c->sor_max; h.sor_check = c->sor_check; h.psi_valid = c->psi_valid && c->psi;
+    h.rounding = c->rounding; h.round_seed = c->round_seed;
     h.lB = c->lB; h.sig_lo = c->sig_lo; h.sig_hi = c->sig_hi;
     for (int d = 0; d < 3; ++d) h.E[d] = c->E[d];
     h.sor_tol = c->sor_tol; h.sor_omega = c->sor_omega; h.steps = c->steps;
@@ -758,6 +790,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     c->compute_scales();
     c->tau_v = h.tau_v; c->tau_d = h.tau_d; c->sc = h.sc; c->drag_from_sc = h.drag_from_sc != 0;
     c->sor_max = h.sor_max; c->sor_check = h.sor_check; c->sor_tol = h.sor_tol; c->sor_omega = h.sor_omega;
+    c->rounding = h.rounding; c->round_seed = h.round_seed;
     c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
     if ((rc = c->hip(hipMemcpyAsync(c->f[c->cur], buf.data(), pop, hipMemcpyHostToDevice, c->stream), "copy f"))) return rc;

@@ -25,7 +25,7 @@ MAX_SPECIES = 4
 EXPORTS = (
     "lbmix_version", "lbmix_create", "lbmix_add_species", "lbmix_set_tau_visc",
     "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics", "lbmix_set_poisson",
-    "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_set_rounding", "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
@@ -71,6 +71,8 @@ def load_library():
         "lbmix_set_schmidt": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_electrostatics": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
         "lbmix_set_poisson": ([vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_rounding": ([vp, ctypes.c_int, ctypes.c_ulonglong], ctypes.c_int),
+        "lbmix_set_storage_range": ([vp, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_step": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_get_moments": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
@@ -176,6 +178,12 @@ class Lattice:
         self._check(self._L.lbmix_set_poisson(self._h, float(rel_tol), int(max_sweeps),
                                               int(check_every), float(omega)))
 
+    def set_rounding(self, stochastic=True, seed=0):
+        self._check(self._L.lbmix_set_rounding(self._h, 1 if stochastic else 0, int(seed)))
+
+    def set_storage_range(self, s, rel_range):
+        self._check(self._L.lbmix_set_storage_range(self._h, int(s), float(rel_range)))
+
     def set_state(self, s, n, u=None):
         n = _f64(n, self.shape)
         uu = None if u is None else _f64(u, (3,) + self.shape)
@@ -247,11 +255,14 @@ class Lattice:
         self._check(self._L.lbmix_load(self._h, str(path).encode()))
 
 
-def from_workload(w, storage="f64", stream=None, poisson=None):
-    """Build a Lattice from a workloads.Workload description (parameters and initial fields)."""
+def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0):
+    """Build a Lattice from a workloads.Workload description (parameters and initial fields).
+    stochastic: rounding of the 16-bit forms (default: stochastic for them)."""
     lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream)
     for s in range(w.nspecies):
         lat.add_species(w.rho0[s], w.valence[s])
+    if storage in ("bf16s", "f16s"):
+        lat.set_rounding(True if stochastic is None else stochastic, seed)
     lat.set_tau_visc(w.tau_visc)
     lat.set_tau_drag(w.tau_drag)
     if w.bjerrum > 0 or any(w.E):

@@ -1,0 +1,144 @@
+"""Reduced-precision storage: errors of the transport coefficients against FP64.
+
+The shifted forms store d_p = f_p - w_p rho0; BF16 and FP16 round stochastically (unbiased)
+by default.  The FP64 run of the GPU library is itself pinned to the oracle (test_gpu_parity),
+so it is the reference here.  Measured on MI355X (the design doc lists the numbers):
+
+* D from a concentration wave (Sec. IV, D = v_T^2 (1/omega_drag - 1/2)) at Sc = 10 and 100;
+* nu from a shear wave (Sec. IV, nu = v_T^2 (1/omega_visc - 1/2));
+* the electro-osmotic velocity at the centre of a charged slit at Sc = 100 (the mobility
+  u_centre / E_x of Sec. IV).
+
+The bar is 1e-3 relative for D and the mobility at Sc <= 100 with FP32 and FP16 storage, and
+2e-3 for BF16 (8 significant bits: its stochastic-rounding noise is 8 times FP16's); nu to
+5e-4.  Plain (unshifted) FP32 storage is shown to stall the slow diffusion mode: the
+per-step change of the populations is below their unit in the last place.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+L = 128
+K = 2 * math.pi / L
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1507_04891_amd as P
+    P.load_library()
+    return P
+
+
+def diffusion(P, storage, sc, stochastic=None):
+    t1, t2 = (300, 6300) if sc <= 10 else (2000, 22000)
+    w = WL.binary_sine(L, 64, 64, amp=1e-3, tau_visc=1.0, sc=sc)
+    lat = P.from_workload(w, storage=storage, stochastic=stochastic, seed=7)
+    basis = np.sin(K * np.arange(L))[None, None, :]
+
+    def amp():
+        n, _ = lat.moments(0)
+        return float(((n - 0.5) * basis).sum())
+
+    lat.step(t1)
+    a1 = amp()
+    lat.step(t2 - t1)
+    a2 = amp()
+    return -math.log(a2 / a1) / (t2 - t1) / K ** 2
+
+
+def viscosity(P, storage):
+    shape = (64, 64, L)
+    u = np.zeros((3,) + shape)
+    u[1] = 1e-3 * np.sin(K * np.arange(L))[None, None, :]
+    w = WL.Workload("shear", L, 64, 64, "periodic", [0.5, 0.5], [0, 0], 0.8,
+                    WL.tau_drag_for_schmidt(0.8, 100.0), [np.full(shape, 0.5)] * 2, [u, u])
+    lat = P.from_workload(w, storage=storage, seed=7)
+    basis = np.sin(K * np.arange(L))[None, None, :]
+
+    def amp():
+        return sum(float((lat.moments(q)[1][1] * basis).sum()) for q in range(2))
+
+    lat.step(100)
+    a1 = amp()
+    lat.step(3000)
+    a2 = amp()
+    return -math.log(a2 / a1) / 3000 / K ** 2
+
+
+_cache = {}
+
+
+def cached(key, fn):
+    if key not in _cache:
+        _cache[key] = fn()
+    return _cache[key]
+
+
+@pytest.mark.parametrize("sc", [10.0, 100.0])
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-3), ("f16s", 1e-3), ("bf16s", 2e-3)])
+def test_diffusion_coefficient_error(P, sc, storage, tol):
+    ref = cached(("D", sc, "f64"), lambda: diffusion(P, "f64", sc))
+    got = diffusion(P, storage, sc)
+    assert abs(got / ref - 1) <= tol, (storage, sc, got, ref)
+
+
+def test_plain_fp32_stalls_slow_diffusion(P):
+    ref = cached(("D", 100.0, "f64"), lambda: diffusion(P, "f64", 100.0))
+    assert abs(diffusion(P, "f32", 100.0) / ref - 1) > 0.5
+    # nearest rounding of FP16 deviations stalls it completely as well
+    assert abs(diffusion(P, "f16s", 100.0, stochastic=False) / ref - 1) > 0.5
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f16s", "bf16s"])
+def test_viscosity_error(P, storage):
+    ref = cached(("nu", "f64"), lambda: viscosity(P, "f64"))
+    assert abs(viscosity(P, storage) / ref - 1) <= 5e-4
+
+
+def mobility(P, storage):
+    w = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
+    lat = P.from_workload(w, storage=storage, seed=7,
+                          poisson=dict(rel_tol=1e-9, max_sweeps=20000, check_every=10))
+    lat.step(28000)
+    acc = None
+    for _ in range(20):
+        lat.step(100)
+        pr = lat.zprofiles()
+        acc = pr if acc is None else acc + pr
+    pr = acc / 20
+    rho = pr[:, 0, 1:-1].sum(0)
+    ux = pr[:, 1, 1:-1].sum(0) / rho
+    return ux[16] / 1e-5
+
+
+@pytest.mark.parametrize("storage,tol", [("f32s", 1e-3), ("f16s", 1e-3), ("bf16s", 2.5e-3)])
+def test_electroosmotic_mobility_error(P, storage, tol):
+    ref = cached(("mob", "f64"), lambda: mobility(P, "f64"))
+    assert abs(mobility(P, storage) / ref - 1) <= tol
+
+
+@pytest.mark.parametrize("storage,eps", [("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)])
+def test_sixteen_bit_parity_with_oracle(P, oracle_mod, storage, eps):
+    """Short run against the oracle: every stored deviation carries a rounding error below
+    one unit in the last place (stochastic) per step; after k steps the populations agree
+    with the FP64 oracle within a few k eps max|f - w rho0|."""
+    from parity_util import W as WQ, oracle_for
+    w = WL.binary_multimode(n=32, amp=1e-2, shear=1e-2, sc=10.0, seed=5)
+    k = 8
+    lat = P.from_workload(w, storage=storage, seed=3)
+    o = oracle_for(oracle_mod, w)
+    lat.step(k)
+    o.step(k)
+    for s in range(2):
+        fo = o.populations(s)
+        dev = np.abs(fo - (WQ * 0.5)[:, None, None, None]).max()
+        err = np.abs(lat.populations(s) - fo).max()
+        assert err <= 2 * k * eps * dev, (storage, s, err, dev)
+        assert err > 0.0
