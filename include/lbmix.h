@@ -139,6 +139,25 @@ int lbmix_set_electrostatics(lbmix_ctx *ctx, double bjerrum, double sigma_lo,
 int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_every,
                       double omega_sor);
 
+/* Poisson solver method: 0 red-black SOR (default); 1 geometric multigrid: cell-centred
+ * V-cycles of red-black Gauss-Seidel (one sweep before and after the correction on the
+ * finest level, two on coarser ones) over a hierarchy that halves each axis while the
+ * colouring stays consistent (coefficients 1 / H^2 per axis, cell-average restriction,
+ * linear interpolation; the levels of at most 2048 cells are cycled by one work-group in
+ * LDS, the coarsest of at most 64 cells solved exactly), each cycle and its residual replayed
+ * as one captured HIP graph.  With multigrid, max_sweeps of
+ * lbmix_set_poisson caps (or, with rel_tol == 0, fixes) the number of V-cycles per solve and
+ * lbmix_stats counts cycles in place of sweeps.  Errors: EINVAL for another method. */
+int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
+
+/* Warm start of each Poisson solve: 0 the previous potential (default); 1 the
+ * extrapolation psi(t-1) + psi(t-2) - psi(t-3), exact for a potential that changes linearly
+ * in time plus an oscillation of period two steps (the interdiffusion flux relaxes with the
+ * factor 1 - omega_drag per step, which is close to -1 at large Schmidt number).  A plain
+ * linear extrapolation 2 psi(t-1) - psi(t-2) triples that oscillation instead.  Errors:
+ * EINVAL. */
+int lbmix_set_poisson_warm_start(lbmix_ctx *ctx, int mode);
+
 /* Rounding of the 16-bit storage forms (LBMIX_BF16_SHIFTED, LBMIX_F16_SHIFTED): mode 0
  * rounds to nearest-even (default); mode 1 rounds stochastically, each stored value going
  * up or down with the probabilities that make its expectation exact, the random bits drawn

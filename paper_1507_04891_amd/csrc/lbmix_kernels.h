@@ -50,6 +50,28 @@ struct PoissonArgs {
     double omega;                    // SOR factor
 };
 
+// One level of the multigrid hierarchy for the Poisson operator: cell-centred grid of
+// nx * ny * nz cells with per-direction coefficients (1 / H_d^2 for spacing H_d relative to the
+// fluid grid); e = correction (the potential itself on level 0), r = right-hand side.
+struct MGLevel {
+    double *e, *r;
+    uint32_t nx, ny, nz;
+    double ax, ay, az;
+    int periodic_z;              // 1: periodic box, 0: zero-flux planes (slit)
+    int fx, fy, fz;              // coarsening factor (1 or 2) towards the next level
+};
+
+constexpr int MG_MAX_BOTTOM = 8;
+constexpr int MG_BOTTOM_LDS = 4096;   // cells of all bottom levels together (LDS, FP64, e and r)
+// The coarse end of the hierarchy, solved by one work-group in LDS: a V-cycle over
+// lev[0..n-1]; only lev[0] refers to global memory (its r in, its e out).
+struct MGBottom {
+    MGLevel lev[MG_MAX_BOTTOM];
+    int n;
+    int coarse_sweeps;
+    const double *coarse_inv;    // dense (A + 1 1^T / m)^-1 of the coarsest level (m cells), or null
+};
+
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
 
@@ -92,6 +114,22 @@ hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *
 //   mode 2: out[nv] = out[2] / N                                (mean of psi).
 hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out,
                            int mode, double K, double lumps, double N, hipStream_t stream);
+
+// Level-0 right-hand side b = -K (q + lump) - mean(b) into r.
+hipError_t launch_make_rhs(const PoissonArgs &a, double *r, hipStream_t stream);
+// One red-black Gauss-Seidel half-sweep of level L.
+hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream);
+// Residual of level F restricted (cell average) into the right-hand side of level C; e of
+// level C set to 0.
+hipError_t launch_mg_restrict(const MGLevel &F, const MGLevel &C, hipStream_t stream);
+// e of level F += trilinear interpolation of e of level C.
+hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t stream);
+// The levels of `b`, solved by one work-group in LDS: V-cycle (2 pre-, 2 post-sweeps) whose
+// coarsest level gets b.coarse_sweeps red-black sweeps; e of b.lev[0] starts at 0 and is
+// written back to global memory.
+hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream);
+// Warm start from the last three solutions: psi <- psi + p1 - p2, p2 <- p1, p1 <- old psi.
+hipError_t launch_extrapolate(double *psi, double *p1, double *p2, uint32_t N, hipStream_t stream);
 
 // psi -= *mean on the fluid nodes.
 hipError_t launch_shift(double *psi, uint32_t N, const double *mean, hipStream_t stream);

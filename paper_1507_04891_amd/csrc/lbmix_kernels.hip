@@ -597,18 +597,23 @@ __global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colou
     a.psi[i] = a.psi[i] + a.omega * (gs - a.psi[i]);
 }
 
+constexpr uint32_t RES_PLANES = 8;   // fluid planes per work-group of the residual kernel
+
 __global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *partials) {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
     if (x < a.nx) {
-        const uint32_t y = blockIdx.y, z = blockIdx.z;
-        const uint32_t i = (z * a.ny + y) * a.nx + x;
-        const Stencil st = neighbours(a, a.psi, x, y, z);
-        const double b = rhs(a, i, z);
-        const double r = b - (st.sum - st.deg * a.psi[i]);
-        v[0] = r * r;
-        v[1] = b * b;
-        v[2] = a.psi[i];
+        const uint32_t y = blockIdx.y;
+        const uint32_t z1 = min(a.nzf, (blockIdx.z + 1) * RES_PLANES);
+        for (uint32_t z = blockIdx.z * RES_PLANES; z < z1; ++z) {
+            const uint32_t i = (z * a.ny + y) * a.nx + x;
+            const Stencil st = neighbours(a, a.psi, x, y, z);
+            const double b = rhs(a, i, z);
+            const double r = b - (st.sum - st.deg * a.psi[i]);
+            v[0] += r * r;
+            v[1] += b * b;
+            v[2] += a.psi[i];
+        }
     }
     const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     block_sum_store<3>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
@@ -620,15 +625,17 @@ __global__ __launch_bounds__(BLOCK) void qsum(const double *q, uint32_t N, doubl
     block_sum_store<1>(v, partials, gridDim.x, blockIdx.x);
 }
 
-__global__ __launch_bounds__(BLOCK) void finalize(const double *partials, uint32_t nb, int nv, double *out,
-                                                 int mode, double K, double lumps, double N) {
-    __shared__ double red[BLOCK];
+constexpr int FIN_BLOCK = 1024;
+
+__global__ __launch_bounds__(FIN_BLOCK) void finalize(const double *partials, uint32_t nb, int nv, double *out,
+                                                     int mode, double K, double lumps, double N) {
+    __shared__ double red[FIN_BLOCK];
     for (int v = 0; v < nv; ++v) {
         double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < nb; b += BLOCK) s += partials[(size_t)v * nb + b];
+        for (uint32_t b = threadIdx.x; b < nb; b += FIN_BLOCK) s += partials[(size_t)v * nb + b];
         red[threadIdx.x] = s;
         __syncthreads();
-        for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        for (int w = FIN_BLOCK / 2; w > 0; w >>= 1) {
             if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
@@ -639,6 +646,217 @@ __global__ __launch_bounds__(BLOCK) void finalize(const double *partials, uint32
         if (mode == 1) out[nv] = -K * (out[0] + lumps) / N;
         if (mode == 2) out[nv] = out[2] / N;
     }
+}
+
+__global__ __launch_bounds__(BLOCK) void make_rhs(const PoissonArgs a, double *r) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= a.nx) return;
+    const uint32_t i = (blockIdx.z * a.ny + blockIdx.y) * a.nx + x;
+    r[i] = rhs(a, i, blockIdx.z);
+}
+
+// ---------------------------------------------------------------------------------------
+// Geometric multigrid for the same operator (cell-centred, V-cycles).  On a level with
+// spacings H_d the equation reads sum_d a_d (e_{+d} + e_{-d} - 2 e) = r, a_d = 1 / H_d^2, with
+// periodic x, y, periodic or zero-flux z (a missing neighbour drops its term).
+
+struct MGNb {
+    double sum, diag;
+};
+
+__device__ inline MGNb mg_nb(const MGLevel &L, const double *e, uint32_t x, uint32_t y, uint32_t z) {
+    double s = 0.0, dg = 0.0;
+    if (L.nx > 1) {
+        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1, xp = x + 1 == L.nx ? 0 : x + 1;
+        s += L.ax * (e[(z * L.ny + y) * L.nx + xp] + e[(z * L.ny + y) * L.nx + xm]);
+        dg += 2.0 * L.ax;
+    }
+    if (L.ny > 1) {
+        const uint32_t ym = y == 0 ? L.ny - 1 : y - 1, yp = y + 1 == L.ny ? 0 : y + 1;
+        s += L.ay * (e[(z * L.ny + yp) * L.nx + x] + e[(z * L.ny + ym) * L.nx + x]);
+        dg += 2.0 * L.ay;
+    }
+    if (L.nz > 1) {
+        if (L.periodic_z) {
+            const uint32_t zm = z == 0 ? L.nz - 1 : z - 1, zp = z + 1 == L.nz ? 0 : z + 1;
+            s += L.az * (e[(zp * L.ny + y) * L.nx + x] + e[(zm * L.ny + y) * L.nx + x]);
+            dg += 2.0 * L.az;
+        } else {
+            if (z + 1 < L.nz) { s += L.az * e[((z + 1) * L.ny + y) * L.nx + x]; dg += L.az; }
+            if (z > 0) { s += L.az * e[((z - 1) * L.ny + y) * L.nx + x]; dg += L.az; }
+        }
+    }
+    return {s, dg};
+}
+
+__global__ __launch_bounds__(BLOCK) void mg_smooth(const MGLevel L, int colour) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= L.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    if (((x + y + z) & 1u) != (uint32_t)colour) return;
+    const uint32_t i = (z * L.ny + y) * L.nx + x;
+    const MGNb nb = mg_nb(L, L.e, x, y, z);
+    if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
+}
+
+// one thread per coarse cell: average of the fine residuals of its children
+__global__ __launch_bounds__(BLOCK) void mg_restrict(const MGLevel F, const MGLevel C) {
+    const uint32_t X = blockIdx.x * blockDim.x + threadIdx.x;
+    if (X >= C.nx) return;
+    const uint32_t Y = blockIdx.y, Z = blockIdx.z;
+    double acc = 0.0;
+    for (int k = 0; k < F.fz; ++k)
+        for (int j = 0; j < F.fy; ++j)
+            for (int i = 0; i < F.fx; ++i) {
+                const uint32_t x = X * F.fx + i, y = Y * F.fy + j, z = Z * F.fz + k;
+                const uint32_t fi = (z * F.ny + y) * F.nx + x;
+                const MGNb nb = mg_nb(F, F.e, x, y, z);
+                acc += F.r[fi] - (nb.sum - nb.diag * F.e[fi]);
+            }
+    const uint32_t ci = (Z * C.ny + Y) * C.nx + X;
+    C.r[ci] = acc / double(F.fx * F.fy * F.fz);
+    C.e[ci] = 0.0;
+}
+
+// cell-centred linear interpolation along each coarsened axis: weights 3/4 (own coarse
+// cell) and 1/4 (the coarse neighbour on the side of the fine cell); a zero-flux boundary
+// reflects (the neighbour is the cell itself), a periodic one wraps
+__device__ inline void lin1(uint32_t f, int factor, uint32_t nc, bool periodic, uint32_t &c0, uint32_t &c1,
+                            double &w0) {
+    if (factor == 1) { c0 = c1 = f; w0 = 1.0; return; }
+    c0 = f >> 1;
+    const bool lo = (f & 1u) == 0;
+    if (lo) c1 = c0 == 0 ? (periodic ? nc - 1 : 0) : c0 - 1;
+    else c1 = c0 + 1 == nc ? (periodic ? 0 : c0) : c0 + 1;
+    w0 = 0.75;
+}
+
+__global__ __launch_bounds__(BLOCK) void mg_prolong(const MGLevel F, const MGLevel C) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= F.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    uint32_t xa, xb, ya, yb, za, zb;
+    double wx, wy, wz;
+    lin1(x, F.fx, C.nx, true, xa, xb, wx);
+    lin1(y, F.fy, C.ny, true, ya, yb, wy);
+    lin1(z, F.fz, C.nz, F.periodic_z != 0, za, zb, wz);
+    const double *e = C.e;
+    auto at = [&](uint32_t i, uint32_t j, uint32_t k) { return e[(k * C.ny + j) * C.nx + i]; };
+    const double v = wz * (wy * (wx * at(xa, ya, za) + (1 - wx) * at(xb, ya, za)) +
+                           (1 - wy) * (wx * at(xa, yb, za) + (1 - wx) * at(xb, yb, za))) +
+                     (1 - wz) * (wy * (wx * at(xa, ya, zb) + (1 - wx) * at(xb, ya, zb)) +
+                                 (1 - wy) * (wx * at(xa, yb, zb) + (1 - wx) * at(xb, yb, zb)));
+    F.e[(z * F.ny + y) * F.nx + x] += v;
+}
+
+// The coarse end of the hierarchy in one work-group: every sweep, restriction and
+// interpolation of the small levels is a loop over cells with barriers between phases.
+__device__ void blk_smooth(const MGLevel &L, int colour) {
+    const uint32_t n = L.nx * L.ny * L.nz;
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const uint32_t x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
+        if (((x + y + z) & 1u) != (uint32_t)colour) continue;
+        const MGNb nb = mg_nb(L, L.e, x, y, z);
+        if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
+    }
+    __syncthreads();
+}
+
+// View of bottom level l in LDS (offsets from the sizes of the levels above it); built from
+// the kernel arguments on demand, so no level table is indexed at run time in private memory.
+__device__ inline MGLevel bottom_view(const MGBottom &b, int l, double *se, double *sr) {
+    uint32_t off = 0;
+    for (int k = 0; k < l; ++k) off += b.lev[k].nx * b.lev[k].ny * b.lev[k].nz;
+    MGLevel v = b.lev[l];
+    v.e = se + off;
+    v.r = sr + off;
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void mg_bottom(const MGBottom b) {
+    __shared__ double se[MG_BOTTOM_LDS], sr[MG_BOTTOM_LDS];
+    {
+        const uint32_t n0 = b.lev[0].nx * b.lev[0].ny * b.lev[0].nz;
+        for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) {
+            se[i] = 0.0;
+            sr[i] = b.lev[0].r[i];
+        }
+        __syncthreads();
+    }
+    for (int l = 0; l < b.n; ++l) {
+        const MGLevel L = bottom_view(b, l, se, sr);
+        if (l > 0) {   // restrict the residual of level l-1 into level l, e = 0
+            const MGLevel F = bottom_view(b, l - 1, se, sr);
+            const uint32_t n = L.nx * L.ny * L.nz;
+            for (uint32_t ci = threadIdx.x; ci < n; ci += blockDim.x) {
+                const uint32_t X = ci % L.nx, Y = (ci / L.nx) % L.ny, Z = ci / (L.nx * L.ny);
+                double acc = 0.0;
+                for (int k = 0; k < F.fz; ++k)
+                    for (int j = 0; j < F.fy; ++j)
+                        for (int i = 0; i < F.fx; ++i) {
+                            const uint32_t x = X * F.fx + i, y = Y * F.fy + j, z = Z * F.fz + k;
+                            const uint32_t fi = (z * F.ny + y) * F.nx + x;
+                            const MGNb nb = mg_nb(F, F.e, x, y, z);
+                            acc += F.r[fi] - (nb.sum - nb.diag * F.e[fi]);
+                        }
+                L.r[ci] = acc / double(F.fx * F.fy * F.fz);
+                L.e[ci] = 0.0;
+            }
+            __syncthreads();
+        }
+        if (l == b.n - 1 && b.coarse_inv) {
+            // exact coarsest solve: (A + 1 1^T / m) e = r gives the zero-mean solution of a
+            // consistent r (and absorbs the rounding of its mean)
+            const uint32_t m = L.nx * L.ny * L.nz;
+            double acc = 0.0;
+            if (threadIdx.x < m)
+                for (uint32_t j = 0; j < m; ++j) acc += b.coarse_inv[threadIdx.x * m + j] * L.r[j];
+            __syncthreads();
+            if (threadIdx.x < m) L.e[threadIdx.x] = acc;
+            __syncthreads();
+            continue;
+        }
+        const int sweeps = (l == b.n - 1) ? b.coarse_sweeps : 2;
+        for (int k = 0; k < sweeps; ++k) {
+            blk_smooth(L, 0);
+            blk_smooth(L, 1);
+        }
+    }
+    for (int l = b.n - 2; l >= 0; --l) {
+        const MGLevel F = bottom_view(b, l, se, sr), C = bottom_view(b, l + 1, se, sr);
+        const uint32_t n = F.nx * F.ny * F.nz;
+        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint32_t x = i % F.nx, y = (i / F.nx) % F.ny, z = i / (F.nx * F.ny);
+            uint32_t xa, xb, ya, yb, za, zb;
+            double wx, wy, wz;
+            lin1(x, F.fx, C.nx, true, xa, xb, wx);
+            lin1(y, F.fy, C.ny, true, ya, yb, wy);
+            lin1(z, F.fz, C.nz, F.periodic_z != 0, za, zb, wz);
+            auto at = [&](uint32_t ii, uint32_t jj, uint32_t kk) { return C.e[(kk * C.ny + jj) * C.nx + ii]; };
+            F.e[i] += wz * (wy * (wx * at(xa, ya, za) + (1 - wx) * at(xb, ya, za)) +
+                            (1 - wy) * (wx * at(xa, yb, za) + (1 - wx) * at(xb, yb, za))) +
+                      (1 - wz) * (wy * (wx * at(xa, ya, zb) + (1 - wx) * at(xb, ya, zb)) +
+                                  (1 - wy) * (wx * at(xa, yb, zb) + (1 - wx) * at(xb, yb, zb)));
+        }
+        __syncthreads();
+        for (int k = 0; k < 2; ++k) {
+            blk_smooth(F, 0);
+            blk_smooth(F, 1);
+        }
+    }
+    const uint32_t n0 = b.lev[0].nx * b.lev[0].ny * b.lev[0].nz;
+    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) b.lev[0].e[i] = se[i];
+}
+
+// psi <- psi + p1 - p2 (p1, p2 = the two previous solutions), then p2 <- p1, p1 <- psi_old:
+// exact for a linear trend plus an oscillation of period two steps
+__global__ __launch_bounds__(BLOCK) void extrapolate(double *psi, double *p1, double *p2, uint32_t N) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double a = psi[i], b = p1[i];
+    psi[i] = a + b - p2[i];
+    p2[i] = b;
+    p1[i] = a;
 }
 
 __global__ __launch_bounds__(BLOCK) void shift(double *psi, uint32_t N, const double *mean) {
@@ -798,7 +1016,7 @@ hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream) {
 
 hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb, hipStream_t stream) {
     dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    const dim3 g = node_grid(a.nx, a.ny, (a.nzf + RES_PLANES - 1) / RES_PLANES, &b);
     *nb = g.x * g.y * g.z;
     hipLaunchKernelGGL(residual, g, b, 0, stream, a, partials);
     return hipGetLastError();
@@ -812,7 +1030,40 @@ hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *
 
 hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out, int mode, double K,
                            double lumps, double N, hipStream_t stream) {
-    hipLaunchKernelGGL(finalize, dim3(1), dim3(BLOCK), 0, stream, partials, nblocks, nv, out, mode, K, lumps, N);
+    hipLaunchKernelGGL(finalize, dim3(1), dim3(FIN_BLOCK), 0, stream, partials, nblocks, nv, out, mode, K, lumps, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_make_rhs(const PoissonArgs &a, double *r, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    hipLaunchKernelGGL(make_rhs, g, b, 0, stream, a, r);
+    return hipGetLastError();
+}
+hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(L.nx, L.ny, L.nz, &b);
+    hipLaunchKernelGGL(mg_smooth, g, b, 0, stream, L, colour);
+    return hipGetLastError();
+}
+hipError_t launch_mg_restrict(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(C.nx, C.ny, C.nz, &b);
+    hipLaunchKernelGGL(mg_restrict, g, b, 0, stream, F, C);
+    return hipGetLastError();
+}
+hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(F.nx, F.ny, F.nz, &b);
+    hipLaunchKernelGGL(mg_prolong, g, b, 0, stream, F, C);
+    return hipGetLastError();
+}
+hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream) {
+    hipLaunchKernelGGL(mg_bottom, dim3(1), dim3(1024), 0, stream, b);
+    return hipGetLastError();
+}
+hipError_t launch_extrapolate(double *psi, double *p1, double *p2, uint32_t N, hipStream_t stream) {
+    hipLaunchKernelGGL(extrapolate, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, psi, p1, p2, N);
     return hipGetLastError();
 }
 

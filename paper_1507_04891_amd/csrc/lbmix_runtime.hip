@@ -45,6 +45,11 @@ struct lbmix_ctx {
     bool drag_from_sc = true;
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
+    int poisson_method = 0;           // 0 red-black SOR, 1 multigrid V(2,2) cycles
+    int warm_start = 0;               // 0 previous potential, 1 linear extrapolation in time
+    double *psi_prev = nullptr;       // two previous solutions (warm_start 1)
+    int have_prev = 0;
+    int mg_last = 0;                  // V-cycles of the last multigrid solve
     int rounding = 0;                 // 16-bit forms: 0 nearest-even, 1 stochastic
     unsigned long long round_seed = 0;
     int sor_max = 200000, sor_check = 10;
@@ -62,6 +67,13 @@ struct lbmix_ctx {
     double *hred = nullptr;           // pinned host mirror
     double *scratch = nullptr;        // readback staging
     size_t scratch_cap = 0;
+    // multigrid: level 0 is (psi, b); coarser levels own their arrays
+    std::vector<MGLevel> mg;
+    double *mg_b = nullptr;
+    double *mg_cinv = nullptr;        // exact inverse of the coarsest level (<= 64 cells)
+    hipStream_t cap_stream = nullptr;  // capture-only stream (graphs replay on `stream`)
+    hipGraph_t vgraph = nullptr;
+    hipGraphExec_t vexec = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
     // state
     bool allocated = false, started = false, psi_valid = false;
@@ -186,6 +198,14 @@ struct lbmix_ctx {
 
 namespace {
 
+// A captured V-cycle holds the Poisson arguments by value; drop it when they change.
+void drop_graph(lbmix_ctx *c) {
+    if (c->vexec) (void)hipGraphExecDestroy(c->vexec);
+    if (c->vgraph) (void)hipGraphDestroy(c->vgraph);
+    c->vexec = nullptr;
+    c->vgraph = nullptr;
+}
+
 int ensure_scratch(lbmix_ctx *c, size_t bytes) {
     if (c->scratch_cap >= bytes) return LBMIX_OK;
     if (c->scratch) (void)hipFree(c->scratch);
@@ -255,7 +275,220 @@ int residual(lbmix_ctx *c, const PoissonArgs &pa) {
                   "finalize(residual)");
 }
 
+// ---- multigrid -------------------------------------------------------------------------
+
+// sweeps before / after the coarse-grid correction: one on the finest level (the costly
+// one), two on the coarser grid levels
+constexpr int kPre0 = 1, kPost0 = 1, kPre = 2, kPost = 2;
+
+int mg_build(lbmix_ctx *c) {
+    if (!c->mg.empty()) return LBMIX_OK;
+    int rc = c->hip(hipMalloc((void **)&c->mg_b, (size_t)c->Nf * sizeof(double)), "hipMalloc(mg)");
+    if (rc) return rc;
+    MGLevel L{};
+    L.e = c->psi;
+    L.r = c->mg_b;
+    L.nx = c->nx;
+    L.ny = c->ny;
+    L.nz = c->nzf;
+    L.ax = L.ay = L.az = 1.0;
+    L.periodic_z = c->slit ? 0 : 1;
+    double hx = 1.0, hy = 1.0, hz = 1.0;
+    for (;;) {
+        // a periodic axis halves while the red-black colouring stays consistent (even size
+        // after halving, or one cell); a zero-flux axis halves while its size is even
+        auto per_ok = [](uint32_t n) { return n >= 2 && n % 2 == 0 && ((n / 2) % 2 == 0 || n == 2); };
+        auto neu_ok = [](uint32_t n) { return n >= 2 && n % 2 == 0; };
+        L.fx = per_ok(L.nx) ? 2 : 1;
+        L.fy = per_ok(L.ny) ? 2 : 1;
+        L.fz = (L.periodic_z ? per_ok(L.nz) : neu_ok(L.nz)) ? 2 : 1;
+        const bool last = (L.fx == 1 && L.fy == 1 && L.fz == 1) || (size_t)L.nx * L.ny * L.nz <= 64;
+        if (last) L.fx = L.fy = L.fz = 1;
+        c->mg.push_back(L);
+        if (last) break;
+        MGLevel C{};
+        C.nx = L.nx / L.fx;
+        C.ny = L.ny / L.fy;
+        C.nz = L.nz / L.fz;
+        hx *= L.fx;
+        hy *= L.fy;
+        hz *= L.fz;
+        C.ax = 1.0 / (hx * hx);
+        C.ay = 1.0 / (hy * hy);
+        C.az = 1.0 / (hz * hz);
+        C.periodic_z = L.periodic_z;
+        const size_t n = (size_t)C.nx * C.ny * C.nz;
+        if ((rc = c->hip(hipMalloc((void **)&C.e, n * sizeof(double)), "hipMalloc(mg)"))) return rc;
+        if ((rc = c->hip(hipMalloc((void **)&C.r, n * sizeof(double)), "hipMalloc(mg)"))) return rc;
+        L = C;
+    }
+    // exact coarsest solve: invert A + 1 1^T / m (A: the level's operator, m <= 64 cells) by
+    // Gauss-Jordan elimination with partial pivoting in FP64
+    const MGLevel &B = c->mg.back();
+    const int m = (int)(B.nx * B.ny * B.nz);
+    if (c->mg.size() >= 2 && m <= 64) {
+        std::vector<double> A((size_t)m * m, 0.0), I((size_t)m * m, 0.0);
+        auto id = [&](int x, int y, int z) { return (z * (int)B.ny + y) * (int)B.nx + x; };
+        for (int z = 0; z < (int)B.nz; ++z)
+            for (int y = 0; y < (int)B.ny; ++y)
+                for (int x = 0; x < (int)B.nx; ++x) {
+                    const int i = id(x, y, z);
+                    auto link = [&](int j, double a) { A[(size_t)i * m + j] += a; A[(size_t)i * m + i] -= a; };
+                    if (B.nx > 1) {
+                        link(id((x + 1) % B.nx, y, z), B.ax);
+                        link(id((x + B.nx - 1) % B.nx, y, z), B.ax);
+                    }
+                    if (B.ny > 1) {
+                        link(id(x, (y + 1) % B.ny, z), B.ay);
+                        link(id(x, (y + B.ny - 1) % B.ny, z), B.ay);
+                    }
+                    if (B.nz > 1) {
+                        if (B.periodic_z) {
+                            link(id(x, y, (z + 1) % B.nz), B.az);
+                            link(id(x, y, (z + B.nz - 1) % B.nz), B.az);
+                        } else {
+                            if (z + 1 < (int)B.nz) link(id(x, y, z + 1), B.az);
+                            if (z > 0) link(id(x, y, z - 1), B.az);
+                        }
+                    }
+                }
+        for (int i = 0; i < m; ++i) {
+            for (int j = 0; j < m; ++j) A[(size_t)i * m + j] += 1.0 / m;
+            I[(size_t)i * m + i] = 1.0;
+        }
+        bool ok = true;
+        for (int col = 0; col < m && ok; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < m; ++r)
+                if (std::fabs(A[(size_t)r * m + col]) > std::fabs(A[(size_t)piv * m + col])) piv = r;
+            if (std::fabs(A[(size_t)piv * m + col]) < 1e-12) { ok = false; break; }
+            for (int j = 0; j < m; ++j) {
+                std::swap(A[(size_t)col * m + j], A[(size_t)piv * m + j]);
+                std::swap(I[(size_t)col * m + j], I[(size_t)piv * m + j]);
+            }
+            const double d = A[(size_t)col * m + col];
+            for (int j = 0; j < m; ++j) {
+                A[(size_t)col * m + j] /= d;
+                I[(size_t)col * m + j] /= d;
+            }
+            for (int r = 0; r < m; ++r) {
+                if (r == col) continue;
+                const double f = A[(size_t)r * m + col];
+                if (f == 0.0) continue;
+                for (int j = 0; j < m; ++j) {
+                    A[(size_t)r * m + j] -= f * A[(size_t)col * m + j];
+                    I[(size_t)r * m + j] -= f * I[(size_t)col * m + j];
+                }
+            }
+        }
+        if (ok) {
+            if ((rc = c->hip(hipMalloc((void **)&c->mg_cinv, (size_t)m * m * sizeof(double)), "hipMalloc(mg)")))
+                return rc;
+            if ((rc = c->hip(hipMemcpy(c->mg_cinv, I.data(), (size_t)m * m * sizeof(double), hipMemcpyHostToDevice),
+                             "copy coarse inverse")))
+                return rc;
+        }
+    }
+    return LBMIX_OK;
+}
+
+// One V(2,2) cycle on level 0 (psi, b), then the residual norms of the result.  The levels
+// from the first one of at most kBottomCells cells down are solved by one work-group in LDS
+// (their cells together must fit MG_BOTTOM_LDS).
+constexpr size_t kBottomCells = 2048;
+
+int mg_vcycle(lbmix_ctx *c, const PoissonArgs &pa, hipStream_t st) {
+    const int nl = (int)c->mg.size();
+    // levels [0, lb) run as grid kernels, levels [lb, nl) inside one work-group; a hierarchy
+    // of one level (no axis could be halved) is plain red-black Gauss-Seidel
+    int lb = nl;
+    for (int l = 1; l < nl; ++l)
+        if ((size_t)c->mg[l].nx * c->mg[l].ny * c->mg[l].nz <= kBottomCells) { lb = l; break; }
+    auto bottom_fits = [&](int from) {
+        size_t cells = 0;
+        for (int l = from; l < nl; ++l) cells += (size_t)c->mg[l].nx * c->mg[l].ny * c->mg[l].nz;
+        return nl - from <= MG_MAX_BOTTOM && cells <= (size_t)MG_BOTTOM_LDS;
+    };
+    while (lb < nl && !bottom_fits(lb)) ++lb;   // a bottom that does not fit stays on the grid
+    int rc;
+    for (int l = 0; l < lb; ++l) {
+        for (int k = 0; k < (l == 0 ? kPre0 : kPre); ++k)
+            for (int col = 0; col < 2; ++col)
+                if ((rc = c->hip(launch_mg_smooth(c->mg[l], col, st), "mg_smooth"))) return rc;
+        if (l + 1 < nl && (rc = c->hip(launch_mg_restrict(c->mg[l], c->mg[l + 1], st), "mg_restrict")))
+            return rc;
+    }
+    if (lb == nl) {   // no bottom solve: the coarsest grid level gets many sweeps
+        const MGLevel &B = c->mg[nl - 1];
+        const int sweeps = nl == 1 ? 0 : std::max(20, 4 * (int)std::max(B.nx, std::max(B.ny, B.nz)));
+        for (int k = 0; k < sweeps; ++k)
+            for (int col = 0; col < 2; ++col)
+                if ((rc = c->hip(launch_mg_smooth(B, col, st), "mg_smooth"))) return rc;
+    }
+    if (lb < nl) {
+        MGBottom bb{};
+        bb.n = nl - lb;
+        for (int l = lb; l < nl; ++l) bb.lev[l - lb] = c->mg[l];
+        const MGLevel &B = c->mg[nl - 1];
+        bb.coarse_sweeps = std::max(20, 4 * (int)std::max(B.nx, std::max(B.ny, B.nz)));
+        bb.coarse_inv = c->mg_cinv;
+        if ((rc = c->hip(launch_mg_bottom(bb, st), "mg_bottom"))) return rc;
+    }
+    for (int l = lb - 1; l >= 0; --l) {
+        if (l + 1 < nl && (rc = c->hip(launch_mg_prolong(c->mg[l], c->mg[l + 1], st), "mg_prolong"))) return rc;
+        for (int k = 0; k < (l == 0 ? kPost0 : kPost); ++k)
+            for (int col = 0; col < 2; ++col)
+                if ((rc = c->hip(launch_mg_smooth(c->mg[l], col, st), "mg_smooth"))) return rc;
+    }
+    uint32_t nb = 0;
+    if ((rc = c->hip(launch_residual(pa, c->partials, &nb, st), "residual"))) return rc;
+    return c->hip(launch_finalize(c->partials, nb, 3, c->dred + 4, 2, 0.0, 0.0, (double)c->Nf, st),
+                  "finalize(residual)");
+}
+
+// The V-cycle and its residual as one graph, captured once and replayed on the context stream.
+int mg_cycle(lbmix_ctx *c, const PoissonArgs &pa) {
+    int rc;
+    if (!c->vexec) {
+        if (!c->cap_stream &&
+            (rc = c->hip(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate")))
+            return rc;
+        if ((rc = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture")))
+            return rc;
+        const int r1 = mg_vcycle(c, pa, c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (r1) {
+            if (g) (void)hipGraphDestroy(g);
+            return r1;
+        }
+        if ((rc = c->hip(e, "hipStreamEndCapture"))) return rc;
+        c->vgraph = g;
+        if ((rc = c->hip(hipGraphInstantiate(&c->vexec, c->vgraph, nullptr, nullptr, 0), "hipGraphInstantiate")))
+            return rc;
+    }
+    return c->hip(hipGraphLaunch(c->vexec, c->stream), "hipGraphLaunch");
+}
+
 // Poisson solve of the charge in c->q into c->psi (warm start), then zero-mean gauge.
+int finish_zero_rhs(lbmix_ctx *c) {   // b == 0: the solution is psi = 0
+    int rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
+    if (rc) return rc;
+    c->last_resid = 0.0;
+    c->last_sweeps = 0;
+    c->last_status = LBMIX_OK;
+    c->resid_on_device = false;
+    c->solves++;
+    c->psi_valid = true;
+    return LBMIX_OK;
+}
+
+// Relative residual from the norms in dred[4..5] (fetched), or -1 when b == 0.
+double fetched_residual(lbmix_ctx *c) {
+    const double r2 = c->hred[4], b2 = c->hred[5];
+    return b2 == 0.0 ? -1.0 : std::sqrt(r2 / b2);
+}
+
 int solve(lbmix_ctx *c) {
     uint32_t nb = 0;
     const double lumps = c->slit ? (c->sig_lo + c->sig_hi) * (double)c->nx * c->ny : 0.0;
@@ -265,55 +498,103 @@ int solve(lbmix_ctx *c) {
                 "finalize(qsum)");
     if (rc) return rc;
     const PoissonArgs pa = c->pargs();
-    int sweeps = 0, status = LBMIX_OK;
-    auto sweep = [&](int count) -> int {
-        for (int k = 0; k < count; ++k) {
-            int r = c->hip(launch_sor(pa, 0, c->stream), "sor(red)");
-            if (r) return r;
-            r = c->hip(launch_sor(pa, 1, c->stream), "sor(black)");
-            if (r) return r;
+    // warm start: the previous potential, or psi(t-1) + psi(t-2) - psi(t-3) once three
+    // solutions exist (exact for a linear trend plus a period-two oscillation in time)
+    if (c->warm_start == 1 && c->psi_valid) {
+        const size_t bytes = (size_t)c->Nf * sizeof(double);
+        if (!c->psi_prev) {
+            if ((rc = c->hip(hipMalloc((void **)&c->psi_prev, 2 * bytes), "hipMalloc(psi_prev)"))) return rc;
+            c->have_prev = 0;
         }
-        return LBMIX_OK;
-    };
-    if (c->sor_tol > 0.0) {
-        for (;;) {
-            if ((rc = residual(c, pa))) return rc;
-            if ((rc = fetch(c, 8))) return rc;
-            const double r2 = c->hred[4], b2 = c->hred[5];
-            if (b2 == 0.0) {
-                rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
-                if (rc) return rc;
-                c->last_resid = 0.0;
-                c->last_sweeps = 0;
-                c->last_status = LBMIX_OK;
-                c->resid_on_device = false;
-                c->solves++;
-                c->psi_valid = true;
-                return LBMIX_OK;
-            }
-            c->last_resid = std::sqrt(r2 / b2);
-            if (c->last_resid <= c->sor_tol) break;
-            if (sweeps >= c->sor_max) {
-                status = LBMIX_ENOCONV;
-                break;
-            }
-            const int todo = std::min(c->sor_check, c->sor_max - sweeps);
-            if ((rc = sweep(todo))) return rc;
-            sweeps += todo;
+        double *p1 = c->psi_prev, *p2 = c->psi_prev + c->Nf;
+        if (c->have_prev >= 2) {
+            if ((rc = c->hip(launch_extrapolate(c->psi, p1, p2, c->Nf, c->stream), "extrapolate"))) return rc;
+        } else {
+            // history not complete: shift it, keep the previous potential as the guess
+            if (c->have_prev == 1 &&
+                (rc = c->hip(hipMemcpyAsync(p2, p1, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi")))
+                return rc;
+            if ((rc = c->hip(hipMemcpyAsync(p1, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi")))
+                return rc;
+            c->have_prev++;
         }
-        c->resid_on_device = false;
+    }
+    int work = 0, status = LBMIX_OK;
+    if (c->poisson_method == 1) {
+        // multigrid: each V-cycle is one graph replay that also leaves the residual norms of
+        // its result in dred[4..7]; the first (previous count - 1) cycles run without reading
+        // them back, since they are expected to be needed
+        if ((rc = mg_build(c))) return rc;
+        if ((rc = c->hip(launch_make_rhs(pa, c->mg_b, c->stream), "make_rhs"))) return rc;
+        if (c->sor_tol > 0.0) {
+            const int blind = std::min(std::max(0, c->mg_last - 1), c->sor_max);
+            double res;
+            if (blind == 0) {
+                if ((rc = residual(c, pa)) || (rc = fetch(c, 8))) return rc;
+            } else {
+                for (int k = 0; k < blind; ++k)
+                    if ((rc = mg_cycle(c, pa))) return rc;
+                work = blind;
+                if ((rc = fetch(c, 8))) return rc;
+            }
+            res = fetched_residual(c);
+            if (res < 0.0) return finish_zero_rhs(c);
+            while (res > c->sor_tol) {
+                if (work >= c->sor_max) {
+                    status = LBMIX_ENOCONV;
+                    break;
+                }
+                if ((rc = mg_cycle(c, pa)) || (rc = fetch(c, 8))) return rc;
+                ++work;
+                res = fetched_residual(c);
+            }
+            c->last_resid = res;
+            c->mg_last = work;
+            c->resid_on_device = false;
+        } else {
+            for (int k = 0; k < c->sor_max; ++k)
+                if ((rc = mg_cycle(c, pa))) return rc;
+            work = c->sor_max;
+            c->resid_on_device = true;
+        }
     } else {
-        if ((rc = sweep(c->sor_max))) return rc;
-        sweeps = c->sor_max;
-        if ((rc = residual(c, pa))) return rc;
-        c->resid_on_device = true;
+        auto sweeps = [&](int count) -> int {
+            for (int k = 0; k < count; ++k) {
+                int r = c->hip(launch_sor(pa, 0, c->stream), "sor(red)");
+                if (r) return r;
+                if ((r = c->hip(launch_sor(pa, 1, c->stream), "sor(black)"))) return r;
+            }
+            return LBMIX_OK;
+        };
+        if (c->sor_tol > 0.0) {
+            for (;;) {
+                if ((rc = residual(c, pa)) || (rc = fetch(c, 8))) return rc;
+                const double res = fetched_residual(c);
+                if (res < 0.0) return finish_zero_rhs(c);
+                c->last_resid = res;
+                if (res <= c->sor_tol) break;
+                if (work >= c->sor_max) {
+                    status = LBMIX_ENOCONV;
+                    break;
+                }
+                const int todo = std::min(c->sor_check, c->sor_max - work);
+                if ((rc = sweeps(todo))) return rc;
+                work += todo;
+            }
+            c->resid_on_device = false;
+        } else {
+            if ((rc = sweeps(c->sor_max))) return rc;
+            work = c->sor_max;
+            if ((rc = residual(c, pa))) return rc;
+            c->resid_on_device = true;
+        }
     }
     // zero-mean gauge with the mean of the final psi (dred[7])
     rc = c->hip(launch_shift(c->psi, c->Nf, c->dred + 7, c->stream), "shift(psi)");
     if (rc) return rc;
-    c->last_sweeps = sweeps;
+    c->last_sweeps = work;
     c->last_status = status;
-    c->total_sweeps += sweeps;
+    c->total_sweeps += work;
     c->solves++;
     c->psi_valid = true;
     return status;
@@ -372,7 +653,7 @@ struct Header {
     int32_t version, nx, ny, nz, geometry, storage, ns, valence[MAXS];
     double rho0[MAXS], rel_range[MAXS], host_total[MAXS];
     double tau_v, tau_d, sc;
-    int32_t drag_from_sc, sor_max, sor_check, psi_valid, rounding, pad_;
+    int32_t drag_from_sc, sor_max, sor_check, psi_valid, rounding, poisson_method;
     uint64_t round_seed;
     double lB, sig_lo, sig_hi, E[3], sor_tol, sor_omega;
     int64_t steps;
@@ -469,6 +750,7 @@ int lbmix_set_electrostatics(lbmix_ctx *c, double bjerrum, double sigma_lo, doub
     if (E)
         for (int d = 0; d < 3; ++d)
             if (!std::isfinite(E[d])) return c->fail(LBMIX_EINVAL, "bad field");
+    drop_graph(c);
     c->lB = bjerrum;
     c->sig_lo = sigma_lo;
     c->sig_hi = sigma_hi;
@@ -481,10 +763,27 @@ int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_ev
     if (!c) return LBMIX_EINVAL;
     if (!(rel_tol >= 0.0) || max_sweeps < 1 || check_every < 1 || !(omega_sor < 2.0))
         return c->fail(LBMIX_EINVAL, "bad Poisson parameters");
+    drop_graph(c);
     c->sor_tol = rel_tol;
     c->sor_max = max_sweeps;
     c->sor_check = check_every;
     c->sor_omega = omega_sor;
+    return LBMIX_OK;
+}
+
+int lbmix_set_poisson_method(lbmix_ctx *c, int method) {
+    if (!c) return LBMIX_EINVAL;
+    if (method != 0 && method != 1) return c->fail(LBMIX_EINVAL, "Poisson method is 0 (SOR) or 1 (multigrid)");
+    drop_graph(c);
+    c->poisson_method = method;
+    return LBMIX_OK;
+}
+
+int lbmix_set_poisson_warm_start(lbmix_ctx *c, int mode) {
+    if (!c) return LBMIX_EINVAL;
+    if (mode != 0 && mode != 1) return c->fail(LBMIX_EINVAL, "warm start is 0 (previous) or 1 (extrapolated)");
+    c->warm_start = mode;
+    c->have_prev = 0;
     return LBMIX_OK;
 }
 
@@ -540,6 +839,8 @@ int lbmix_set_state(lbmix_ctx *c, int s, const double *n, const double *u) {
     if (du) (void)hipFree(du);
     if (rc) return rc;
     c->host_total[s] = tot;
+    c->have_prev = 0;
+    c->mg_last = 0;
     c->set[s] = true;
     c->started = false;
     c->psi_valid = false;
@@ -740,7 +1041,7 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     }
     h.tau_v = c->tau_v; h.tau_d = c->tau_d; h.sc = c->sc; h.drag_from_sc = c->drag_from_sc;
     h.sor_max = c->sor_max; h.sor_check = c->sor_check; h.psi_valid = c->psi_valid && c->psi;
-    h.rounding = c->rounding; h.round_seed = c->round_seed;
+    h.rounding = c->rounding; h.round_seed = c->round_seed; h.poisson_method = c->poisson_method;
     h.lB = c->lB; h.sig_lo = c->sig_lo; h.sig_hi = c->sig_hi;
     for (int d = 0; d < 3; ++d) h.E[d] = c->E[d];
     h.sor_tol = c->sor_tol; h.sor_omega = c->sor_omega; h.steps = c->steps;
@@ -790,7 +1091,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     c->compute_scales();
     c->tau_v = h.tau_v; c->tau_d = h.tau_d; c->sc = h.sc; c->drag_from_sc = h.drag_from_sc != 0;
     c->sor_max = h.sor_max; c->sor_check = h.sor_check; c->sor_tol = h.sor_tol; c->sor_omega = h.sor_omega;
-    c->rounding = h.rounding; c->round_seed = h.round_seed;
+    c->rounding = h.rounding; c->round_seed = h.round_seed; c->poisson_method = h.poisson_method;
     c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
     if ((rc = c->hip(hipMemcpyAsync(c->f[c->cur], buf.data(), pop, hipMemcpyHostToDevice, c->stream), "copy f"))) return rc;
@@ -824,6 +1125,15 @@ void lbmix_destroy(lbmix_ctx *c) {
         if (c->dred) (void)hipFree(c->dred);
         if (c->hred) (void)hipHostFree(c->hred);
         if (c->scratch) (void)hipFree(c->scratch);
+        drop_graph(c);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        if (c->mg_b) (void)hipFree(c->mg_b);
+        if (c->mg_cinv) (void)hipFree(c->mg_cinv);
+        if (c->psi_prev) (void)hipFree(c->psi_prev);
+        for (size_t l = 1; l < c->mg.size(); ++l) {
+            (void)hipFree(c->mg[l].e);
+            (void)hipFree(c->mg[l].r);
+        }
     }
     delete c;
 }

@@ -19,13 +19,15 @@ PERIODIC, SLIT_Z = 0, 1
 F64, F32, F32_SHIFTED, BF16_SHIFTED, F16_SHIFTED = 0, 1, 2, 3, 4
 STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "f16s": F16_SHIFTED}
 GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z}
+POISSON = {"sor": 0, "multigrid": 1}
+WARM_START = {"previous": 0, "extrapolated": 1}
 ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
 Q = 19
 MAX_SPECIES = 4
 EXPORTS = (
     "lbmix_version", "lbmix_create", "lbmix_add_species", "lbmix_set_tau_visc",
     "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics", "lbmix_set_poisson",
-    "lbmix_set_rounding", "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding", "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
@@ -71,6 +73,8 @@ def load_library():
         "lbmix_set_schmidt": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_electrostatics": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
         "lbmix_set_poisson": ([vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_poisson_method": ([vp, ctypes.c_int], ctypes.c_int),
+        "lbmix_set_poisson_warm_start": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_set_rounding": ([vp, ctypes.c_int, ctypes.c_ulonglong], ctypes.c_int),
         "lbmix_set_storage_range": ([vp, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
@@ -174,9 +178,12 @@ class Lattice:
         self._check(self._L.lbmix_set_electrostatics(self._h, float(bjerrum), float(sigma_lo),
                                                      float(sigma_hi), e))
 
-    def set_poisson(self, rel_tol=1e-8, max_sweeps=200000, check_every=10, omega=-1.0):
+    def set_poisson(self, rel_tol=1e-8, max_sweeps=200000, check_every=10, omega=-1.0, method="sor",
+                    warm_start="previous"):
         self._check(self._L.lbmix_set_poisson(self._h, float(rel_tol), int(max_sweeps),
                                               int(check_every), float(omega)))
+        self._check(self._L.lbmix_set_poisson_method(self._h, POISSON[method]))
+        self._check(self._L.lbmix_set_poisson_warm_start(self._h, WARM_START[warm_start]))
 
     def set_rounding(self, stochastic=True, seed=0):
         self._check(self._L.lbmix_set_rounding(self._h, 1 if stochastic else 0, int(seed)))
