@@ -29,8 +29,9 @@ Q = 19
 
 
 def kernel_source_hash() -> str:
+    """Hash of the sources of the fused step kernel (its counters are void once they change)."""
     h = hashlib.sha256()
-    for name in ("lbmix_kernels.hip", "lbmix_kernels.h"):
+    for name in ("lbmix_step.hip", "lbmix_step.h", "lbmix_device.h"):
         with open(os.path.join(ROOT, "paper_1507_04891_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -157,7 +158,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--workload", default="binary", choices=["binary", "slit"],
                     help="binary: the 256^3 throughput benchmark (default); slit: the charged slit")
-    ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid"])
+    ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid", "direct"])
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--warm-start", default="previous", choices=["previous", "extrapolated"])
     ap.add_argument("--copy-probe", type=float, default=0.0,

@@ -147,7 +147,14 @@ int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_
  * LDS, the coarsest of at most 64 cells solved exactly), each cycle and its residual replayed
  * as one captured HIP graph.  With multigrid, max_sweeps of
  * lbmix_set_poisson caps (or, with rel_tol == 0, fixes) the number of V-cycles per solve and
- * lbmix_stats counts cycles in place of sweeps.  Errors: EINVAL for another method. */
+ * lbmix_stats counts cycles in place of sweeps.  2 direct: the operator of eq. `Poisson` is
+ * diagonalised along x and y by orthonormal real Fourier bases (batched FP64 products) and
+ * solved exactly along z, by one tridiagonal elimination per (x, y) mode in a slit, by a
+ * third Fourier basis in a periodic box; its result is exact to rounding (rel_tol, max_sweeps
+ * and check_every do not apply; lbmix_stats counts one sweep per solve and reports the
+ * residual of the result), takes any extents, and needs no warm start.  SOR and multigrid
+ * need even periodic extents (or 1).  Errors: EINVAL for another method, or for SOR or
+ * multigrid on odd extents once stepping has started (checked by lbmix_step before). */
 int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
 
 /* Warm start of each Poisson solve: 0 the previous potential (default); 1 the

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbmix.so")
-SOURCES = [os.path.join(HERE, "csrc", "lbmix_kernels.hip"), os.path.join(HERE, "csrc", "lbmix_runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", name)
+           for name in ("lbmix_step.hip", "lbmix_poisson.hip", "lbmix_runtime.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -16,7 +17,6 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # no packed FP32 instructions in generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
@@ -25,8 +25,22 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
+    """Compile the sources in parallel into objects under _build/, then link the library."""
+    out = os.path.join(HERE, "_build")
+    os.makedirs(out, exist_ok=True)
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(out, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd), src))
+        objs.append(obj)
+    failed = [src for p, src in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, "hipcc " + " ".join(failed))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *SOURCES]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -1,42 +1,10 @@
-// Internal interface between the C-ABI runtime and the gfx950 kernels of the library.
+// Internal interface between the C-ABI runtime and the gfx950 Poisson kernels.
 // Not installed; the public interface is include/lbmix.h.
 #pragma once
 
-#include <hip/hip_runtime.h>
-#include <cstdint>
+#include "lbmix_step.h"
 
 namespace lbmix {
-
-constexpr int Q = 19;
-constexpr int MAXS = 4;
-constexpr int BLOCK = 256;        // threads per work-group row of the node kernels
-constexpr int STEP_BLOCK = 512;   // threads per work-group of stream_collide (two rows)
-
-enum class Store : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
-
-// Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
-// over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
-// storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
-struct StepArgs {
-    const void *fin;
-    void *fout;
-    uint32_t nx, ny, nzf;
-    uint32_t N;                      // nx * ny * nzf
-    int ns;                          // species count (element stride of the layout)
-    double rho_bar[MAXS];            // storage shift per species (0: plain f)
-    float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
-    float inv_scale[MAXS][Q];
-    double omega_v, omega_d;
-    double valence[MAXS];
-    double E[3];                     // applied field, acceleration per unit valence
-    const double *psi;               // potential on fluid nodes (charged runs)
-    double *q;                       // out: charge density on fluid nodes (charged runs)
-    double q_rest;                   // sum_s valence_s * rho_bar_s
-    double ghost_lo, ghost_hi;       // 4 pi l_B sigma of the walls z = 0 and z = nz-1
-    double *partials;                // out: [species][block] FP64 sums of n - rho_bar
-    int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
-    uint32_t seed;                   // per-step seed of the rounding hash
-};
 
 struct PoissonArgs {
     double *psi;                     // fluid nodes
@@ -72,31 +40,6 @@ struct MGBottom {
     const double *coarse_inv;    // dense (A + 1 1^T / m)^-1 of the coarsest level (m cells), or null
 };
 
-dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
-dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
-
-hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
-                                 const StepArgs &a, hipStream_t stream);
-
-// Equilibrium of species s from host-layout device arrays n[N_full], u[3][N_full] (u may
-// be null), scattered into the slots the first pull reads.
-hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n,
-                       const double *u, hipStream_t stream);
-
-// Pull-gathered pre-collision moments of species s into full-lattice arrays (wall planes
-// written as 0); j may be null.
-hipError_t launch_moments(Store st, bool slit, int s, const StepArgs &a, double *n, double *j,
-                          hipStream_t stream);
-
-// Pull-gathered pre-collision populations (shift added back) of species s, [19][N_full].
-hipError_t launch_populations(Store st, bool slit, int s, const StepArgs &a, double *f,
-                              hipStream_t stream);
-
-// Charge density q = q_rest + sum_s valence_s (n_s - rho_bar_s) of the pre-collision state
-// on fluid nodes.
-hipError_t launch_charge(Store st, bool slit, int ns, const StepArgs &a, double *q,
-                         hipStream_t stream);
-
 // Red-black SOR half-sweep of colour 0 or 1.
 hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream);
 
@@ -130,6 +73,25 @@ hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t str
 hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream);
 // Warm start from the last three solutions: psi <- psi + p1 - p2, p2 <- p1, p1 <- old psi.
 hipError_t launch_extrapolate(double *psi, double *p1, double *p2, uint32_t N, hipStream_t stream);
+
+// Batched FP64 product C_b[m][n] = sum_k A_b[m][k] B_b[k][n] with element strides (the
+// unit stride of C is n).
+struct SpecGemm {
+    const double *A, *B;
+    double *C;
+    uint32_t M, N, K, batch;
+    size_t sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm;
+};
+// a_k_unit: sAk == 1 (else sAm == 1); b_n_unit: sBn == 1 (else sBk == 1); these choose the
+// coalesced load pattern only.
+hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipStream_t stream);
+// Tridiagonal solves along z for every mode (nmodes per plane) and every segment of planes
+// [seg[s], seg[s+1]), s < nseg; piv = inverse pivots [plane][mode].
+hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
+                            uint32_t nseg, hipStream_t stream);
+// a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
+hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,
+                                 uint32_t ny, uint32_t N, hipStream_t stream);
 
 // psi -= *mean on the fluid nodes.
 hipError_t launch_shift(double *psi, uint32_t N, const double *mean, hipStream_t stream);

@@ -6,7 +6,8 @@
 // launch, then for charged runs the Poisson solve of the new charge density, used by the
 // next collision.
 #include "lbmix.h"
-#include "lbmix_kernels.h"
+#include "lbmix_poisson.h"
+#include "lbmix_step.h"
 
 #include <cmath>
 #include <cstdarg>
@@ -45,7 +46,7 @@ struct lbmix_ctx {
     bool drag_from_sc = true;
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
-    int poisson_method = 0;           // 0 red-black SOR, 1 multigrid V(2,2) cycles
+    int poisson_method = 0;           // 0 red-black SOR, 1 multigrid, 2 direct (spectral)
     int warm_start = 0;               // 0 previous potential, 1 linear extrapolation in time
     double *psi_prev = nullptr;       // two previous solutions (warm_start 1)
     int have_prev = 0;
@@ -74,6 +75,11 @@ struct lbmix_ctx {
     hipStream_t cap_stream = nullptr;  // capture-only stream (graphs replay on `stream`)
     hipGraph_t vgraph = nullptr;
     hipGraphExec_t vexec = nullptr;
+    // direct solve: orthonormal bases of the periodic axes, their eigenvalues, the inverse
+    // pivots of the z systems (slit), segment bounds, two work arrays
+    double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
+    double *sp_piv = nullptr, *sp_a = nullptr, *sp_b = nullptr;
+    uint32_t *sp_seg = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
     // state
     bool allocated = false, started = false, psi_valid = false;
@@ -470,6 +476,121 @@ int mg_cycle(lbmix_ctx *c, const PoissonArgs &pa) {
     return c->hip(hipGraphLaunch(c->vexec, c->stream), "hipGraphLaunch");
 }
 
+// ---- direct solve -----------------------------------------------------------------------
+
+// Orthonormal real Fourier basis of a periodic axis of n nodes, row k = basis vector k
+// (frequency (k + 1) / 2), and the eigenvalues 4 sin^2(pi freq / n) of minus the 1-D
+// second difference.
+void periodic_basis(int n, std::vector<double> &T, std::vector<double> &mu) {
+    T.assign((size_t)n * n, 0.0);
+    mu.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        const int freq = (k + 1) / 2;
+        const bool nyquist = (2 * freq == n);
+        const bool sine = (k % 2 == 0) && k > 0 && !nyquist;
+        const double norm = (k == 0 || nyquist) ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n);
+        for (int x = 0; x < n; ++x) {
+            const double ang = 2.0 * kPi * (double)(((long long)freq * x) % n) / n;
+            T[(size_t)k * n + x] = norm * (sine ? std::sin(ang) : std::cos(ang));
+        }
+        const double sn = std::sin(kPi * freq / n);
+        mu[k] = 4.0 * sn * sn;
+    }
+}
+
+int upload(lbmix_ctx *c, double **dst, const std::vector<double> &v) {
+    int rc = c->hip(hipMalloc((void **)dst, v.size() * sizeof(double)), "hipMalloc(direct solve)");
+    if (rc) return rc;
+    return c->hip(hipMemcpy(*dst, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice), "copy(direct solve)");
+}
+
+int spec_build(lbmix_ctx *c) {
+    if (c->sp_a) return LBMIX_OK;
+    std::vector<double> tx, ty, tz, mux, muy, muz;
+    periodic_basis(c->nx, tx, mux);
+    periodic_basis(c->ny, ty, muy);
+    int rc;
+    if ((rc = upload(c, &c->sp_tx, tx)) || (rc = upload(c, &c->sp_ty, ty))) return rc;
+    std::vector<double> mu(mux);
+    mu.insert(mu.end(), muy.begin(), muy.end());
+    if (c->slit) {
+        // zero-flux z: rows of the z system carry diagonal -(2 + mu), -(1 + mu) on the two
+        // end planes (-mu for a single plane)
+        const size_t nm = (size_t)c->nx * c->ny;
+        std::vector<double> piv(nm * c->nzf);
+        for (int my = 0; my < c->ny; ++my)
+            for (int mx = 0; mx < c->nx; ++mx) {
+                const size_t m = (size_t)my * c->nx + mx;
+                const double mxy = mux[mx] + muy[my];
+                double prev = 0.0;
+                for (int z = 0; z < c->nzf; ++z) {
+                    const double d = -(2.0 + mxy) + (z == 0 ? 1.0 : 0.0) + (z == c->nzf - 1 ? 1.0 : 0.0);
+                    const bool pin = (m == 0 && z == c->nzf - 1);
+                    prev = pin ? 0.0 : 1.0 / (d - prev);
+                    piv[(size_t)z * nm + m] = prev;
+                }
+            }
+        if ((rc = upload(c, &c->sp_piv, piv))) return rc;
+        const uint32_t seg[2] = {0u, (uint32_t)c->nzf};
+        if ((rc = c->hip(hipMalloc((void **)&c->sp_seg, sizeof seg), "hipMalloc(direct solve)"))) return rc;
+        if ((rc = c->hip(hipMemcpy(c->sp_seg, seg, sizeof seg, hipMemcpyHostToDevice), "copy(direct solve)")))
+            return rc;
+    } else {
+        periodic_basis(c->nzf, tz, muz);
+        if ((rc = upload(c, &c->sp_tz, tz))) return rc;
+        mu.insert(mu.end(), muz.begin(), muz.end());
+    }
+    if ((rc = upload(c, &c->sp_mu, mu))) return rc;
+    const size_t bytes = (size_t)c->Nf * sizeof(double);
+    if ((rc = c->hip(hipMalloc((void **)&c->sp_b, bytes), "hipMalloc(direct solve)"))) return rc;
+    return c->hip(hipMalloc((void **)&c->sp_a, bytes), "hipMalloc(direct solve)");
+}
+
+// Transforms along x (rows of nx), y (per plane) and z (whole array) into `out`;
+// inverse = the transposed basis.
+int spec_x(lbmix_ctx *c, const double *in, double *out, bool inverse) {
+    SpecGemm g{};
+    g.A = in; g.C = out; g.B = c->sp_tx;
+    g.M = (uint32_t)c->ny * c->nzf; g.N = c->nx; g.K = c->nx; g.batch = 1;
+    g.sAm = c->nx; g.sAk = 1; g.sCm = c->nx;
+    // forward: C[m][k] = sum_x A[m][x] T[k][x];  inverse: C[m][x] = sum_k A[m][k] T[k][x]
+    if (inverse) { g.sBk = c->nx; g.sBn = 1; } else { g.sBk = 1; g.sBn = c->nx; }
+    return c->hip(launch_gemm_f64(g, true, inverse, c->stream), "gemm(x)");
+}
+int spec_left(lbmix_ctx *c, const double *T, uint32_t n, uint32_t inner, uint32_t batch, const double *in,
+              double *out, bool inverse, const char *what) {
+    SpecGemm g{};
+    g.A = T; g.B = in; g.C = out;
+    g.M = n; g.N = inner; g.K = n; g.batch = batch;
+    // forward: C[k][i] = sum_j T[k][j] B[j][i];  inverse: C[j][i] = sum_k T[k][j] B[k][i]
+    if (inverse) { g.sAm = 1; g.sAk = n; } else { g.sAm = n; g.sAk = 1; }
+    g.sBb = g.sCb = (size_t)n * inner;
+    g.sBk = inner; g.sBn = 1; g.sCm = inner;
+    return c->hip(launch_gemm_f64(g, !inverse, true, c->stream), what);
+}
+
+int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
+    int rc;
+    if ((rc = spec_build(c))) return rc;
+    const uint32_t nxy = (uint32_t)c->nx * c->ny;
+    double *a = c->sp_a, *b = c->sp_b;
+    if ((rc = c->hip(launch_make_rhs(pa, a, c->stream), "make_rhs"))) return rc;
+    if ((rc = spec_x(c, a, b, false))) return rc;
+    if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, false, "gemm(y)"))) return rc;
+    if (c->slit) {
+        if ((rc = c->hip(launch_tridiag_z(a, c->sp_piv, b, nxy, c->sp_seg, 1, c->stream), "tridiag_z"))) return rc;
+    } else {
+        if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, a, b, false, "gemm(z)"))) return rc;
+        if ((rc = c->hip(launch_spectral_scale(b, c->sp_mu, c->sp_mu + c->nx, c->sp_mu + c->nx + c->ny, c->nx,
+                                               c->ny, c->Nf, c->stream), "spectral_scale")))
+            return rc;
+        if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, b, a, true, "gemm(z)"))) return rc;
+        std::swap(a, b);
+    }
+    if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, true, "gemm(y)"))) return rc;
+    return spec_x(c, a, c->psi, true);
+}
+
 // Poisson solve of the charge in c->q into c->psi (warm start), then zero-mean gauge.
 int finish_zero_rhs(lbmix_ctx *c) {   // b == 0: the solution is psi = 0
     int rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
@@ -500,7 +621,7 @@ int solve(lbmix_ctx *c) {
     const PoissonArgs pa = c->pargs();
     // warm start: the previous potential, or psi(t-1) + psi(t-2) - psi(t-3) once three
     // solutions exist (exact for a linear trend plus a period-two oscillation in time)
-    if (c->warm_start == 1 && c->psi_valid) {
+    if (c->warm_start == 1 && c->psi_valid && c->poisson_method != 2) {
         const size_t bytes = (size_t)c->Nf * sizeof(double);
         if (!c->psi_prev) {
             if ((rc = c->hip(hipMalloc((void **)&c->psi_prev, 2 * bytes), "hipMalloc(psi_prev)"))) return rc;
@@ -520,7 +641,12 @@ int solve(lbmix_ctx *c) {
         }
     }
     int work = 0, status = LBMIX_OK;
-    if (c->poisson_method == 1) {
+    if (c->poisson_method == 2) {
+        // direct: exact to rounding; the residual norms stay on the device for the stats
+        if ((rc = spec_solve(c, pa)) || (rc = residual(c, pa))) return rc;
+        work = 1;
+        c->resid_on_device = true;
+    } else if (c->poisson_method == 1) {
         // multigrid: each V-cycle is one graph replay that also leaves the residual norms of
         // its result in dred[4..7]; the first (previous count - 1) cycles run without reading
         // them back, since they are expected to be needed
@@ -618,11 +744,16 @@ int check_ready(lbmix_ctx *c) {
     return LBMIX_OK;
 }
 
+bool redblack_extents(const lbmix_ctx *c) {
+    auto bad_extent = [](int n) { return n > 1 && (n % 2) != 0; };
+    return !(bad_extent(c->nx) || bad_extent(c->ny) || (!c->slit && bad_extent(c->nz)));
+}
+
 int validate_start(lbmix_ctx *c) {
     if (!c->charged()) return LBMIX_OK;
-    auto bad_extent = [](int n) { return n > 1 && (n % 2) != 0; };
-    if (bad_extent(c->nx) || bad_extent(c->ny) || (!c->slit && bad_extent(c->nz)))
-        return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR");
+    if (c->poisson_method != 2 && !redblack_extents(c))
+        return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR and "
+                                     "multigrid (the direct solve takes any)");
     double qtot = 0.0, scale = 0.0;
     for (int s = 0; s < c->ns; ++s) {
         qtot += c->valence[s] * c->host_total[s];
@@ -773,7 +904,9 @@ int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_ev
 
 int lbmix_set_poisson_method(lbmix_ctx *c, int method) {
     if (!c) return LBMIX_EINVAL;
-    if (method != 0 && method != 1) return c->fail(LBMIX_EINVAL, "Poisson method is 0 (SOR) or 1 (multigrid)");
+    if (method < 0 || method > 2) return c->fail(LBMIX_EINVAL, "Poisson method is 0 (SOR), 1 (multigrid) or 2 (direct)");
+    if (c->started && method != 2 && c->charged() && !redblack_extents(c))
+        return c->fail(LBMIX_EINVAL, "SOR and multigrid need even periodic extents (or 1)");
     drop_graph(c);
     c->poisson_method = method;
     return LBMIX_OK;
@@ -1130,6 +1263,9 @@ void lbmix_destroy(lbmix_ctx *c) {
         if (c->mg_b) (void)hipFree(c->mg_b);
         if (c->mg_cinv) (void)hipFree(c->mg_cinv);
         if (c->psi_prev) (void)hipFree(c->psi_prev);
+        for (double *p : {c->sp_tx, c->sp_ty, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
+            if (p) (void)hipFree(p);
+        if (c->sp_seg) (void)hipFree(c->sp_seg);
         for (size_t l = 1; l < c->mg.size(); ++l) {
             (void)hipFree(c->mg[l].e);
             (void)hipFree(c->mg[l].r);

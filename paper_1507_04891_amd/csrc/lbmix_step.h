@@ -1,0 +1,66 @@
+// Internal interface between the C-ABI runtime and the gfx950 kernels of the fused step.
+// Not installed; the public interface is include/lbmix.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace lbmix {
+
+constexpr int Q = 19;
+constexpr int MAXS = 4;
+constexpr int BLOCK = 256;        // threads per work-group row of the node kernels
+constexpr int STEP_BLOCK = 512;   // threads per work-group of stream_collide (two rows)
+
+enum class Store : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
+
+// Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
+// over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
+// storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
+struct StepArgs {
+    const void *fin;
+    void *fout;
+    uint32_t nx, ny, nzf;
+    uint32_t N;                      // nx * ny * nzf
+    int ns;                          // species count (element stride of the layout)
+    double rho_bar[MAXS];            // storage shift per species (0: plain f)
+    float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
+    float inv_scale[MAXS][Q];
+    double omega_v, omega_d;
+    double valence[MAXS];
+    double E[3];                     // applied field, acceleration per unit valence
+    const double *psi;               // potential on fluid nodes (charged runs)
+    double *q;                       // out: charge density on fluid nodes (charged runs)
+    double q_rest;                   // sum_s valence_s * rho_bar_s
+    double ghost_lo, ghost_hi;       // 4 pi l_B sigma of the walls z = 0 and z = nz-1
+    double *partials;                // out: [species][block] FP64 sums of n - rho_bar
+    int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
+    uint32_t seed;                   // per-step seed of the rounding hash
+};
+
+dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
+dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
+
+hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
+                                 const StepArgs &a, hipStream_t stream);
+
+// Equilibrium of species s from host-layout device arrays n[N_full], u[3][N_full] (u may
+// be null), scattered into the slots the first pull reads.
+hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n,
+                       const double *u, hipStream_t stream);
+
+// Pull-gathered pre-collision moments of species s into full-lattice arrays (wall planes
+// written as 0); j may be null.
+hipError_t launch_moments(Store st, bool slit, int s, const StepArgs &a, double *n, double *j,
+                          hipStream_t stream);
+
+// Pull-gathered pre-collision populations (shift added back) of species s, [19][N_full].
+hipError_t launch_populations(Store st, bool slit, int s, const StepArgs &a, double *f,
+                              hipStream_t stream);
+
+// Charge density q = q_rest + sum_s valence_s (n_s - rho_bar_s) of the pre-collision state
+// on fluid nodes.
+hipError_t launch_charge(Store st, bool slit, int ns, const StepArgs &a, double *q,
+                         hipStream_t stream);
+
+}  // namespace lbmix

@@ -15,7 +15,8 @@
 // non-temporal vector load and one vector store of all species.  All arithmetic is done on deviations d_p = f_p - w_p
 // rho_bar, which makes the shifted storage forms exact in their range and costs nothing
 // for the plain ones (rho_bar = 0).
-#include "lbmix_kernels.h"
+#include "lbmix_step.h"
+#include "lbmix_device.h"
 
 #include <hip/hip_fp16.h>
 
@@ -218,38 +219,6 @@ struct Pull {
         node = bb ? own() : (sz * ny + sy) * nx + sx;
     }
 };
-
-template <int P, class F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (P > 0) {
-        static_for<P - 1>(f);
-        f(std::integral_constant<int, P - 1>{});
-    }
-}
-
-// Deterministic work-group sum of NV doubles (fixed shuffle tree, fixed wave order).
-template <int NV>
-__device__ void block_sum_store(double (&v)[NV], double *partials, uint32_t nblocks, uint32_t bid) {
-    __shared__ double red[NV][STEP_BLOCK / 64];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        double t = v[k];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-        v[k] = t;
-    }
-    const int tid = threadIdx.x + blockDim.x * threadIdx.y;     // blockDim.x is a multiple of 64
-    const int lane = tid & 63, wave = tid >> 6;
-    const int nwaves = (blockDim.x * blockDim.y + 63) >> 6;
-    if (lane == 0)
-        for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
-    __syncthreads();
-    if (tid < NV) {
-        double s = 0.0;
-        for (int w = 0; w < nwaves; ++w) s += red[tid][w];
-        partials[(size_t)tid * nblocks + bid] = s;
-    }
-}
 
 // ---------------------------------------------------------------------------------------
 // The fused step.
@@ -544,350 +513,6 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
 }
 
 // ---------------------------------------------------------------------------------------
-// Poisson: 7-point finite-volume operator on fluid nodes (eq. Poisson, Sec. II), periodic in
-// x, y (and z for the box); no neighbour across a wall, whose charge sits in the first
-// fluid layer.  b = -K (q + lump) - mean(b).
-
-struct Stencil {
-    double sum;
-    int deg;
-};
-
-__device__ inline Stencil neighbours(const PoissonArgs &a, const double *psi, uint32_t x, uint32_t y,
-                                     uint32_t z) {
-    const uint32_t xm = x == 0 ? a.nx - 1 : x - 1, xp = x + 1 == a.nx ? 0 : x + 1;
-    const uint32_t ym = y == 0 ? a.ny - 1 : y - 1, yp = y + 1 == a.ny ? 0 : y + 1;
-    const uint32_t row = (z * a.ny + y) * a.nx;
-    double s = psi[row + xp];
-    s += psi[row + xm];
-    s += psi[(z * a.ny + yp) * a.nx + x];
-    s += psi[(z * a.ny + ym) * a.nx + x];
-    int deg = 4;
-    if (a.slit) {
-        if (z + 1 < a.nzf) { s += psi[((z + 1) * a.ny + y) * a.nx + x]; ++deg; }
-        if (z > 0) { s += psi[((z - 1) * a.ny + y) * a.nx + x]; ++deg; }
-    } else {
-        const uint32_t zp = z + 1 == a.nzf ? 0 : z + 1, zm = z == 0 ? a.nzf - 1 : z - 1;
-        s += psi[(zp * a.ny + y) * a.nx + x];
-        s += psi[(zm * a.ny + y) * a.nx + x];
-        deg = 6;
-    }
-    return {s, deg};
-}
-
-__device__ inline double rhs(const PoissonArgs &a, uint32_t i, uint32_t z) {
-    double lump = 0.0;
-    if (a.slit) {
-        if (z == 0) lump += a.lump_lo;
-        if (z + 1 == a.nzf) lump += a.lump_hi;
-    }
-    return -a.K * (a.q[i] + lump) - *a.bmean;
-}
-
-__global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colour) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
-    const uint32_t zfull = a.slit ? z + 1 : z;
-    if (((x + y + zfull) & 1u) != (uint32_t)colour) return;
-    const uint32_t i = (z * a.ny + y) * a.nx + x;
-    const Stencil st = neighbours(a, a.psi, x, y, z);
-    const double b = rhs(a, i, z);
-    const double gs = (st.sum - b) / (double)st.deg;
-    a.psi[i] = a.psi[i] + a.omega * (gs - a.psi[i]);
-}
-
-constexpr uint32_t RES_PLANES = 8;   // fluid planes per work-group of the residual kernel
-
-__global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *partials) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[3] = {0.0, 0.0, 0.0};
-    if (x < a.nx) {
-        const uint32_t y = blockIdx.y;
-        const uint32_t z1 = min(a.nzf, (blockIdx.z + 1) * RES_PLANES);
-        for (uint32_t z = blockIdx.z * RES_PLANES; z < z1; ++z) {
-            const uint32_t i = (z * a.ny + y) * a.nx + x;
-            const Stencil st = neighbours(a, a.psi, x, y, z);
-            const double b = rhs(a, i, z);
-            const double r = b - (st.sum - st.deg * a.psi[i]);
-            v[0] += r * r;
-            v[1] += b * b;
-            v[2] += a.psi[i];
-        }
-    }
-    const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    block_sum_store<3>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
-}
-
-__global__ __launch_bounds__(BLOCK) void qsum(const double *q, uint32_t N, double *partials) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    double v[1] = {i < N ? q[i] : 0.0};
-    block_sum_store<1>(v, partials, gridDim.x, blockIdx.x);
-}
-
-constexpr int FIN_BLOCK = 1024;
-
-__global__ __launch_bounds__(FIN_BLOCK) void finalize(const double *partials, uint32_t nb, int nv, double *out,
-                                                     int mode, double K, double lumps, double N) {
-    __shared__ double red[FIN_BLOCK];
-    for (int v = 0; v < nv; ++v) {
-        double s = 0.0;
-        for (uint32_t b = threadIdx.x; b < nb; b += FIN_BLOCK) s += partials[(size_t)v * nb + b];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = FIN_BLOCK / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[v] = red[0];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        if (mode == 1) out[nv] = -K * (out[0] + lumps) / N;
-        if (mode == 2) out[nv] = out[2] / N;
-    }
-}
-
-__global__ __launch_bounds__(BLOCK) void make_rhs(const PoissonArgs a, double *r) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.nx) return;
-    const uint32_t i = (blockIdx.z * a.ny + blockIdx.y) * a.nx + x;
-    r[i] = rhs(a, i, blockIdx.z);
-}
-
-// ---------------------------------------------------------------------------------------
-// Geometric multigrid for the same operator (cell-centred, V-cycles).  On a level with
-// spacings H_d the equation reads sum_d a_d (e_{+d} + e_{-d} - 2 e) = r, a_d = 1 / H_d^2, with
-// periodic x, y, periodic or zero-flux z (a missing neighbour drops its term).
-
-struct MGNb {
-    double sum, diag;
-};
-
-__device__ inline MGNb mg_nb(const MGLevel &L, const double *e, uint32_t x, uint32_t y, uint32_t z) {
-    double s = 0.0, dg = 0.0;
-    if (L.nx > 1) {
-        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1, xp = x + 1 == L.nx ? 0 : x + 1;
-        s += L.ax * (e[(z * L.ny + y) * L.nx + xp] + e[(z * L.ny + y) * L.nx + xm]);
-        dg += 2.0 * L.ax;
-    }
-    if (L.ny > 1) {
-        const uint32_t ym = y == 0 ? L.ny - 1 : y - 1, yp = y + 1 == L.ny ? 0 : y + 1;
-        s += L.ay * (e[(z * L.ny + yp) * L.nx + x] + e[(z * L.ny + ym) * L.nx + x]);
-        dg += 2.0 * L.ay;
-    }
-    if (L.nz > 1) {
-        if (L.periodic_z) {
-            const uint32_t zm = z == 0 ? L.nz - 1 : z - 1, zp = z + 1 == L.nz ? 0 : z + 1;
-            s += L.az * (e[(zp * L.ny + y) * L.nx + x] + e[(zm * L.ny + y) * L.nx + x]);
-            dg += 2.0 * L.az;
-        } else {
-            if (z + 1 < L.nz) { s += L.az * e[((z + 1) * L.ny + y) * L.nx + x]; dg += L.az; }
-            if (z > 0) { s += L.az * e[((z - 1) * L.ny + y) * L.nx + x]; dg += L.az; }
-        }
-    }
-    return {s, dg};
-}
-
-__global__ __launch_bounds__(BLOCK) void mg_smooth(const MGLevel L, int colour) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= L.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
-    if (((x + y + z) & 1u) != (uint32_t)colour) return;
-    const uint32_t i = (z * L.ny + y) * L.nx + x;
-    const MGNb nb = mg_nb(L, L.e, x, y, z);
-    if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
-}
-
-// one thread per coarse cell: average of the fine residuals of its children
-__global__ __launch_bounds__(BLOCK) void mg_restrict(const MGLevel F, const MGLevel C) {
-    const uint32_t X = blockIdx.x * blockDim.x + threadIdx.x;
-    if (X >= C.nx) return;
-    const uint32_t Y = blockIdx.y, Z = blockIdx.z;
-    double acc = 0.0;
-    for (int k = 0; k < F.fz; ++k)
-        for (int j = 0; j < F.fy; ++j)
-            for (int i = 0; i < F.fx; ++i) {
-                const uint32_t x = X * F.fx + i, y = Y * F.fy + j, z = Z * F.fz + k;
-                const uint32_t fi = (z * F.ny + y) * F.nx + x;
-                const MGNb nb = mg_nb(F, F.e, x, y, z);
-                acc += F.r[fi] - (nb.sum - nb.diag * F.e[fi]);
-            }
-    const uint32_t ci = (Z * C.ny + Y) * C.nx + X;
-    C.r[ci] = acc / double(F.fx * F.fy * F.fz);
-    C.e[ci] = 0.0;
-}
-
-// cell-centred linear interpolation along each coarsened axis: weights 3/4 (own coarse
-// cell) and 1/4 (the coarse neighbour on the side of the fine cell); a zero-flux boundary
-// reflects (the neighbour is the cell itself), a periodic one wraps
-__device__ inline void lin1(uint32_t f, int factor, uint32_t nc, bool periodic, uint32_t &c0, uint32_t &c1,
-                            double &w0) {
-    if (factor == 1) { c0 = c1 = f; w0 = 1.0; return; }
-    c0 = f >> 1;
-    const bool lo = (f & 1u) == 0;
-    if (lo) c1 = c0 == 0 ? (periodic ? nc - 1 : 0) : c0 - 1;
-    else c1 = c0 + 1 == nc ? (periodic ? 0 : c0) : c0 + 1;
-    w0 = 0.75;
-}
-
-__global__ __launch_bounds__(BLOCK) void mg_prolong(const MGLevel F, const MGLevel C) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= F.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
-    uint32_t xa, xb, ya, yb, za, zb;
-    double wx, wy, wz;
-    lin1(x, F.fx, C.nx, true, xa, xb, wx);
-    lin1(y, F.fy, C.ny, true, ya, yb, wy);
-    lin1(z, F.fz, C.nz, F.periodic_z != 0, za, zb, wz);
-    const double *e = C.e;
-    auto at = [&](uint32_t i, uint32_t j, uint32_t k) { return e[(k * C.ny + j) * C.nx + i]; };
-    const double v = wz * (wy * (wx * at(xa, ya, za) + (1 - wx) * at(xb, ya, za)) +
-                           (1 - wy) * (wx * at(xa, yb, za) + (1 - wx) * at(xb, yb, za))) +
-                     (1 - wz) * (wy * (wx * at(xa, ya, zb) + (1 - wx) * at(xb, ya, zb)) +
-                                 (1 - wy) * (wx * at(xa, yb, zb) + (1 - wx) * at(xb, yb, zb)));
-    F.e[(z * F.ny + y) * F.nx + x] += v;
-}
-
-// The coarse end of the hierarchy in one work-group: every sweep, restriction and
-// interpolation of the small levels is a loop over cells with barriers between phases.
-__device__ void blk_smooth(const MGLevel &L, int colour) {
-    const uint32_t n = L.nx * L.ny * L.nz;
-    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const uint32_t x = i % L.nx, y = (i / L.nx) % L.ny, z = i / (L.nx * L.ny);
-        if (((x + y + z) & 1u) != (uint32_t)colour) continue;
-        const MGNb nb = mg_nb(L, L.e, x, y, z);
-        if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
-    }
-    __syncthreads();
-}
-
-// View of bottom level l in LDS (offsets from the sizes of the levels above it); built from
-// the kernel arguments on demand, so no level table is indexed at run time in private memory.
-__device__ inline MGLevel bottom_view(const MGBottom &b, int l, double *se, double *sr) {
-    uint32_t off = 0;
-    for (int k = 0; k < l; ++k) off += b.lev[k].nx * b.lev[k].ny * b.lev[k].nz;
-    MGLevel v = b.lev[l];
-    v.e = se + off;
-    v.r = sr + off;
-    return v;
-}
-
-__global__ __launch_bounds__(1024) void mg_bottom(const MGBottom b) {
-    __shared__ double se[MG_BOTTOM_LDS], sr[MG_BOTTOM_LDS];
-    {
-        const uint32_t n0 = b.lev[0].nx * b.lev[0].ny * b.lev[0].nz;
-        for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) {
-            se[i] = 0.0;
-            sr[i] = b.lev[0].r[i];
-        }
-        __syncthreads();
-    }
-    for (int l = 0; l < b.n; ++l) {
-        const MGLevel L = bottom_view(b, l, se, sr);
-        if (l > 0) {   // restrict the residual of level l-1 into level l, e = 0
-            const MGLevel F = bottom_view(b, l - 1, se, sr);
-            const uint32_t n = L.nx * L.ny * L.nz;
-            for (uint32_t ci = threadIdx.x; ci < n; ci += blockDim.x) {
-                const uint32_t X = ci % L.nx, Y = (ci / L.nx) % L.ny, Z = ci / (L.nx * L.ny);
-                double acc = 0.0;
-                for (int k = 0; k < F.fz; ++k)
-                    for (int j = 0; j < F.fy; ++j)
-                        for (int i = 0; i < F.fx; ++i) {
-                            const uint32_t x = X * F.fx + i, y = Y * F.fy + j, z = Z * F.fz + k;
-                            const uint32_t fi = (z * F.ny + y) * F.nx + x;
-                            const MGNb nb = mg_nb(F, F.e, x, y, z);
-                            acc += F.r[fi] - (nb.sum - nb.diag * F.e[fi]);
-                        }
-                L.r[ci] = acc / double(F.fx * F.fy * F.fz);
-                L.e[ci] = 0.0;
-            }
-            __syncthreads();
-        }
-        if (l == b.n - 1 && b.coarse_inv) {
-            // exact coarsest solve: (A + 1 1^T / m) e = r gives the zero-mean solution of a
-            // consistent r (and absorbs the rounding of its mean)
-            const uint32_t m = L.nx * L.ny * L.nz;
-            double acc = 0.0;
-            if (threadIdx.x < m)
-                for (uint32_t j = 0; j < m; ++j) acc += b.coarse_inv[threadIdx.x * m + j] * L.r[j];
-            __syncthreads();
-            if (threadIdx.x < m) L.e[threadIdx.x] = acc;
-            __syncthreads();
-            continue;
-        }
-        const int sweeps = (l == b.n - 1) ? b.coarse_sweeps : 2;
-        for (int k = 0; k < sweeps; ++k) {
-            blk_smooth(L, 0);
-            blk_smooth(L, 1);
-        }
-    }
-    for (int l = b.n - 2; l >= 0; --l) {
-        const MGLevel F = bottom_view(b, l, se, sr), C = bottom_view(b, l + 1, se, sr);
-        const uint32_t n = F.nx * F.ny * F.nz;
-        for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
-            const uint32_t x = i % F.nx, y = (i / F.nx) % F.ny, z = i / (F.nx * F.ny);
-            uint32_t xa, xb, ya, yb, za, zb;
-            double wx, wy, wz;
-            lin1(x, F.fx, C.nx, true, xa, xb, wx);
-            lin1(y, F.fy, C.ny, true, ya, yb, wy);
-            lin1(z, F.fz, C.nz, F.periodic_z != 0, za, zb, wz);
-            auto at = [&](uint32_t ii, uint32_t jj, uint32_t kk) { return C.e[(kk * C.ny + jj) * C.nx + ii]; };
-            F.e[i] += wz * (wy * (wx * at(xa, ya, za) + (1 - wx) * at(xb, ya, za)) +
-                            (1 - wy) * (wx * at(xa, yb, za) + (1 - wx) * at(xb, yb, za))) +
-                      (1 - wz) * (wy * (wx * at(xa, ya, zb) + (1 - wx) * at(xb, ya, zb)) +
-                                  (1 - wy) * (wx * at(xa, yb, zb) + (1 - wx) * at(xb, yb, zb)));
-        }
-        __syncthreads();
-        for (int k = 0; k < 2; ++k) {
-            blk_smooth(F, 0);
-            blk_smooth(F, 1);
-        }
-    }
-    const uint32_t n0 = b.lev[0].nx * b.lev[0].ny * b.lev[0].nz;
-    for (uint32_t i = threadIdx.x; i < n0; i += blockDim.x) b.lev[0].e[i] = se[i];
-}
-
-// psi <- psi + p1 - p2 (p1, p2 = the two previous solutions), then p2 <- p1, p1 <- psi_old:
-// exact for a linear trend plus an oscillation of period two steps
-__global__ __launch_bounds__(BLOCK) void extrapolate(double *psi, double *p1, double *p2, uint32_t N) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const double a = psi[i], b = p1[i];
-    psi[i] = a + b - p2[i];
-    p2[i] = b;
-    p1[i] = a;
-}
-
-__global__ __launch_bounds__(BLOCK) void shift(double *psi, uint32_t N, const double *mean) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) psi[i] -= *mean;
-}
-
-__global__ __launch_bounds__(BLOCK) void plane_sums(const double *n, const double *j, uint32_t nx, uint32_t ny,
-                                                   uint32_t nz, double *out) {
-    __shared__ double red[4][BLOCK];
-    const uint32_t z = blockIdx.x;
-    const size_t plane = (size_t)nx * ny, Nfull = plane * nz;
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (size_t k = threadIdx.x; k < plane; k += BLOCK) {
-        const size_t i = z * plane + k;
-        s[0] += n[i];
-        s[1] += j[i];
-        s[2] += j[Nfull + i];
-        s[3] += j[2 * Nfull + i];
-    }
-    for (int v = 0; v < 4; ++v) red[v][threadIdx.x] = s[v];
-    __syncthreads();
-    for (int w = BLOCK / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int v = 0; v < 4; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x < 4) out[(size_t)threadIdx.x * nz + z] = red[threadIdx.x][0];
-}
-
-// ---------------------------------------------------------------------------------------
 // Launchers.
 
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block) {
@@ -1005,77 +630,6 @@ hipError_t launch_populations(Store st, bool slit, int s, const StepArgs &a, dou
 }
 hipError_t launch_charge(Store st, bool slit, int ns, const StepArgs &a, double *q, hipStream_t stream) {
     return by_store<ChargeK>(st, slit, ns, a, q, stream);
-}
-
-hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
-    hipLaunchKernelGGL(sor_half, g, b, 0, stream, a, colour);
-    return hipGetLastError();
-}
-
-hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, (a.nzf + RES_PLANES - 1) / RES_PLANES, &b);
-    *nb = g.x * g.y * g.z;
-    hipLaunchKernelGGL(residual, g, b, 0, stream, a, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *nb, hipStream_t stream) {
-    *nb = (N + BLOCK - 1) / BLOCK;
-    hipLaunchKernelGGL(qsum, dim3(*nb), dim3(BLOCK), 0, stream, q, N, partials);
-    return hipGetLastError();
-}
-
-hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out, int mode, double K,
-                           double lumps, double N, hipStream_t stream) {
-    hipLaunchKernelGGL(finalize, dim3(1), dim3(FIN_BLOCK), 0, stream, partials, nblocks, nv, out, mode, K, lumps, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_make_rhs(const PoissonArgs &a, double *r, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
-    hipLaunchKernelGGL(make_rhs, g, b, 0, stream, a, r);
-    return hipGetLastError();
-}
-hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(L.nx, L.ny, L.nz, &b);
-    hipLaunchKernelGGL(mg_smooth, g, b, 0, stream, L, colour);
-    return hipGetLastError();
-}
-hipError_t launch_mg_restrict(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(C.nx, C.ny, C.nz, &b);
-    hipLaunchKernelGGL(mg_restrict, g, b, 0, stream, F, C);
-    return hipGetLastError();
-}
-hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(F.nx, F.ny, F.nz, &b);
-    hipLaunchKernelGGL(mg_prolong, g, b, 0, stream, F, C);
-    return hipGetLastError();
-}
-hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream) {
-    hipLaunchKernelGGL(mg_bottom, dim3(1), dim3(1024), 0, stream, b);
-    return hipGetLastError();
-}
-hipError_t launch_extrapolate(double *psi, double *p1, double *p2, uint32_t N, hipStream_t stream) {
-    hipLaunchKernelGGL(extrapolate, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, psi, p1, p2, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_shift(double *psi, uint32_t N, const double *mean, hipStream_t stream) {
-    hipLaunchKernelGGL(shift, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, psi, N, mean);
-    return hipGetLastError();
-}
-
-hipError_t launch_plane_sums(const double *n, const double *j, uint32_t nx, uint32_t ny, uint32_t nz,
-                             double *out, hipStream_t stream) {
-    hipLaunchKernelGGL(plane_sums, dim3(nz), dim3(BLOCK), 0, stream, n, j, nx, ny, nz, out);
-    return hipGetLastError();
 }
 
 }  // namespace lbmix

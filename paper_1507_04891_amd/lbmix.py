@@ -19,7 +19,7 @@ PERIODIC, SLIT_Z = 0, 1
 F64, F32, F32_SHIFTED, BF16_SHIFTED, F16_SHIFTED = 0, 1, 2, 3, 4
 STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "f16s": F16_SHIFTED}
 GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z}
-POISSON = {"sor": 0, "multigrid": 1}
+POISSON = {"sor": 0, "multigrid": 1, "direct": 2}
 WARM_START = {"previous": 0, "extrapolated": 1}
 ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
 Q = 19
