@@ -145,6 +145,111 @@ def bench_slit(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_channels(args):
+    """The batched charged channels: 64 slit channels of 32 x 32 x W (W ~ U{32..256}, seed 5,
+    9.2 M fluid nodes), wall charges ~ -U[1e-4, 1e-3], Sc 10 / 100 / 1000, lambda_D = 8,
+    E_x = 1e-4, one fused stream-collide launch for all channels plus the Poisson solve of
+    every channel each step.  Prints its own JSON line."""
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    w = WL.batched_channels()
+    stream = torch.cuda.current_stream()
+    lat = P.from_workload(w, storage=args.storage, stream=stream,
+                          poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
+                                       method=args.poisson))
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    st0 = lat.stats()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    lat.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / args.steps
+    st1 = lat.stats()
+    nodes = sum(w.widths) * w.nx * w.ny
+    sites = w.nspecies * nodes
+    print(json.dumps({"workload": f"{len(w.widths)} charged slit channels {w.nx}x{w.ny}xW, W in "
+                                  f"{min(w.widths)}..{max(w.widths)} (seed 5), {nodes} fluid nodes, Sc 10/100/1000",
+                      "storage": args.storage, "poisson_method": args.poisson,
+                      "ms_per_step": round(ms, 4), "glups": round(sites / (ms * 1e-3) / 1e9, 3),
+                      "poisson_work_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 2),
+                      "last_residual": st1["last_residual"]}), flush=True)
+
+
+def bench_precision(args):
+    """Transport coefficients with every storage form against FP64 storage: the mutual
+    diffusivity D from a decaying concentration wave (Sc 10 and 100; D = v_T^2 (1/omega_drag
+    - 1/2)), the viscosity nu from a shear wave (nu = v_T^2 (1/omega_visc - 1/2)), and the
+    electro-osmotic mobility u_centre / E_x of a charged 16 x 16 x 32 slit at Sc 100 (steady
+    state, time-averaged).  Prints one JSON line of values and relative errors."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    L = 128
+    k = 2 * math.pi / L
+    basis = np.sin(k * np.arange(L))[None, None, :]
+    forms = [("f64", None), ("f32", None), ("f32s", None), ("f16s", True), ("f16s", False), ("bf16s", True)]
+    name = lambda st, sr: st + ("" if sr is None else (" SR" if sr else " RNE"))
+    out = {"workload": "D: binary sine 128x64x64 (amp 1e-3); nu: shear wave 128x64x64, tau 0.8; "
+                       "mobility: charged slit 16x16x34, lambda_D 4, sigma -1e-4, E_x 1e-5, Sc 100"}
+    for sc, t1, t2 in [(10.0, 300, 6300), (100.0, 2000, 22000)]:
+        w = WL.binary_sine(L, 64, 64, amp=1e-3, tau_visc=1.0, sc=sc)
+        for st, sr in forms:
+            lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
+            lat.step(t1)
+            a1 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
+            lat.step(t2 - t1)
+            a2 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
+            out[f"D Sc={sc:g} {name(st, sr)}"] = -math.log(a2 / a1) / (t2 - t1) / k ** 2 if a2 / a1 > 0 else None
+            del lat
+            print(f"D Sc={sc:g} {name(st, sr)} done", file=sys.stderr, flush=True)
+    shape = (64, 64, L)
+    u = np.zeros((3,) + shape)
+    u[1] = 1e-3 * basis
+    w = WL.Workload("shear", L, 64, 64, "periodic", [0.5, 0.5], [0, 0], 0.8, WL.tau_drag_for_schmidt(0.8, 100.0),
+                    [np.full(shape, 0.5)] * 2, [u, u])
+    for st, sr in forms:
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
+        amp = lambda: sum(float((lat.moments(q)[1][1] * basis).sum()) for q in range(2))
+        lat.step(100)
+        a1 = amp()
+        lat.step(3000)
+        out[f"nu {name(st, sr)}"] = -math.log(amp() / a1) / 3000 / k ** 2
+        del lat
+    w = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
+    for st, sr in forms:
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, poisson=dict(method="direct"))
+        lat.step(28000)
+        acc = None
+        for _ in range(20):
+            lat.step(100)
+            pr = lat.zprofiles()
+            acc = pr if acc is None else acc + pr
+        pr = acc / 20
+        rho = pr[:, 0, 1:-1].sum(0)
+        out[f"mobility {name(st, sr)}"] = float(pr[:, 1, 1:-1].sum(0)[16] / rho[16] / 1e-5)
+        del lat
+        print(f"mobility {name(st, sr)} done", file=sys.stderr, flush=True)
+    for key in list(out):
+        if key == "workload" or " f64" in key or out[key] is None:
+            continue
+        ref = out[key.split(" ")[0] + (" " + key.split(" ")[1] if key.startswith("D") else "") + " f64"]
+        out["err " + key] = out[key] / ref - 1.0
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,8 +261,9 @@ def main():
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--workload", default="binary", choices=["binary", "slit"],
-                    help="binary: the 256^3 throughput benchmark (default); slit: the charged slit")
+    ap.add_argument("--workload", default="binary", choices=["binary", "slit", "channels", "precision"],
+                    help="binary: the 256^3 throughput benchmark (default); slit: the charged slit; "
+                         "channels: 64 charged slit channels in one lattice")
     ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid", "direct"])
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--warm-start", default="previous", choices=["previous", "extrapolated"])
@@ -173,6 +279,12 @@ def main():
 
     if args.workload == "slit":
         bench_slit(args)
+        return
+    if args.workload == "channels":
+        bench_channels(args)
+        return
+    if args.workload == "precision":
+        bench_precision(args)
         return
 
     import torch

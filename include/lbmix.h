@@ -20,8 +20,10 @@
  *     vector fields are planar [3][nz][ny][nx], populations [19][nz][ny][nx];
  *   - geometry LBMIX_PERIODIC: periodic in x, y, z;  LBMIX_SLIT_Z: periodic in x and y,
  *     the planes z = 0 and z = nz-1 are solid walls at rest (half-way bounce-back, wall
- *     surfaces at z = 1/2 and z = nz - 3/2); wall-plane entries of host arrays are ignored
- *     on input and written as 0 on output;
+ *     surfaces at z = 1/2 and z = nz - 3/2); LBMIX_CHANNELS: independent slit channels of
+ *     their own widths stacked along z (lbmix_create_channels), each with its two wall
+ *     planes; wall-plane entries of host arrays are ignored on input and written as 0 on
+ *     output;
  *   - D3Q19 order: p = 0 rest; 1..6 = +x, -x, +y, -y, +z, -z; 7..18 = (+1,+1,0), (-1,-1,0),
  *     (+1,-1,0), (-1,+1,0), (+1,0,+1), (-1,0,-1), (+1,0,-1), (-1,0,+1), (0,+1,+1),
  *     (0,-1,-1), (0,+1,-1), (0,-1,+1); weights 1/3, 1/18, 1/36;
@@ -58,7 +60,7 @@ enum lbmix_status {
     LBMIX_ENONFINITE = -6  /* a mass total is NaN or Inf; latched until set_state / load */
 };
 
-enum lbmix_geometry { LBMIX_PERIODIC = 0, LBMIX_SLIT_Z = 1 };
+enum lbmix_geometry { LBMIX_PERIODIC = 0, LBMIX_SLIT_Z = 1, LBMIX_CHANNELS = 2 };
 
 /* Population storage.  F64 and F32 store f.  The SHIFTED forms store the deviation
  * f_p - w_p rho0 (rho0 = the species' rest density given to lbmix_add_species), in FP32,
@@ -99,6 +101,25 @@ int lbmix_version(void);
 int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage,
                  void *hip_stream);
 
+/* Create a stack of `nchannels` slit channels (the charged slit of Sec. IV, many at once):
+ * each channel c has nx * ny lateral nodes (periodic), widths[c] >= 1 fluid planes and its
+ * own two wall planes, so host arrays cover nz = sum_c (widths[c] + 2) planes, channel c
+ * from plane sum_{c' < c} (widths[c'] + 2) (its lower wall) upwards.  Channels share the
+ * species, tau_visc, the Bjerrum length, the field and the storage; each has its own drag
+ * and wall charges (lbmix_set_channel) and is neutral and gauged on its own.  One fused
+ * launch steps all channels; the Poisson solve is the direct one or SOR (not multigrid).
+ * Errors: as lbmix_create; EINVAL for nchannels < 1 or a width < 1. */
+int lbmix_create_channels(lbmix_ctx **out, int nx, int ny, int nchannels, const int *widths,
+                          int storage, void *hip_stream);
+
+/* Parameters of channel `channel` of a stack: tau_drag > 1/2 (<= 0: the context's drag, from
+ * lbmix_set_tau_drag or lbmix_set_schmidt), and the surface charges of its lower and upper
+ * walls in units of e per lattice area.  Defaults: the context's drag, uncharged walls.
+ * Errors: EINVAL for a context not made by lbmix_create_channels, a bad index or tau_drag
+ * in (0, 1/2]; ESTATE after the first step. */
+int lbmix_set_channel(lbmix_ctx *ctx, int channel, double tau_drag, double sigma_lo,
+                      double sigma_hi);
+
 /* Add a species with rest density rho0 > 0 (the storage shift of the SHIFTED forms and
  * the reference density of the FP16 scale) and integer valence z^alpha (Sec. II; the
  * ternary electrolyte of Sec. III has z = 0, +1, -1).  Writes its index to *id_out.
@@ -120,11 +141,13 @@ int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
 
 /* Electrostatics (Sec. II, eq. Poisson and its surface-charge condition): Bjerrum length
  * l_B >= 0 (0: no Poisson solve), surface charges of the walls z = 0 and z = nz-1 in units
- * of e per lattice area (used by LBMIX_SLIT_Z only), and the applied field E_ext[3] as an
- * acceleration per unit valence (may be NULL for zero).  A charged run (l_B > 0 and a
- * species with z != 0) needs nx and ny even or 1 (nz too for a periodic box) for the
- * red-black ordering, and a neutral system: |sum z rho0 N + (sigma_lo + sigma_hi) nx ny|
- * must be small against the charge carried by the species (checked at the first step).
+ * of e per lattice area (used by LBMIX_SLIT_Z only; channels take theirs from
+ * lbmix_set_channel), and the applied field E_ext[3] as an acceleration per unit valence
+ * (may be NULL for zero).  A charged run (l_B > 0 and a species with z != 0) needs nx and
+ * ny even or 1 (nz too for a periodic box) for the red-black ordering of SOR and multigrid,
+ * and neutral channels: |sum z rho0 N + (sigma_lo + sigma_hi) nx ny| of each channel (the
+ * whole lattice for the box) must be small against the charge carried by its species
+ * (checked at the first step).
  * Errors: EINVAL for l_B < 0; ESTATE after the first step. */
 int lbmix_set_electrostatics(lbmix_ctx *ctx, double bjerrum, double sigma_lo,
                              double sigma_hi, const double *E_ext);
@@ -134,7 +157,9 @@ int lbmix_set_electrostatics(lbmix_ctx *ctx, double bjerrum, double sigma_lo,
  * rel_tol, checking every check_every sweeps, and report ENOCONV from lbmix_step when
  * max_sweeps is reached first; rel_tol == 0: exactly max_sweeps sweeps per solve, never
  * ENOCONV.  omega_sor in (0, 2), or <= 0 for 2 / (1 + sin(pi / L)), L the largest fluid
- * extent.  After each solve psi is shifted to zero mean over the fluid.  Errors: EINVAL
+ * extent.  After each solve psi is shifted to zero mean over the fluid of each channel.
+ * The right-hand side b = -4 pi l_B (q + wall charge lumped into the first and last fluid
+ * planes) is projected onto zero mean per channel.  Errors: EINVAL
  * for rel_tol < 0, max_sweeps < 1, check_every < 1 or omega_sor >= 2. */
 int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_every,
                       double omega_sor);
@@ -148,13 +173,15 @@ int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_
  * as one captured HIP graph.  With multigrid, max_sweeps of
  * lbmix_set_poisson caps (or, with rel_tol == 0, fixes) the number of V-cycles per solve and
  * lbmix_stats counts cycles in place of sweeps.  2 direct: the operator of eq. `Poisson` is
- * diagonalised along x and y by orthonormal real Fourier bases (batched FP64 products) and
- * solved exactly along z, by one tridiagonal elimination per (x, y) mode in a slit, by a
- * third Fourier basis in a periodic box; its result is exact to rounding (rel_tol, max_sweeps
- * and check_every do not apply; lbmix_stats counts one sweep per solve and reports the
- * residual of the result), takes any extents, and needs no warm start.  SOR and multigrid
- * need even periodic extents (or 1).  Errors: EINVAL for another method, or for SOR or
- * multigrid on odd extents once stepping has started (checked by lbmix_step before). */
+ * diagonalised along x and y by orthonormal real Fourier bases (planes of up to 64 x 64
+ * nodes in LDS, larger ones by batched FP64 products) and solved exactly along z, by one
+ * tridiagonal elimination per (x, y) mode and channel in a slit or stack, by a third
+ * Fourier basis in a periodic box; its result is exact to rounding, takes any extents and
+ * needs no warm start (rel_tol and max_sweeps do not apply; lbmix_stats counts one sweep
+ * per solve and reports the residual of every check_every-th solve).  SOR and multigrid
+ * need even periodic extents (or 1); multigrid does not take channel stacks.  Errors:
+ * EINVAL for another method, multigrid on a stack, or SOR or multigrid on odd extents once
+ * stepping has started (checked by lbmix_step before). */
 int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
 
 /* Warm start of each Poisson solve: 0 the previous potential (default); 1 the

@@ -53,6 +53,7 @@ class _Params(ctypes.Structure):
         ("poisson", ctypes.c_int), ("lagged", ctypes.c_int),
         ("sor_omega", ctypes.c_double), ("sor_tol", ctypes.c_double),
         ("sor_max", ctypes.c_int), ("sor_check", ctypes.c_int),
+        ("pair_drag", ctypes.c_int), ("drag_pair", ctypes.c_double * (MAXS * MAXS)),
     ]
 
 
@@ -84,6 +85,7 @@ def lib():
         L.ora_phi_perp.argtypes = [ctypes.c_double, dp, dp, dp]
         L.ora_forcing.argtypes = [ctypes.c_double, dp, dp, dp]
         L.ora_drag.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp]
+        L.ora_drag_pair.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, dp]
         _lib = L
     return _lib
 
@@ -126,6 +128,16 @@ def drag(n, ua, omega_drag: float) -> np.ndarray:
     return F
 
 
+def drag_pair(n, ua, omega) -> np.ndarray:
+    """Drag with a frequency per pair: omega is [ns][ns] (symmetric)."""
+    n = _f64(n)
+    ua = _f64(ua).reshape(len(n), 3)
+    om = _f64(omega).reshape(len(n), len(n))
+    F = np.zeros_like(ua)
+    lib().ora_drag_pair(len(n), _dp(n), _dp(ua), _dp(om), len(n), _dp(F))
+    return F
+
+
 def sor_omega_default(nx: int, ny: int, nzf: int) -> float:
     """Over-relaxation factor 2 / (1 + sin(pi / L)) with L the largest fluid extent."""
     L = max(nx, ny, nzf)
@@ -142,7 +154,7 @@ class Oracle:
     def __init__(self, nx, ny, nz, nspecies, omega_visc, omega_drag, geometry="periodic",
                  valence=None, bjerrum=0.0, sigma=(0.0, 0.0), E=(0.0, 0.0, 0.0),
                  poisson="direct", lagged=True, sor_omega=None, sor_tol=1e-8,
-                 sor_max=100000, sor_check=10):
+                 sor_max=100000, sor_check=10, drag_pair=None):
         if nspecies > MAXS:
             raise ValueError("too many species")
         p = _Params()
@@ -164,6 +176,12 @@ class Oracle:
         p.sor_tol = sor_tol
         p.sor_max = sor_max
         p.sor_check = sor_check
+        if drag_pair is not None:   # [ns][ns] drag frequencies omega^{ab}
+            om = np.asarray(drag_pair, dtype=np.float64).reshape(nspecies, nspecies)
+            p.pair_drag = 1
+            for a in range(nspecies):
+                for b in range(nspecies):
+                    p.drag_pair[a * MAXS + b] = om[a, b]
         self.params = p
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz

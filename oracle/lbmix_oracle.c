@@ -102,6 +102,8 @@ typedef struct {
     double sor_tol;        /* > 0: stop at ||b - A psi||_2 / ||b||_2 <= tol; 0: fixed sweeps */
     int sor_max;           /* sweep cap (fixed count when sor_tol == 0) */
     int sor_check;         /* sweeps between residual evaluations */
+    int pair_drag;         /* 1: drag frequency per pair of species from drag_pair */
+    double drag_pair[ORA_MAXS * ORA_MAXS]; /* omega^{ab} at [a * ORA_MAXS + b], symmetric */
 } ora_params;
 
 typedef struct {
@@ -188,6 +190,24 @@ void ora_drag(int ns, const double *n, const double *ua, double omega_drag, doub
             if (ntot != 0.0)
                 for (int b = 0; b < ns; ++b) acc += (n[b] / ntot) * (ua[3 * a + d] - ua[3 * b + d]);
             F[3 * a + d] = -omega_drag * acc;
+        }
+    }
+}
+
+/* Drag with one frequency per pair of species (Sec. II: the friction coefficient of the
+ * pair (a, b), here for equal masses):  F^a = -sum_b omega^{ab} (n^b / n)(u^a - u^b).
+ * omega[a * ld + b] must be symmetric for the pair forces to cancel (third law); the
+ * diagonal does not contribute. */
+void ora_drag_pair(int ns, const double *n, const double *ua, const double *omega, int ld, double *F) {
+    double ntot = 0.0;
+    for (int b = 0; b < ns; ++b) ntot += n[b];
+    for (int a = 0; a < ns; ++a) {
+        for (int d = 0; d < 3; ++d) {
+            double acc = 0.0;
+            if (ntot != 0.0)
+                for (int b = 0; b < ns; ++b)
+                    acc += omega[a * ld + b] * (n[b] / ntot) * (ua[3 * a + d] - ua[3 * b + d]);
+            F[3 * a + d] = -acc;
         }
     }
 }
@@ -641,7 +661,10 @@ static int one_step(ora_ctx *c) {
                 umid[3 * s + d] = ua[3 * s + d] + 0.5 * acc[3 * s + d];
             }
         /* drag on the mid-step velocities [R3b], then the total force */
-        ora_drag(ns, n, umid, P->omega_drag, F);
+        if (P->pair_drag)
+            ora_drag_pair(ns, n, umid, P->drag_pair, ORA_MAXS, F);
+        else
+            ora_drag(ns, n, umid, P->omega_drag, F);
         for (int s = 0; s < ns; ++s)
             for (int d = 0; d < 3; ++d) F[3 * s + d] += acc[3 * s + d];
 

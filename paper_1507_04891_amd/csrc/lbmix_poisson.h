@@ -11,10 +11,10 @@ struct PoissonArgs {
     const double *q;                 // fluid nodes
     uint32_t nx, ny, nzf;
     uint32_t N;
-    int slit;
+    int slit;                        // 1: walls from `planes` (slit or channel stack)
+    const PlaneInfo *planes;         // [nzf] (walls: zero-flux faces, wall charge lumps)
     double K;                        // 4 pi l_B
-    double lump_lo, lump_hi;         // wall charge added to the first / last fluid plane
-    const double *bmean;             // device scalar: mean of b over the fluid
+    const double *bmean;             // device, per channel: mean of -K (q + lump) over it
     double omega;                    // SOR factor
 };
 
@@ -51,6 +51,19 @@ hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb,
 hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *nb,
                        hipStream_t stream);
 
+// out[z] = sum of v over fluid plane z (nxy nodes per plane), z < nplanes, in a fixed order.
+hipError_t launch_plane_sum(const double *v, uint32_t nxy, uint32_t nplanes, double *out, hipStream_t stream);
+// Per channel c < nch (planes [first[c], first[c+1])), from the plane sums S_z:
+//   mode 0: out[c] = -K (sum_z S_z + nxy sum_z lump_z) / (nxy W_c)   (mean of b);
+//   mode 1: out[c] = sum_z S_z / (nxy W_c)                             (mean of psi).
+// planes may be null (no lumps).
+hipError_t launch_channel_means(const double *plane_sums, const uint32_t *first, uint32_t nch,
+                                const PlaneInfo *planes, uint32_t nxy, int mode, double K, double *out,
+                                hipStream_t stream);
+// psi -= mean[channel of the plane] (planes null: one channel).
+hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const PlaneInfo *planes,
+                               const double *mean, hipStream_t stream);
+
 // out[v] = sum_b partials[v * nblocks + b] for v < nv, in a fixed order; then
 // out[nv + k] for the post-processing `mode`:
 //   mode 0: none;  mode 1: out[nv] = -K (out[0] + lumps) / N   (mean of b);
@@ -58,7 +71,7 @@ hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *
 hipError_t launch_finalize(const double *partials, uint32_t nblocks, int nv, double *out,
                            int mode, double K, double lumps, double N, hipStream_t stream);
 
-// Level-0 right-hand side b = -K (q + lump) - mean(b) into r.
+// Level-0 right-hand side b = -K (q + lump) - mean(b) into r (mean per channel).
 hipError_t launch_make_rhs(const PoissonArgs &a, double *r, hipStream_t stream);
 // One red-black Gauss-Seidel half-sweep of level L.
 hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream);
@@ -89,6 +102,26 @@ hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipS
 // [seg[s], seg[s+1]), s < nseg; piv = inverse pivots [plane][mode].
 hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
                             uint32_t nseg, hipStream_t stream);
+// Per-plane transform along x and y of a plane of at most SPEC_XY_MAX nodes (nx, ny <= 64),
+// in LDS, one work-group per plane.  Forward: out = Ty P Tx^T with P the plane of `in`, or,
+// when `q` is given, of b = -K (q + lump_z) (lumps from planes, which may be null).
+// Inverse: out = Ty^T P Tx.
+constexpr uint32_t SPEC_XY_MAX = 4096;
+struct SpecXY {
+    const double *in, *q;
+    double *out;
+    const double *tx, *ty;           // nx x nx and ny x ny bases (row k = basis vector k)
+    const PlaneInfo *planes;
+    double K;
+    uint32_t nx, ny, nplanes;
+};
+hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream);
+// Tridiagonal solves as launch_tridiag_z, the columns staged in LDS; segments of at most
+// TRI_LDS_MAX planes.  Both forms also remove the segment mean of mode 0 from the right-hand
+// side first (the projection onto consistent data of each channel).
+constexpr uint32_t TRI_LDS_MAX = 256;
+hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
+                              const uint32_t *seg, uint32_t nseg, hipStream_t stream);
 // a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
 hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,
                                  uint32_t ny, uint32_t N, hipStream_t stream);

@@ -10,7 +10,8 @@ namespace lbmix {
 // ---------------------------------------------------------------------------------------
 // Poisson: 7-point finite-volume operator on fluid nodes (eq. Poisson, Sec. II), periodic in
 // x, y (and z for the box); no neighbour across a wall, whose charge sits in the first
-// fluid layer.  b = -K (q + lump) - mean(b).
+// fluid layer.  b = -K (q + lump) - mean(b), the mean taken per channel (each channel of a
+// stack is an independent problem).
 
 struct Stencil {
     double sum;
@@ -28,8 +29,9 @@ __device__ inline Stencil neighbours(const PoissonArgs &a, const double *psi, ui
     s += psi[(z * a.ny + ym) * a.nx + x];
     int deg = 4;
     if (a.slit) {
-        if (z + 1 < a.nzf) { s += psi[((z + 1) * a.ny + y) * a.nx + x]; ++deg; }
-        if (z > 0) { s += psi[((z - 1) * a.ny + y) * a.nx + x]; ++deg; }
+        const uint32_t walls = a.planes[z].walls;
+        if (!(walls & 2u)) { s += psi[((z + 1) * a.ny + y) * a.nx + x]; ++deg; }
+        if (!(walls & 1u)) { s += psi[((z - 1) * a.ny + y) * a.nx + x]; ++deg; }
     } else {
         const uint32_t zp = z + 1 == a.nzf ? 0 : z + 1, zm = z == 0 ? a.nzf - 1 : z - 1;
         s += psi[(zp * a.ny + y) * a.nx + x];
@@ -40,20 +42,16 @@ __device__ inline Stencil neighbours(const PoissonArgs &a, const double *psi, ui
 }
 
 __device__ inline double rhs(const PoissonArgs &a, uint32_t i, uint32_t z) {
-    double lump = 0.0;
-    if (a.slit) {
-        if (z == 0) lump += a.lump_lo;
-        if (z + 1 == a.nzf) lump += a.lump_hi;
-    }
-    return -a.K * (a.q[i] + lump) - *a.bmean;
+    if (a.slit) return -a.K * (a.q[i] + a.planes[z].lump) - a.bmean[a.planes[z].chan];
+    return -a.K * a.q[i] - a.bmean[0];
 }
 
 __global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colour) {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
     const uint32_t y = blockIdx.y, z = blockIdx.z;
-    const uint32_t zfull = a.slit ? z + 1 : z;
-    if (((x + y + zfull) & 1u) != (uint32_t)colour) return;
+    const uint32_t zc = a.slit ? a.planes[z].zloc : z;   // colour by the channel's own lattice
+    if (((x + y + zc) & 1u) != (uint32_t)colour) return;
     const uint32_t i = (z * a.ny + y) * a.nx + x;
     const Stencil st = neighbours(a, a.psi, x, y, z);
     const double b = rhs(a, i, z);
@@ -87,6 +85,43 @@ __global__ __launch_bounds__(BLOCK) void qsum(const double *q, uint32_t N, doubl
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[1] = {i < N ? q[i] : 0.0};
     block_sum_store<1>(v, partials, gridDim.x, blockIdx.x);
+}
+
+// Sum of one fluid plane per work-group (fixed order).
+__global__ __launch_bounds__(BLOCK) void plane_sum(const double *v, uint32_t nxy, double *out) {
+    __shared__ double red[BLOCK];
+    const double *p = v + (size_t)blockIdx.x * nxy;
+    double s = 0.0;
+    for (uint32_t i = threadIdx.x; i < nxy; i += BLOCK) s += p[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// One thread per channel: the plane sums of the channel in order.
+__global__ __launch_bounds__(BLOCK) void channel_means(const double *ps, const uint32_t *first, uint32_t nch,
+                                                      const PlaneInfo *planes, uint32_t nxy, int mode, double K,
+                                                      double *out) {
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nch) return;
+    double s = 0.0, lump = 0.0;
+    for (uint32_t z = first[c]; z < first[c + 1]; ++z) {
+        s += ps[z];
+        if (planes) lump += planes[z].lump;
+    }
+    const double n = (double)nxy * (double)(first[c + 1] - first[c]);
+    out[c] = mode == 0 ? -K * (s + (double)nxy * lump) / n : s / n;
+}
+
+__global__ __launch_bounds__(BLOCK) void shift_planes(double *psi, uint32_t nxy, uint32_t N, const PlaneInfo *planes,
+                                                     const double *mean) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    psi[i] -= mean[planes ? planes[i / nxy].chan : 0u];
 }
 
 constexpr int FIN_BLOCK = 1024;
@@ -403,11 +438,16 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
     const uint32_t mode = blockIdx.x * 64 + threadIdx.x;
     if (mode >= nmodes) return;
     const uint32_t z0 = seg[blockIdx.y], z1 = seg[blockIdx.y + 1];
+    double bm = 0.0;   // mode 0: project the right-hand side onto zero segment mean
+    if (mode == 0) {
+        for (uint32_t z = z0; z < z1; ++z) bm += b[(size_t)z * nmodes];
+        bm /= double(z1 - z0);
+    }
     double r = 0.0;
 #pragma unroll 8
     for (uint32_t z = z0; z < z1; ++z) {
         const size_t i = (size_t)z * nmodes + mode;
-        r = (b[i] - r) * piv[i];
+        r = (b[i] - bm - r) * piv[i];
         out[i] = r;
     }
     double x = 0.0;
@@ -423,6 +463,127 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
         const double mean = sum / double(z1 - z0);
         for (uint32_t z = z0; z < z1; ++z) out[(size_t)z * nmodes] -= mean;
     }
+}
+
+// The same eliminations with the columns staged in LDS: one wave per 32 modes of one segment
+// (at most TRI_LDS_MAX planes); all 64 lanes stage the right-hand side and pivots with
+// coalesced loads, 32 lanes run the recurrences from LDS, all 64 write the result back.
+constexpr uint32_t TRI_MODES = 32;
+
+__global__ __launch_bounds__(64) void tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
+                                                  const uint32_t *seg) {
+    __shared__ double sb[TRI_LDS_MAX][TRI_MODES], sp[TRI_LDS_MAX][TRI_MODES];
+    const uint32_t m0 = blockIdx.x * TRI_MODES;
+    const uint32_t z0 = seg[blockIdx.y], L = seg[blockIdx.y + 1] - z0;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t k = t; k < L * TRI_MODES; k += 64) {
+        const uint32_t z = k / TRI_MODES, m = k % TRI_MODES;
+        const bool in = m0 + m < nmodes;
+        const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
+        sb[z][m] = in ? b[i] : 0.0;
+        sp[z][m] = in ? piv[i] : 0.0;
+    }
+    __syncthreads();
+    if (t < TRI_MODES && m0 + t < nmodes) {
+        double bm = 0.0;   // mode 0: project onto zero segment mean
+        if (m0 + t == 0) {
+            for (uint32_t z = 0; z < L; ++z) bm += sb[z][0];
+            bm /= double(L);
+        }
+        double r = 0.0;
+        for (uint32_t z = 0; z < L; ++z) {
+            r = (sb[z][t] - bm - r) * sp[z][t];
+            sb[z][t] = r;
+        }
+        double x = 0.0;
+        for (uint32_t z = L; z-- > 0;) {
+            x = sb[z][t] - sp[z][t] * x;
+            sb[z][t] = x;
+        }
+        if (m0 + t == 0) {
+            double sum = 0.0;
+            for (uint32_t z = 0; z < L; ++z) sum += sb[z][0];
+            const double mean = sum / double(L);
+            for (uint32_t z = 0; z < L; ++z) sb[z][0] -= mean;
+        }
+    }
+    __syncthreads();
+    for (uint32_t k = t; k < L * TRI_MODES; k += 64) {
+        const uint32_t z = k / TRI_MODES, m = k % TRI_MODES;
+        if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[z][m];
+    }
+}
+
+// C[r][c] = sum_k A(r, k) B(k, c) between LDS arrays (r < R, c < CN, k < K), with
+// A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc], C[r ldc + c]; 4 x 4 outputs per thread
+// (edge indices clamped, their outputs not stored).
+__device__ void lds_product(const double *A, int ar, int ak, const double *B, int bk, int bc, double *C, int ldc,
+                            int R, int CN, int K) {
+    const int nbr = (R + 3) / 4, nbc = (CN + 3) / 4;
+    for (int blk = threadIdx.x; blk < nbr * nbc; blk += blockDim.x) {
+        const int r0 = (blk / nbc) * 4, c0 = (blk % nbc) * 4;
+        int ra[4], cb[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            ra[i] = min(r0 + i, R - 1) * ar;
+            cb[i] = min(c0 + i, CN - 1) * bc;
+        }
+        double acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double av[4], bv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) av[i] = A[ra[i] + k * ak];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = B[k * bk + cb[j]];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (r0 + i < R && c0 + j < CN) C[(r0 + i) * ldc + c0 + j] = acc[i][j];
+    }
+}
+
+// Transform of one plane along x and y in LDS (one work-group per plane, nx, ny <= 64).
+constexpr int XY_LD = 65;   // row stride of the LDS arrays (64 + 1)
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void spec_xy(const SpecXY a) {
+    __shared__ double P[64 * XY_LD], R[64 * XY_LD], Tx[64 * XY_LD], Ty[64 * XY_LD];
+    const int nx = a.nx, ny = a.ny;
+    const uint32_t z = blockIdx.x;
+    const size_t base = (size_t)z * nx * ny;
+    for (int k = threadIdx.x; k < nx * nx; k += blockDim.x) Tx[(k / nx) * XY_LD + k % nx] = a.tx[k];
+    for (int k = threadIdx.x; k < ny * ny; k += blockDim.x) Ty[(k / ny) * XY_LD + k % ny] = a.ty[k];
+    if (FWD && a.q) {
+        const double lump = a.planes ? a.planes[z].lump : 0.0;
+        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x)
+            P[(k / nx) * XY_LD + k % nx] = -a.K * (a.q[base + k] + lump);
+    } else {
+        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) P[(k / nx) * XY_LD + k % nx] = a.in[base + k];
+    }
+    __syncthreads();
+    if (FWD) {
+        // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
+        lds_product(P, XY_LD, 1, Tx, 1, XY_LD, R, XY_LD, ny, nx, nx);
+        __syncthreads();
+        lds_product(Ty, XY_LD, 1, R, XY_LD, 1, P, XY_LD, ny, nx, ny);
+    } else {
+        // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
+        lds_product(Ty, 1, XY_LD, P, XY_LD, 1, R, XY_LD, ny, nx, ny);
+        __syncthreads();
+        lds_product(R, XY_LD, 1, Tx, XY_LD, 1, P, XY_LD, ny, nx, nx);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * XY_LD + k % nx];
 }
 
 // a <- -a / (mu_x + mu_y + mu_z) in the transformed basis of a periodic box (0 for the
@@ -537,6 +698,41 @@ hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipS
         hipLaunchKernelGGL((gemm_f64<false, true>), grid, dim3(256), 0, stream, g);
     else
         hipLaunchKernelGGL((gemm_f64<false, false>), grid, dim3(256), 0, stream, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_plane_sum(const double *v, uint32_t nxy, uint32_t nplanes, double *out, hipStream_t stream) {
+    hipLaunchKernelGGL(plane_sum, dim3(nplanes), dim3(BLOCK), 0, stream, v, nxy, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_channel_means(const double *plane_sums, const uint32_t *first, uint32_t nch,
+                                const PlaneInfo *planes, uint32_t nxy, int mode, double K, double *out,
+                                hipStream_t stream) {
+    hipLaunchKernelGGL(channel_means, dim3((nch + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, plane_sums, first, nch,
+                       planes, nxy, mode, K, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const PlaneInfo *planes, const double *mean,
+                               hipStream_t stream) {
+    hipLaunchKernelGGL(shift_planes, dim3((N + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, psi, nxy, N, planes, mean);
+    return hipGetLastError();
+}
+
+hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
+    if (a.nx > 64 || a.ny > 64) return hipErrorInvalidValue;
+    if (forward)
+        hipLaunchKernelGGL(spec_xy<true>, dim3(a.nplanes), dim3(256), 0, stream, a);
+    else
+        hipLaunchKernelGGL(spec_xy<false>, dim3(a.nplanes), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
+                              uint32_t nseg, hipStream_t stream) {
+    hipLaunchKernelGGL(tridiag_lds, dim3((nmodes + TRI_MODES - 1) / TRI_MODES, nseg), dim3(64), 0, stream, b, piv,
+                       out, nmodes, seg);
     return hipGetLastError();
 }
 

@@ -35,7 +35,21 @@ struct lbmix_ctx {
     size_t esize = 8;
     uint32_t Nf = 0;
     size_t Nfull = 0;
-    bool slit = false;
+    bool slit = false;                // walls along z (a slit or a stack of channels)
+    // channels along z: a slit is one channel, the periodic box one channel without walls.
+    // Fluid width, first fluid plane and first full plane (its lower wall) of each channel,
+    // per-channel drag (tau <= 0: the context's) and wall charges.
+    int nch = 1;
+    std::vector<int> ch_width, ch_first, ch_full;
+    std::vector<double> ch_tau_d, ch_sig_lo, ch_sig_hi;
+    std::vector<double> ch_total;     // [species][channel]: FP64 totals of the initial densities
+    PlaneInfo *d_planes = nullptr;
+    int32_t *d_fof = nullptr;         // fluid plane of each full plane (-1: wall)
+    uint32_t *d_first = nullptr;      // first fluid plane of each channel, then nzf
+    double *d_chan = nullptr;         // per channel: mean of b, then mean of psi
+    double *d_psums = nullptr;        // per fluid plane sums
+    bool tables_dirty = true;
+    int direct_count = 0;             // direct solves (the residual is evaluated every check_every)
     // species and parameters
     int ns = 0;
     double rho0[MAXS] = {};
@@ -156,8 +170,9 @@ struct lbmix_ctx {
         for (int d = 0; d < 3; ++d) a.E[d] = E[d];
         a.psi = psi;
         a.q = q;
-        a.ghost_lo = 4.0 * kPi * lB * sig_lo;
-        a.ghost_hi = 4.0 * kPi * lB * sig_hi;
+        a.planes = slit ? d_planes : nullptr;
+        a.fluid_of_full = d_fof;
+        a.nzfull = (uint32_t)nz;
         a.partials = step_partials;
         a.stochastic = rounding;
         {   // per-step seed: a splitmix64 finaliser of (seed, step), folded to 32 bits
@@ -179,9 +194,8 @@ struct lbmix_ctx {
         p.N = Nf;
         p.slit = slit ? 1 : 0;
         p.K = 4.0 * kPi * lB;
-        p.lump_lo = slit ? sig_lo : 0.0;
-        p.lump_hi = slit ? sig_hi : 0.0;
-        p.bmean = dred + 1;
+        p.planes = slit ? d_planes : nullptr;
+        p.bmean = d_chan;
         p.omega = sor_w();
         return p;
     }
@@ -263,6 +277,69 @@ int ensure_field_buffers(lbmix_ctx *c) {
     rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
     if (rc) return rc;
     return c->hip(hipMemsetAsync(c->q, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(q)");
+}
+
+double channel_omega_drag(const lbmix_ctx *c, int ch) {
+    const double t = c->ch_tau_d.empty() ? 0.0 : c->ch_tau_d[ch];
+    return t > 0.0 ? 1.0 / t : c->omega_drag();
+}
+
+// Per-plane and per-channel device tables from the current parameters (after every change).
+int ensure_tables(lbmix_ctx *c) {
+    if (!c->tables_dirty) return LBMIX_OK;
+    int rc;
+    if (!c->d_fof) {
+        if ((rc = c->hip(hipMalloc((void **)&c->d_planes, (size_t)c->nzf * sizeof(PlaneInfo)), "hipMalloc(tables)")) ||
+            (rc = c->hip(hipMalloc((void **)&c->d_fof, (size_t)c->nz * sizeof(int32_t)), "hipMalloc(tables)")) ||
+            (rc = c->hip(hipMalloc((void **)&c->d_first, (size_t)(c->nch + 1) * sizeof(uint32_t)), "hipMalloc(tables)")) ||
+            (rc = c->hip(hipMalloc((void **)&c->d_chan, (size_t)2 * c->nch * sizeof(double)), "hipMalloc(tables)")) ||
+            (rc = c->hip(hipMalloc((void **)&c->d_psums, (size_t)c->nzf * sizeof(double)), "hipMalloc(tables)")))
+            return rc;
+    }
+    std::vector<PlaneInfo> pl(c->nzf);
+    std::vector<int32_t> fof(c->nz, -1);
+    std::vector<uint32_t> first(c->nch + 1);
+    const double K = 4.0 * kPi * c->lB;
+    for (int ch = 0; ch < c->nch; ++ch) {
+        first[ch] = (uint32_t)c->ch_first[ch];
+        const int W = c->ch_width[ch];
+        for (int k = 0; k < W; ++k) {
+            const int zf = c->ch_first[ch] + k;
+            const int zfull = c->slit ? c->ch_full[ch] + 1 + k : zf;
+            PlaneInfo &P = pl[zf];
+            std::memset(&P, 0, sizeof P);
+            P.omega_d = channel_omega_drag(c, ch);
+            P.chan = (uint32_t)ch;
+            P.zfull = (uint32_t)zfull;
+            P.zloc = (uint32_t)(c->slit ? k + 1 : k);
+            if (c->slit) {
+                if (k == 0) { P.walls |= 1u; P.ghost_lo = K * c->ch_sig_lo[ch]; P.lump += c->ch_sig_lo[ch]; }
+                if (k == W - 1) { P.walls |= 2u; P.ghost_hi = K * c->ch_sig_hi[ch]; P.lump += c->ch_sig_hi[ch]; }
+            }
+            fof[zfull] = zf;
+        }
+    }
+    first[c->nch] = (uint32_t)c->nzf;
+    // the tables may be read by work still queued on the stream
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    if ((rc = c->hip(hipMemcpy(c->d_planes, pl.data(), pl.size() * sizeof(PlaneInfo), hipMemcpyHostToDevice), "copy tables")) ||
+        (rc = c->hip(hipMemcpy(c->d_fof, fof.data(), fof.size() * sizeof(int32_t), hipMemcpyHostToDevice), "copy tables")) ||
+        (rc = c->hip(hipMemcpy(c->d_first, first.data(), first.size() * sizeof(uint32_t), hipMemcpyHostToDevice), "copy tables")))
+        return rc;
+    c->tables_dirty = false;
+    drop_graph(c);
+    return LBMIX_OK;
+}
+
+// Per-channel means of v over the fluid into d_chan[off .. off + nch): mode 0 = mean of
+// b = -K (q + lump), mode 1 = plain mean.
+int channel_means(lbmix_ctx *c, const double *v, int mode, int off) {
+    const uint32_t nxy = (uint32_t)c->nx * c->ny;
+    int rc = c->hip(launch_plane_sum(v, nxy, (uint32_t)c->nzf, c->d_psums, c->stream), "plane_sum");
+    if (rc) return rc;
+    return c->hip(launch_channel_means(c->d_psums, c->d_first, (uint32_t)c->nch, c->slit ? c->d_planes : nullptr, nxy,
+                                       mode, 4.0 * kPi * c->lB, c->d_chan + off, c->stream),
+                  "channel_means");
 }
 
 int fetch(lbmix_ctx *c, int count) {
@@ -514,26 +591,32 @@ int spec_build(lbmix_ctx *c) {
     std::vector<double> mu(mux);
     mu.insert(mu.end(), muy.begin(), muy.end());
     if (c->slit) {
-        // zero-flux z: rows of the z system carry diagonal -(2 + mu), -(1 + mu) on the two
-        // end planes (-mu for a single plane)
+        // zero-flux z in every channel: rows of the z system carry diagonal -(2 + mu),
+        // -(1 + mu) on the two end planes of the channel (-mu for a single plane)
         const size_t nm = (size_t)c->nx * c->ny;
         std::vector<double> piv(nm * c->nzf);
-        for (int my = 0; my < c->ny; ++my)
-            for (int mx = 0; mx < c->nx; ++mx) {
-                const size_t m = (size_t)my * c->nx + mx;
-                const double mxy = mux[mx] + muy[my];
-                double prev = 0.0;
-                for (int z = 0; z < c->nzf; ++z) {
-                    const double d = -(2.0 + mxy) + (z == 0 ? 1.0 : 0.0) + (z == c->nzf - 1 ? 1.0 : 0.0);
-                    const bool pin = (m == 0 && z == c->nzf - 1);
-                    prev = pin ? 0.0 : 1.0 / (d - prev);
-                    piv[(size_t)z * nm + m] = prev;
+        for (int ch = 0; ch < c->nch; ++ch) {
+            const int z0 = c->ch_first[ch], W = c->ch_width[ch];
+            for (int my = 0; my < c->ny; ++my)
+                for (int mx = 0; mx < c->nx; ++mx) {
+                    const size_t m = (size_t)my * c->nx + mx;
+                    const double mxy = mux[mx] + muy[my];
+                    double prev = 0.0;
+                    for (int k = 0; k < W; ++k) {
+                        const double d = -(2.0 + mxy) + (k == 0 ? 1.0 : 0.0) + (k == W - 1 ? 1.0 : 0.0);
+                        const bool pin = (m == 0 && k == W - 1);
+                        prev = pin ? 0.0 : 1.0 / (d - prev);
+                        piv[(size_t)(z0 + k) * nm + m] = prev;
+                    }
                 }
-            }
+        }
         if ((rc = upload(c, &c->sp_piv, piv))) return rc;
-        const uint32_t seg[2] = {0u, (uint32_t)c->nzf};
-        if ((rc = c->hip(hipMalloc((void **)&c->sp_seg, sizeof seg), "hipMalloc(direct solve)"))) return rc;
-        if ((rc = c->hip(hipMemcpy(c->sp_seg, seg, sizeof seg, hipMemcpyHostToDevice), "copy(direct solve)")))
+        std::vector<uint32_t> seg(c->nch + 1);
+        for (int ch = 0; ch <= c->nch; ++ch) seg[ch] = ch < c->nch ? (uint32_t)c->ch_first[ch] : (uint32_t)c->nzf;
+        if ((rc = c->hip(hipMalloc((void **)&c->sp_seg, seg.size() * sizeof(uint32_t)), "hipMalloc(direct solve)")))
+            return rc;
+        if ((rc = c->hip(hipMemcpy(c->sp_seg, seg.data(), seg.size() * sizeof(uint32_t), hipMemcpyHostToDevice),
+                         "copy(direct solve)")))
             return rc;
     } else {
         periodic_basis(c->nzf, tz, muz);
@@ -569,16 +652,35 @@ int spec_left(lbmix_ctx *c, const double *T, uint32_t n, uint32_t inner, uint32_
     return c->hip(launch_gemm_f64(g, !inverse, true, c->stream), what);
 }
 
+// The direct solve.  Planes of at most 64 x 64 nodes are transformed in LDS, straight from
+// q (b = -K (q + lump); the projection onto zero channel mean acts on the constant mode
+// only and is applied there); larger planes go through the batched products.
 int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     int rc;
     if ((rc = spec_build(c))) return rc;
     const uint32_t nxy = (uint32_t)c->nx * c->ny;
     double *a = c->sp_a, *b = c->sp_b;
-    if ((rc = c->hip(launch_make_rhs(pa, a, c->stream), "make_rhs"))) return rc;
-    if ((rc = spec_x(c, a, b, false))) return rc;
-    if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, false, "gemm(y)"))) return rc;
+    const bool in_lds = c->nx <= 64 && c->ny <= 64;
+    SpecXY xy{};
+    xy.tx = c->sp_tx; xy.ty = c->sp_ty; xy.planes = c->slit ? c->d_planes : nullptr;
+    xy.K = 4.0 * kPi * c->lB; xy.nx = c->nx; xy.ny = c->ny; xy.nplanes = c->nzf;
+    if (in_lds) {
+        xy.q = c->q; xy.in = nullptr; xy.out = a;
+        if ((rc = c->hip(launch_spec_xy(xy, true, c->stream), "spec_xy"))) return rc;
+    } else {
+        if ((rc = channel_means(c, c->q, 0, 0))) return rc;
+        if ((rc = c->hip(launch_make_rhs(pa, a, c->stream), "make_rhs"))) return rc;
+        if ((rc = spec_x(c, a, b, false))) return rc;
+        if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, false, "gemm(y)"))) return rc;
+    }
     if (c->slit) {
-        if ((rc = c->hip(launch_tridiag_z(a, c->sp_piv, b, nxy, c->sp_seg, 1, c->stream), "tridiag_z"))) return rc;
+        int longest = 0;
+        for (int w : c->ch_width) longest = std::max(longest, w);
+        if (longest <= (int)TRI_LDS_MAX)
+            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_lds");
+        else
+            rc = c->hip(launch_tridiag_z(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_z");
+        if (rc) return rc;
     } else {
         if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, a, b, false, "gemm(z)"))) return rc;
         if ((rc = c->hip(launch_spectral_scale(b, c->sp_mu, c->sp_mu + c->nx, c->sp_mu + c->nx + c->ny, c->nx,
@@ -586,6 +688,10 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
             return rc;
         if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, b, a, true, "gemm(z)"))) return rc;
         std::swap(a, b);
+    }
+    if (in_lds) {
+        xy.q = nullptr; xy.in = b; xy.out = c->psi;
+        return c->hip(launch_spec_xy(xy, false, c->stream), "spec_xy");
     }
     if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, true, "gemm(y)"))) return rc;
     return spec_x(c, a, c->psi, true);
@@ -611,14 +717,24 @@ double fetched_residual(lbmix_ctx *c) {
 }
 
 int solve(lbmix_ctx *c) {
-    uint32_t nb = 0;
-    const double lumps = c->slit ? (c->sig_lo + c->sig_hi) * (double)c->nx * c->ny : 0.0;
-    int rc = c->hip(launch_qsum(c->q, c->Nf, c->partials, &nb, c->stream), "qsum");
-    if (rc) return rc;
-    rc = c->hip(launch_finalize(c->partials, nb, 1, c->dred, 1, 4.0 * kPi * c->lB, lumps, (double)c->Nf, c->stream),
-                "finalize(qsum)");
-    if (rc) return rc;
+    int rc = LBMIX_OK;
     const PoissonArgs pa = c->pargs();
+    if (c->poisson_method == 2) {
+        // direct: exact to rounding, the gauge is part of it; the residual norms of every
+        // check_every-th solve stay on the device for the stats
+        if ((rc = spec_solve(c, pa))) return rc;
+        if (c->direct_count++ % c->sor_check == 0) {
+            if ((rc = channel_means(c, c->q, 0, 0)) || (rc = residual(c, pa))) return rc;
+            c->resid_on_device = true;
+        }
+        c->last_sweeps = 1;
+        c->last_status = LBMIX_OK;
+        c->total_sweeps += 1;
+        c->solves++;
+        c->psi_valid = true;
+        return LBMIX_OK;
+    }
+    if ((rc = channel_means(c, c->q, 0, 0))) return rc;
     // warm start: the previous potential, or psi(t-1) + psi(t-2) - psi(t-3) once three
     // solutions exist (exact for a linear trend plus a period-two oscillation in time)
     if (c->warm_start == 1 && c->psi_valid && c->poisson_method != 2) {
@@ -641,12 +757,7 @@ int solve(lbmix_ctx *c) {
         }
     }
     int work = 0, status = LBMIX_OK;
-    if (c->poisson_method == 2) {
-        // direct: exact to rounding; the residual norms stay on the device for the stats
-        if ((rc = spec_solve(c, pa)) || (rc = residual(c, pa))) return rc;
-        work = 1;
-        c->resid_on_device = true;
-    } else if (c->poisson_method == 1) {
+    if (c->poisson_method == 1) {
         // multigrid: each V-cycle is one graph replay that also leaves the residual norms of
         // its result in dred[4..7]; the first (previous count - 1) cycles run without reading
         // them back, since they are expected to be needed
@@ -715,8 +826,11 @@ int solve(lbmix_ctx *c) {
             c->resid_on_device = true;
         }
     }
-    // zero-mean gauge with the mean of the final psi (dred[7])
-    rc = c->hip(launch_shift(c->psi, c->Nf, c->dred + 7, c->stream), "shift(psi)");
+    // zero-mean gauge per channel
+    if ((rc = channel_means(c, c->psi, 1, c->nch))) return rc;
+    rc = c->hip(launch_shift_planes(c->psi, (uint32_t)c->nx * c->ny, c->Nf, c->slit ? c->d_planes : nullptr,
+                                    c->d_chan + c->nch, c->stream),
+                "shift(psi)");
     if (rc) return rc;
     c->last_sweeps = work;
     c->last_status = status;
@@ -746,7 +860,7 @@ int check_ready(lbmix_ctx *c) {
 
 bool redblack_extents(const lbmix_ctx *c) {
     auto bad_extent = [](int n) { return n > 1 && (n % 2) != 0; };
-    return !(bad_extent(c->nx) || bad_extent(c->ny) || (!c->slit && bad_extent(c->nz)));
+    return !(bad_extent(c->nx) || bad_extent(c->ny) || (!c->slit && bad_extent(c->nz)));   // walls cut z
 }
 
 int validate_start(lbmix_ctx *c) {
@@ -754,15 +868,23 @@ int validate_start(lbmix_ctx *c) {
     if (c->poisson_method != 2 && !redblack_extents(c))
         return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR and "
                                      "multigrid (the direct solve takes any)");
-    double qtot = 0.0, scale = 0.0;
-    for (int s = 0; s < c->ns; ++s) {
-        qtot += c->valence[s] * c->host_total[s];
-        scale += std::fabs((double)c->valence[s]) * c->host_total[s];
+    if (c->poisson_method == 1 && c->nch > 1)
+        return c->fail(LBMIX_EINVAL, "multigrid solves a single lattice; use SOR or the direct solve for channels");
+    const double area = (double)c->nx * c->ny;
+    for (int ch = 0; ch < c->nch; ++ch) {   // every channel is neutral on its own
+        double qtot = 0.0, scale = 0.0;
+        for (int s = 0; s < c->ns; ++s) {
+            const double t = c->ch_total[(size_t)s * c->nch + ch];
+            qtot += c->valence[s] * t;
+            scale += std::fabs((double)c->valence[s]) * t;
+        }
+        const double lo = c->slit ? c->ch_sig_lo[ch] : 0.0, hi = c->slit ? c->ch_sig_hi[ch] : 0.0;
+        const double wall = (lo + hi) * area;
+        scale = std::max(scale, (std::fabs(lo) + std::fabs(hi)) * area);
+        if (std::fabs(qtot + wall) > 1e-9 * scale)
+            return c->fail(LBMIX_EINVAL, "channel %d is not neutral: fluid charge %.17g, wall charge %.17g", ch, qtot,
+                           wall);
     }
-    const double wall = c->slit ? (c->sig_lo + c->sig_hi) * (double)c->nx * c->ny : 0.0;
-    scale = std::max(scale, std::fabs(c->sig_lo * c->nx * c->ny) + std::fabs(c->sig_hi * c->nx * c->ny));
-    if (std::fabs(qtot + wall) > 1e-9 * scale)
-        return c->fail(LBMIX_EINVAL, "system is not neutral: fluid charge %.17g, wall charge %.17g", qtot, wall);
     return LBMIX_OK;
 }
 
@@ -781,7 +903,7 @@ struct Guard {   // make the context's device current for the duration of a call
 
 struct Header {
     char magic[8];
-    int32_t version, nx, ny, nz, geometry, storage, ns, valence[MAXS];
+    int32_t version, nx, ny, nz, geometry, storage, ns, nch, valence[MAXS];
     double rho0[MAXS], rel_range[MAXS], host_total[MAXS];
     double tau_v, tau_d, sc;
     int32_t drag_from_sc, sor_max, sor_check, psi_valid, rounding, poisson_method;
@@ -799,24 +921,47 @@ extern "C" {
 
 int lbmix_version(void) { return 10000; }
 
-int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage, void *hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Context of nx * ny lateral nodes and channels of the given fluid widths along z (walls
+// around each), or one periodic box of widths[0] planes.
+int create_ctx(lbmix_ctx **out, int nx, int ny, int geometry, const std::vector<int> &widths, int storage,
+               void *hip_stream) {
     if (!out) return LBMIX_EINVAL;
     *out = nullptr;
-    if (nx < 1 || ny < 1 || nz < 1) return LBMIX_EINVAL;
-    if (geometry != LBMIX_PERIODIC && geometry != LBMIX_SLIT_Z) return LBMIX_EINVAL;
-    if (geometry == LBMIX_SLIT_Z && nz < 3) return LBMIX_EINVAL;
+    if (nx < 1 || ny < 1 || widths.empty()) return LBMIX_EINVAL;
     if (storage < LBMIX_F64 || storage > LBMIX_F16_SHIFTED) return LBMIX_EINVAL;
-    const int nzf = geometry == LBMIX_SLIT_Z ? nz - 2 : nz;
-    const double nodes = (double)nx * ny * nz;
-    if (nodes > 2147483647.0) return LBMIX_EINVAL;
+    const bool walls = geometry != LBMIX_PERIODIC;
+    double nz = 0, nzf = 0;
+    for (int w : widths) {
+        if (w < 1) return LBMIX_EINVAL;
+        nz += w + (walls ? 2 : 0);
+        nzf += w;
+    }
+    if ((double)nx * ny * nz > 2147483647.0) return LBMIX_EINVAL;
     lbmix_ctx *c = new (std::nothrow) lbmix_ctx();
     if (!c) return LBMIX_ENOMEM;
     c->nx = nx;
     c->ny = ny;
-    c->nz = nz;
-    c->nzf = nzf;
+    c->nz = (int)nz;
+    c->nzf = (int)nzf;
     c->geometry = geometry;
-    c->slit = geometry == LBMIX_SLIT_Z;
+    c->slit = walls;
+    c->nch = (int)widths.size();
+    c->ch_width = widths;
+    int f = 0, full = 0;
+    for (int w : widths) {
+        c->ch_first.push_back(f);
+        c->ch_full.push_back(full);
+        f += w;
+        full += w + (walls ? 2 : 0);
+    }
+    c->ch_tau_d.assign(c->nch, 0.0);
+    c->ch_sig_lo.assign(c->nch, 0.0);
+    c->ch_sig_hi.assign(c->nch, 0.0);
+    c->ch_total.assign((size_t)MAXS * c->nch, 0.0);
     c->storage = storage;
     switch (storage) {
         case LBMIX_F64: c->st = Store::F64; c->esize = 8; break;
@@ -825,12 +970,47 @@ int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int stor
         case LBMIX_BF16_SHIFTED: c->st = Store::BF16; c->esize = 2; break;
         default: c->st = Store::F16; c->esize = 2; break;
     }
-    c->Nf = (uint32_t)((size_t)nx * ny * nzf);
-    c->Nfull = (size_t)nx * ny * nz;
+    c->Nf = (uint32_t)((size_t)nx * ny * c->nzf);
+    c->Nfull = (size_t)nx * ny * c->nz;
     c->stream = static_cast<hipStream_t>(hip_stream);
     for (int s = 0; s < MAXS; ++s) c->rel_range[s] = 0.1;
     c->compute_scales();
     *out = c;
+    return LBMIX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage, void *hip_stream) {
+    if (out) *out = nullptr;
+    if (geometry != LBMIX_PERIODIC && geometry != LBMIX_SLIT_Z) return LBMIX_EINVAL;
+    if (nz < (geometry == LBMIX_SLIT_Z ? 3 : 1)) return LBMIX_EINVAL;
+    return create_ctx(out, nx, ny, geometry, {geometry == LBMIX_SLIT_Z ? nz - 2 : nz}, storage, hip_stream);
+}
+
+int lbmix_create_channels(lbmix_ctx **out, int nx, int ny, int nchannels, const int *widths, int storage,
+                          void *hip_stream) {
+    if (out) *out = nullptr;
+    if (nchannels < 1 || !widths) return LBMIX_EINVAL;
+    return create_ctx(out, nx, ny, LBMIX_CHANNELS, std::vector<int>(widths, widths + nchannels), storage,
+                      hip_stream);
+}
+
+int lbmix_set_channel(lbmix_ctx *c, int channel, double tau_drag, double sigma_lo, double sigma_hi) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (c->geometry != LBMIX_CHANNELS) return c->fail(LBMIX_EINVAL, "not a channel stack (lbmix_create_channels)");
+    if (channel < 0 || channel >= c->nch) return c->fail(LBMIX_EINVAL, "bad channel index");
+    if (!std::isfinite(tau_drag) || (tau_drag > 0.0 && !(tau_drag > 0.5)) || !std::isfinite(sigma_lo) ||
+        !std::isfinite(sigma_hi))
+        return c->fail(LBMIX_EINVAL, "bad channel parameters (tau_drag > 1/2, or <= 0 for the context's)");
+    c->ch_tau_d[channel] = tau_drag > 0.0 ? tau_drag : 0.0;
+    c->ch_sig_lo[channel] = sigma_lo;
+    c->ch_sig_hi[channel] = sigma_hi;
+    c->tables_dirty = true;
+    c->psi_valid = false;
     return LBMIX_OK;
 }
 
@@ -852,6 +1032,7 @@ int lbmix_set_tau_visc(lbmix_ctx *c, double tau) {
     if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
     if (!(tau > 0.5) || !std::isfinite(tau)) return c->fail(LBMIX_EINVAL, "tau_visc must exceed 1/2");
     c->tau_v = tau;
+    c->tables_dirty = true;
     return LBMIX_OK;
 }
 
@@ -861,6 +1042,7 @@ int lbmix_set_tau_drag(lbmix_ctx *c, double tau) {
     if (!(tau > 0.5) || !std::isfinite(tau)) return c->fail(LBMIX_EINVAL, "tau_drag must exceed 1/2");
     c->tau_d = tau;
     c->drag_from_sc = false;
+    c->tables_dirty = true;
     return LBMIX_OK;
 }
 
@@ -870,6 +1052,7 @@ int lbmix_set_schmidt(lbmix_ctx *c, double sc) {
     if (!(sc > 0.0) || !std::isfinite(sc)) return c->fail(LBMIX_EINVAL, "Schmidt number must be positive");
     c->sc = sc;
     c->drag_from_sc = true;
+    c->tables_dirty = true;
     return LBMIX_OK;
 }
 
@@ -885,6 +1068,11 @@ int lbmix_set_electrostatics(lbmix_ctx *c, double bjerrum, double sigma_lo, doub
     c->lB = bjerrum;
     c->sig_lo = sigma_lo;
     c->sig_hi = sigma_hi;
+    if (c->geometry == LBMIX_SLIT_Z) {
+        c->ch_sig_lo[0] = sigma_lo;
+        c->ch_sig_hi[0] = sigma_hi;
+    }
+    c->tables_dirty = true;
     for (int d = 0; d < 3; ++d) c->E[d] = E ? E[d] : 0.0;
     c->psi_valid = false;
     return LBMIX_OK;
@@ -905,6 +1093,7 @@ int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_ev
 int lbmix_set_poisson_method(lbmix_ctx *c, int method) {
     if (!c) return LBMIX_EINVAL;
     if (method < 0 || method > 2) return c->fail(LBMIX_EINVAL, "Poisson method is 0 (SOR), 1 (multigrid) or 2 (direct)");
+    if (method == 1 && c->nch > 1) return c->fail(LBMIX_EINVAL, "multigrid solves a single lattice, not channels");
     if (c->started && method != 2 && c->charged() && !redblack_extents(c))
         return c->fail(LBMIX_EINVAL, "SOR and multigrid need even periodic extents (or 1)");
     drop_graph(c);
@@ -946,11 +1135,17 @@ int lbmix_set_state(lbmix_ctx *c, int s, const double *n, const double *u) {
     int rc = allocate(c);
     if (rc) return rc;
     Guard g(c);
+    if ((rc = ensure_tables(c))) return rc;
     double tot = 0.0;
-    for (size_t i = 0; i < c->Nfull; ++i) {
-        const int z = (int)(i / ((size_t)c->nx * c->ny));
-        if (c->slit && (z == 0 || z == c->nz - 1)) continue;
-        tot += n[i];
+    const size_t plane = (size_t)c->nx * c->ny;
+    for (int ch = 0; ch < c->nch; ++ch) {   // channel totals in plane order
+        double t = 0.0;
+        for (int k = 0; k < c->ch_width[ch]; ++k) {
+            const size_t z = (size_t)(c->slit ? c->ch_full[ch] + 1 + k : c->ch_first[ch] + k);
+            for (size_t i = 0; i < plane; ++i) t += n[z * plane + i];
+        }
+        c->ch_total[(size_t)s * c->nch + ch] = t;
+        tot += t;
     }
     double *dn = nullptr, *du = nullptr;
     rc = c->hip(hipMalloc((void **)&dn, c->Nfull * sizeof(double)), "hipMalloc(staging)");
@@ -988,6 +1183,7 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
     if (nsteps < 0) return c->fail(LBMIX_EINVAL, "negative step count");
     if (c->latched) return c->fail(c->latched, "context latched an earlier error (%d)", c->latched);
     Guard g(c);
+    if ((rc = ensure_tables(c))) return rc;
     if (!c->started) {
         if ((rc = validate_start(c))) return rc;
         c->started = true;
@@ -1020,6 +1216,10 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
 int lbmix_get_moments_device(lbmix_ctx *c, int s, double *n_dev, double *j_dev) {
     int rc = check_ready(c);
     if (rc) return rc;
+    {
+        Guard g0(c);
+        if ((rc = ensure_tables(c))) return rc;
+    }
     if (s < 0 || s >= c->ns) return c->fail(LBMIX_EINVAL, "bad species index");
     Guard g(c);
     const StepArgs a = c->args();
@@ -1034,6 +1234,10 @@ int lbmix_get_moments_device(lbmix_ctx *c, int s, double *n_dev, double *j_dev) 
 int lbmix_get_moments(lbmix_ctx *c, int s, double *n_out, double *j_out) {
     int rc = check_ready(c);
     if (rc) return rc;
+    {
+        Guard g0(c);
+        if ((rc = ensure_tables(c))) return rc;
+    }
     if (s < 0 || s >= c->ns) return c->fail(LBMIX_EINVAL, "bad species index");
     Guard g(c);
     if ((rc = ensure_scratch(c, 4 * c->Nfull * sizeof(double)))) return rc;
@@ -1050,6 +1254,10 @@ int lbmix_get_moments(lbmix_ctx *c, int s, double *n_out, double *j_out) {
 int lbmix_get_populations(lbmix_ctx *c, int s, double *f_out) {
     int rc = check_ready(c);
     if (rc) return rc;
+    {
+        Guard g0(c);
+        if ((rc = ensure_tables(c))) return rc;
+    }
     if (s < 0 || s >= c->ns || !f_out) return c->fail(LBMIX_EINVAL, "bad species index or null output");
     Guard g(c);
     if ((rc = ensure_scratch(c, (size_t)Q * c->Nfull * sizeof(double)))) return rc;
@@ -1067,21 +1275,32 @@ int lbmix_get_potential(lbmix_ctx *c, double *psi_out) {
     Guard g(c);
     std::memset(psi_out, 0, c->Nfull * sizeof(double));
     if (!c->charged()) return LBMIX_OK;
+    if ((rc = ensure_tables(c))) return rc;
     if (!c->psi_valid) {
         if (!c->started) {
             if ((rc = validate_start(c))) return rc;
         }
         if ((rc = initial_potential(c))) return rc;
     }
-    const size_t off = c->slit ? (size_t)c->nx * c->ny : 0;
-    if ((rc = c->hip(hipMemcpyAsync(psi_out + off, c->psi, (size_t)c->Nf * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy psi")))
-        return rc;
+    const size_t plane = (size_t)c->nx * c->ny;
+    for (int ch = 0; ch < c->nch; ++ch) {   // each channel's fluid planes into place
+        const size_t zf = (size_t)c->ch_first[ch], zfull = (size_t)(c->slit ? c->ch_full[ch] + 1 : c->ch_first[ch]);
+        if ((rc = c->hip(hipMemcpyAsync(psi_out + zfull * plane, c->psi + zf * plane,
+                                        (size_t)c->ch_width[ch] * plane * sizeof(double), hipMemcpyDeviceToHost,
+                                        c->stream),
+                         "copy psi")))
+            return rc;
+    }
     return c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
 }
 
 int lbmix_get_mass_totals(lbmix_ctx *c, double *totals) {
     int rc = check_ready(c);
     if (rc) return rc;
+    {
+        Guard g0(c);
+        if ((rc = ensure_tables(c))) return rc;
+    }
     if (!totals) return c->fail(LBMIX_EINVAL, "null output");
     Guard g(c);
     if ((rc = ensure_scratch(c, c->Nfull * sizeof(double)))) return rc;
@@ -1111,6 +1330,10 @@ int lbmix_get_mass_totals(lbmix_ctx *c, double *totals) {
 int lbmix_get_zprofiles(lbmix_ctx *c, double *out) {
     int rc = check_ready(c);
     if (rc) return rc;
+    {
+        Guard g0(c);
+        if ((rc = ensure_tables(c))) return rc;
+    }
     if (!out) return c->fail(LBMIX_EINVAL, "null output");
     Guard g(c);
     if ((rc = ensure_scratch(c, (4 * c->Nfull + 4 * (size_t)c->nz * MAXS) * sizeof(double)))) return rc;
@@ -1164,8 +1387,9 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 1;
+    h.version = 2;
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
+    h.nch = c->nch;
     for (int s = 0; s < MAXS; ++s) {
         h.valence[s] = c->valence[s];
         h.rho0[s] = c->rho0[s];
@@ -1186,9 +1410,20 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
         (rc = c->hip(hipMemcpyAsync(ps.data(), c->psi, c->Nf * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy psi")))
         return rc;
     if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    // per channel: width, drag, wall charges, initial totals of every species
+    std::vector<double> chan;
+    for (int ch = 0; ch < c->nch; ++ch) {
+        chan.push_back(c->ch_width[ch]);
+        chan.push_back(c->ch_tau_d[ch]);
+        chan.push_back(c->ch_sig_lo[ch]);
+        chan.push_back(c->ch_sig_hi[ch]);
+        for (int s = 0; s < MAXS; ++s) chan.push_back(c->ch_total[(size_t)s * c->nch + ch]);
+    }
     FILE *fp = std::fopen(path, "wb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
-    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 && std::fwrite(buf.data(), 1, pop, fp) == pop;
+    bool ok = std::fwrite(&h, sizeof h, 1, fp) == 1 &&
+              std::fwrite(chan.data(), sizeof(double), chan.size(), fp) == chan.size() &&
+              std::fwrite(buf.data(), 1, pop, fp) == pop;
     if (ok && h.psi_valid) ok = std::fwrite(ps.data(), sizeof(double), ps.size(), fp) == ps.size();
     ok = (std::fclose(fp) == 0) && ok;
     return ok ? LBMIX_OK : c->fail(LBMIX_EINVAL, "write to %s failed", path);
@@ -1199,9 +1434,13 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 1;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 2;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
-         h.storage == c->storage && h.ns == c->ns;
+         h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
+    constexpr int kPerChan = 4 + MAXS;
+    std::vector<double> chan(ok ? (size_t)kPerChan * c->nch : 0);
+    ok = ok && std::fread(chan.data(), sizeof(double), chan.size(), fp) == chan.size();
+    for (int ch = 0; ok && ch < c->nch; ++ch) ok = (int)chan[(size_t)kPerChan * ch] == c->ch_width[ch];
     for (int s = 0; ok && s < c->ns; ++s) ok = h.valence[s] == c->valence[s] && h.rho0[s] == c->rho0[s];
     if (!ok) {
         std::fclose(fp);
@@ -1227,6 +1466,16 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     c->rounding = h.rounding; c->round_seed = h.round_seed; c->poisson_method = h.poisson_method;
     c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
+    for (int ch = 0; ch < c->nch; ++ch) {
+        const double *v = chan.data() + (size_t)kPerChan * ch;
+        c->ch_tau_d[ch] = v[1];
+        c->ch_sig_lo[ch] = v[2];
+        c->ch_sig_hi[ch] = v[3];
+        for (int s = 0; s < MAXS; ++s) c->ch_total[(size_t)s * c->nch + ch] = v[4 + s];
+    }
+    c->tables_dirty = true;
+    drop_graph(c);
+    if ((rc = ensure_tables(c))) return rc;
     if ((rc = c->hip(hipMemcpyAsync(c->f[c->cur], buf.data(), pop, hipMemcpyHostToDevice, c->stream), "copy f"))) return rc;
     if (h.psi_valid) {
         if ((rc = ensure_field_buffers(c))) return rc;
@@ -1266,6 +1515,9 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (double *p : {c->sp_tx, c->sp_ty, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
+        for (void *p : {(void *)c->d_planes, (void *)c->d_fof, (void *)c->d_first, (void *)c->d_chan,
+                        (void *)c->d_psums})
+            if (p) (void)hipFree(p);
         for (size_t l = 1; l < c->mg.size(); ++l) {
             (void)hipFree(c->mg[l].e);
             (void)hipFree(c->mg[l].r);

@@ -14,6 +14,19 @@ constexpr int STEP_BLOCK = 512;   // threads per work-group of stream_collide (t
 
 enum class Store : int { F64 = 0, F32 = 1, BF16 = 2, F16 = 3 };
 
+// One fluid plane of a geometry with walls (a slit, or a stack of slit channels along z that
+// share the lateral extent): its wall neighbours, its channel and the channel's parameters.
+struct PlaneInfo {
+    double omega_d;       // drag frequency of the channel
+    double ghost_lo;      // 4 pi l_B sigma of the wall below (used when walls & 1)
+    double ghost_hi;      // 4 pi l_B sigma of the wall above (used when walls & 2)
+    double lump;          // wall charge per node lumped into this plane (Poisson)
+    uint32_t walls;       // bit 0: the plane below is a wall; bit 1: the plane above is a wall
+    uint32_t chan;        // channel index
+    uint32_t zfull;       // index of the plane in the full-lattice arrays
+    uint32_t zloc;        // index of the plane in its own channel's lattice (walls counted)
+};
+
 // Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
 // over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
 // storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
@@ -32,13 +45,17 @@ struct StepArgs {
     const double *psi;               // potential on fluid nodes (charged runs)
     double *q;                       // out: charge density on fluid nodes (charged runs)
     double q_rest;                   // sum_s valence_s * rho_bar_s
-    double ghost_lo, ghost_hi;       // 4 pi l_B sigma of the walls z = 0 and z = nz-1
+    const PlaneInfo *planes;         // [nzf] for geometries with walls (null for the box)
+    const int32_t *fluid_of_full;    // [nzfull]: fluid plane of a full-lattice plane, -1 = wall
+    uint32_t nzfull;                 // planes of the full-lattice arrays
     double *partials;                // out: [species][block] FP64 sums of n - rho_bar
     int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
     uint32_t seed;                   // per-step seed of the rounding hash
 };
 
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
+// Work-group shape of stream_collide: rows of up to 256 nodes along x, two rows per
+// work-group; a plane narrower than 64 nodes packs 512 / nx rows into one work-group.
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
 
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,

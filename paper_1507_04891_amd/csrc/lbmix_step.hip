@@ -9,12 +9,14 @@
 // in FP32), so there are no matrix-core contractions; the design goals are coalesced
 // streams, no re-reads, and no LDS round trips.
 //
-// Work-group shape: 256 threads along x (fewer when nx < 256) times two rows, so y, z and
-// every bounce-back decision are wave-uniform and the x-shifted loads of a row stay in one
-// work-group (and one L2).  Populations are interleaved by species, so each direction is one
-// non-temporal vector load and one vector store of all species.  All arithmetic is done on deviations d_p = f_p - w_p
-// rho_bar, which makes the shifted storage forms exact in their range and costs nothing
-// for the plain ones (rho_bar = 0).
+// Work-group shape: 256 threads along x (fewer when nx < 256) times two rows, so z and every
+// bounce-back decision are uniform per work-group (y too per wave when nx >= 64), and the
+// x-shifted loads of a row stay in one work-group (and one L2).  Planes with walls (a slit,
+// or a stack of channels) read their wall flags and channel parameters from a per-plane
+// table.  Populations are interleaved by species, so each direction is one non-temporal
+// vector load and one vector store of all species.  All arithmetic is done on deviations
+// d_p = f_p - w_p rho_bar, which makes the shifted storage forms exact in their range and
+// costs nothing for the plain ones (rho_bar = 0).
 #include "lbmix_step.h"
 #include "lbmix_device.h"
 
@@ -195,7 +197,7 @@ struct Pull {
     uint32_t nx, ny;
 
     __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx_, uint32_t ny_, uint32_t nzf,
-                    bool slit)
+                    uint32_t walls)
         : xs(x), y(y_), z(z_), nx(nx_), ny(ny_) {
         xm = (x == 0) ? nx - 1 : x - 1;
         xp = (x + 1 == nx) ? 0 : x + 1;
@@ -203,8 +205,8 @@ struct Pull {
         yp = (y + 1 == ny) ? 0 : y + 1;
         zm = (z == 0) ? nzf - 1 : z - 1;
         zp = (z + 1 == nzf) ? 0 : z + 1;
-        bb_lo = slit && z == 0;
-        bb_hi = slit && z + 1 == nzf;
+        bb_lo = (walls & 1u) != 0;
+        bb_hi = (walls & 2u) != 0;
     }
     __device__ uint32_t own() const { return (z * ny + y) * nx + xs; }
     // slot direction and node of the value that direction p pulls
@@ -229,9 +231,11 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     using C = typename CD::C;
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;   // uniform per wave
+    const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;   // uniform per wave if nx >= 64
     const bool active = x < a.nx && y < a.ny;
-    const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const uint32_t z = blockIdx.z;
+    const uint32_t walls = SLIT ? a.planes[z].walls : 0u;   // uniform per work-group
+    const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, z, a.nx, a.ny, a.nzf, walls);
     const uint32_t own = pl.own();
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
@@ -295,8 +299,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             const double here = psi[row + pl.xs];
             gx = 0.5 * (psi[row + pl.xp] - psi[row + pl.xm]);
             gy = 0.5 * (psi[(pl.z * a.ny + pl.yp) * a.nx + pl.xs] - psi[(pl.z * a.ny + pl.ym) * a.nx + pl.xs]);
-            const double up = pl.bb_hi ? here + a.ghost_hi : psi[(pl.zp * a.ny + pl.y) * a.nx + pl.xs];
-            const double dw = pl.bb_lo ? here + a.ghost_lo : psi[(pl.zm * a.ny + pl.y) * a.nx + pl.xs];
+            const double up = (SLIT && pl.bb_hi) ? here + a.planes[z].ghost_hi : psi[(pl.zp * a.ny + pl.y) * a.nx + pl.xs];
+            const double dw = (SLIT && pl.bb_lo) ? here + a.planes[z].ghost_lo : psi[(pl.zm * a.ny + pl.y) * a.nx + pl.xs];
             gz = 0.5 * (up - dw);
         }
         constexpr double cs2 = 1.0 / 3.0;
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     // 4. forces per species: drag on mid-step velocities plus the field force,
     //    F_s = -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s, then the coefficients of the
     //    collision that are common to every direction
-    const C ov = C(a.omega_v), od = C(a.omega_d);
+    const C ov = C(a.omega_v), od = C(SLIT ? a.planes[z].omega_d : a.omega_d);
     C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS], base[NS], ov45[NS], n9[NS], n3[NS];
     C bhi[NS][3], blo[NS][3];   // w ov dn (FP64) split hi + lo for the three weight classes
 #pragma unroll
@@ -422,9 +426,9 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
-    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
-    const size_t Nfull = (size_t)a.nx * a.ny * (SLIT ? a.nzf + 2 : a.nzf);
-    const size_t fi = ((size_t)(SLIT ? pl.z + 1 : pl.z) * a.ny + pl.y) * a.nx + x;
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u);
+    const size_t Nfull = (size_t)a.nx * a.ny * a.nzfull;
+    const size_t fi = ((size_t)(SLIT ? a.planes[pl.z].zfull : pl.z) * a.ny + pl.y) * a.nx + x;
     const double n = nf[fi];
     const double ux = uf ? uf[fi] : 0.0, uy = uf ? uf[Nfull + fi] : 0.0, uz = uf ? uf[2 * Nfull + fi] : 0.0;
     const double uu = ux * ux + uy * uy + uz * uz;
@@ -449,10 +453,10 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
     const uint32_t zfull = blockIdx.z;
-    const uint32_t nzfull = SLIT ? a.nzf + 2 : a.nzf;
-    const size_t Nfull = (size_t)a.nx * a.ny * nzfull;
+    const size_t Nfull = (size_t)a.nx * a.ny * a.nzfull;
     const size_t fi = ((size_t)zfull * a.ny + blockIdx.y) * a.nx + x;
-    if (SLIT && (zfull == 0 || zfull == nzfull - 1)) {
+    const int32_t zf = SLIT ? a.fluid_of_full[zfull] : (int32_t)zfull;
+    if (zf < 0) {
         if constexpr (MODE == 0) {
             out0[fi] = 0.0;
             if (out1) out1[fi] = out1[Nfull + fi] = out1[2 * Nfull + fi] = 0.0;
@@ -461,7 +465,7 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
         }
         return;
     }
-    const Pull pl(x, blockIdx.y, SLIT ? zfull - 1 : zfull, a.nx, a.ny, a.nzf, SLIT);
+    const Pull pl(x, blockIdx.y, (uint32_t)zf, a.nx, a.ny, a.nzf, SLIT ? a.planes[zf].walls : 0u);
     const S *fin = static_cast<const S *>(a.fin);
     double m0 = 0, mx = 0, my = 0, mz = 0;
     static_for<Q>([&](auto pc) {
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
-    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT);
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u);
     const S *fin = static_cast<const S *>(a.fin);
     double qq = a.q_rest;
     for (int s = 0; s < ns; ++s) {
@@ -552,9 +556,16 @@ static hipError_t sc_ns(int ns, bool slit, bool field, bool charged, const StepA
 }
 
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block) {
-    uint32_t bx = ((nx + 63) / 64) * 64;
-    if (bx > BLOCK) bx = BLOCK;
-    const uint32_t by = STEP_BLOCK / BLOCK;   // rows per work-group (two rows of 256 measured best)
+    uint32_t bx, by;
+    if (nx < 64) {   // narrow plane: whole rows, as many as fill the work-group
+        bx = nx;
+        by = STEP_BLOCK / nx;
+        if (by > ny) by = ny;
+    } else {
+        bx = ((nx + 63) / 64) * 64;
+        if (bx > BLOCK) bx = BLOCK;
+        by = STEP_BLOCK / BLOCK;   // rows per work-group (two rows of 256 measured best)
+    }
     *block = dim3(bx, by, 1);
     return dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nzf);
 }
@@ -595,7 +606,7 @@ template <class T, bool SLIT> struct InitK {
 template <class T, bool SLIT> struct MomK {
     static hipError_t go(int s, const StepArgs &a, double *n, double *j, hipStream_t st) {
         dim3 b;
-        const dim3 g = node_grid(a.nx, a.ny, SLIT ? a.nzf + 2 : a.nzf, &b);
+        const dim3 g = node_grid(a.nx, a.ny, a.nzfull, &b);
         hipLaunchKernelGGL((gather<T, SLIT, 0>), g, b, 0, st, a, s, n, j);
         return hipGetLastError();
     }
@@ -603,7 +614,7 @@ template <class T, bool SLIT> struct MomK {
 template <class T, bool SLIT> struct PopK {
     static hipError_t go(int s, const StepArgs &a, double *f, hipStream_t st) {
         dim3 b;
-        const dim3 g = node_grid(a.nx, a.ny, SLIT ? a.nzf + 2 : a.nzf, &b);
+        const dim3 g = node_grid(a.nx, a.ny, a.nzfull, &b);
         hipLaunchKernelGGL((gather<T, SLIT, 1>), g, b, 0, st, a, s, f, (double *)nullptr);
         return hipGetLastError();
     }

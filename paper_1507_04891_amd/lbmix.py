@@ -15,19 +15,20 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbmix.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
-PERIODIC, SLIT_Z = 0, 1
+PERIODIC, SLIT_Z, CHANNELS = 0, 1, 2
 F64, F32, F32_SHIFTED, BF16_SHIFTED, F16_SHIFTED = 0, 1, 2, 3, 4
 STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "f16s": F16_SHIFTED}
-GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z}
+GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z, "channels": CHANNELS}
 POISSON = {"sor": 0, "multigrid": 1, "direct": 2}
 WARM_START = {"previous": 0, "extrapolated": 1}
 ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
 Q = 19
 MAX_SPECIES = 4
 EXPORTS = (
-    "lbmix_version", "lbmix_create", "lbmix_add_species", "lbmix_set_tau_visc",
-    "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics", "lbmix_set_poisson",
-    "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding", "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_version", "lbmix_create", "lbmix_create_channels", "lbmix_set_channel", "lbmix_add_species",
+    "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics",
+    "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
+    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
@@ -67,6 +68,9 @@ def load_library():
         "lbmix_version": ([], ctypes.c_int),
         "lbmix_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                           ctypes.c_int, vp], ctypes.c_int),
+        "lbmix_create_channels": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ctypes.c_int,
+                                   vp], ctypes.c_int),
+        "lbmix_set_channel": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double], ctypes.c_int),
         "lbmix_add_species": ([vp, ctypes.c_double, ctypes.c_int, ip], ctypes.c_int),
         "lbmix_set_tau_visc": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_tau_drag": ([vp, ctypes.c_double], ctypes.c_int),
@@ -114,12 +118,13 @@ def _f64(a, shape):
 class Lattice:
     """A lattice of the GPU library.
 
-    geometry: "periodic" or "slit" (solid planes z = 0 and z = nz-1).
+    geometry: "periodic", "slit" (solid planes z = 0 and z = nz-1) or "channels" (a stack of
+    slit channels of fluid widths `widths`; nz is then sum(widths) + 2 len(widths)).
     storage: "f64", "f32", "f32s", "bf16s", "f16s" (see lbmix_storage).
     stream: a torch.cuda.Stream, a raw hipStream_t integer, or None for torch's current stream.
     """
 
-    def __init__(self, nx, ny, nz, geometry="periodic", storage="f64", stream=None):
+    def __init__(self, nx, ny, nz=None, geometry="periodic", storage="f64", stream=None, widths=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the lbmix library has no CPU path")
@@ -128,13 +133,21 @@ class Lattice:
             stream = torch.cuda.current_stream()
         handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
         self.stream_handle = handle
+        h = ctypes.c_void_p()
+        if geometry == "channels":
+            widths = [int(w) for w in widths]
+            nz = sum(w + 2 for w in widths)
+            wa = (ctypes.c_int * len(widths))(*widths)
+            rc = self._L.lbmix_create_channels(ctypes.byref(h), nx, ny, len(widths), wa, STORAGE[storage],
+                                               ctypes.c_void_p(handle))
+        else:
+            rc = self._L.lbmix_create(ctypes.byref(h), nx, ny, nz, GEOMETRY[geometry], STORAGE[storage],
+                                      ctypes.c_void_p(handle))
         self.shape = (nz, ny, nx)
         self.nx, self.ny, self.nz = nx, ny, nz
         self.geometry = geometry
+        self.widths = widths
         self.storage = storage
-        h = ctypes.c_void_p()
-        rc = self._L.lbmix_create(ctypes.byref(h), nx, ny, nz, GEOMETRY[geometry], STORAGE[storage],
-                                  ctypes.c_void_p(handle))
         if rc:
             raise LbmixError(rc, "lbmix_create rejected the lattice")
         self._h = h
@@ -177,6 +190,9 @@ class Lattice:
         e = (ctypes.c_double * 3)(*[float(v) for v in E])
         self._check(self._L.lbmix_set_electrostatics(self._h, float(bjerrum), float(sigma_lo),
                                                      float(sigma_hi), e))
+
+    def set_channel(self, c, tau_drag=0.0, sigma_lo=0.0, sigma_hi=0.0):
+        self._check(self._L.lbmix_set_channel(self._h, int(c), float(tau_drag), float(sigma_lo), float(sigma_hi)))
 
     def set_poisson(self, rel_tol=1e-8, max_sweeps=200000, check_every=10, omega=-1.0, method="sor",
                     warm_start="previous"):
@@ -263,17 +279,26 @@ class Lattice:
 
 
 def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0):
-    """Build a Lattice from a workloads.Workload description (parameters and initial fields).
-    stochastic: rounding of the 16-bit forms (default: stochastic for them)."""
-    lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream)
+    """Build a Lattice from a workloads.Workload or workloads.ChannelStack description
+    (parameters and initial fields).  stochastic: rounding of the 16-bit forms (default:
+    stochastic for them)."""
+    stack = w.geometry == "channels"
+    lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream,
+                  widths=w.widths if stack else None)
     for s in range(w.nspecies):
         lat.add_species(w.rho0[s], w.valence[s])
     if storage in ("bf16s", "f16s"):
         lat.set_rounding(True if stochastic is None else stochastic, seed)
     lat.set_tau_visc(w.tau_visc)
-    lat.set_tau_drag(w.tau_drag)
-    if w.bjerrum > 0 or any(w.E):
-        lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
+    if stack:
+        for c in range(len(w.widths)):
+            lat.set_channel(c, w.tau_drags[c], w.sigmas[c][0], w.sigmas[c][1])
+        if w.bjerrum > 0 or any(w.E):
+            lat.set_electrostatics(w.bjerrum, 0.0, 0.0, w.E)
+    else:
+        lat.set_tau_drag(w.tau_drag)
+        if w.bjerrum > 0 or any(w.E):
+            lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
     if poisson:
         lat.set_poisson(**poisson)
     for s in range(w.nspecies):

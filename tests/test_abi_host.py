@@ -70,3 +70,24 @@ def test_parameter_validation_without_device(L):
     assert st in (0, -3)
     L.lbmix_destroy(h)
     L.lbmix_destroy(None)
+
+
+def test_channel_stack_validation_without_device(L):
+    h = ctypes.c_void_p()
+    W = ctypes.c_int * 3
+    assert L.lbmix_create_channels(ctypes.byref(h), 8, 8, 0, W(4, 5, 6), 2, None) == -1
+    assert L.lbmix_create_channels(ctypes.byref(h), 8, 8, 3, None, 2, None) == -1
+    assert L.lbmix_create_channels(ctypes.byref(h), 8, 8, 3, W(4, 0, 6), 2, None) == -1
+    assert L.lbmix_create_channels(ctypes.byref(h), 8, 8, 3, W(4, 5, 6), 9, None) == -1
+    assert L.lbmix_create_channels(ctypes.byref(h), 1024, 1024, 3, W(700, 700, 700), 2, None) == -1   # > 2^31
+    assert L.lbmix_create_channels(ctypes.byref(h), 8, 8, 3, W(4, 5, 6), 2, None) == 0
+    assert L.lbmix_set_channel(h, 3, 0.6, 0, 0) == -1              # index
+    assert L.lbmix_set_channel(h, 0, 0.5, 0, 0) == -1              # tau_drag in (0, 1/2]
+    assert L.lbmix_set_channel(h, 0, 0.6, -1e-4, -2e-4) == 0
+    assert L.lbmix_set_channel(h, 1, 0.0, 0, 0) == 0               # the context's drag
+    assert L.lbmix_set_poisson_method(h, 1) == -1                  # multigrid: one lattice only
+    assert L.lbmix_set_poisson_method(h, 2) == 0
+    L.lbmix_destroy(h)
+    assert L.lbmix_create(ctypes.byref(h), 8, 8, 10, 1, 2, None) == 0
+    assert L.lbmix_set_channel(h, 0, 0.6, 0, 0) == -1              # not a stack
+    L.lbmix_destroy(h)

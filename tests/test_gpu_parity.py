@@ -418,3 +418,98 @@ def test_odd_extents_need_the_direct_solve(P):
     with pytest.raises(P.LbmixError):
         lat.set_poisson(method="sor")
     lat.step(1)
+
+
+class ChannelView:
+    """The planes of one channel of a stacked lattice, read back once."""
+
+    def __init__(self, lat, sl, ns, populations=True):
+        self.m = [lat.moments(s) for s in range(ns)]
+        self.f = [lat.populations(s)[:, sl] for s in range(ns)] if populations else None
+        self.psi = lat.potential()[sl]
+        self.sl = sl
+
+    def moments(self, s):
+        n, j = self.m[s]
+        return n[self.sl], j[:, self.sl]
+
+    def populations(self, s):
+        return self.f[s]
+
+    def potential(self):
+        return self.psi
+
+
+SMALL_STACK = dict(nx=8, ny=6, widths=(5, 9, 1, 12), sigmas=(-1e-3, -4e-4, -2e-4, -7e-4),
+                   scs=(10.0, 100.0, 1000.0, 1.0), n_ion=2e-3, debye_length=3.0, lateral=0.3)
+
+
+def test_channel_stack_direct_fp64_matches_each_channel(P, oracle_mod):
+    """Four channels of widths 5, 9, 1, 12 (own drag and wall charge, lateral charge waves)
+    in one stacked lattice: every channel follows its own oracle slit at the FP64 bar."""
+    st = WL.channel_stack(**SMALL_STACK)
+    lat = P.from_workload(st, storage="f64", poisson=dict(method="direct"))
+    lat.step(25)
+    for c in range(len(st.widths)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="direct")
+        o.step(25)
+        view = ChannelView(lat, st.planes(c), 3)
+        compare_fp64(view, o, wc)
+        check_potential(view.potential(), o.potential(), wc)
+    m = lat.mass_totals()
+    assert np.all(np.isfinite(m))
+
+
+def test_channel_stack_sor_fixed_sweeps_fp64(P, oracle_mod):
+    """The same stack with a fixed number of red-black SOR sweeps: each channel is coloured by
+    its own lattice, so it takes exactly the oracle's iterates."""
+    st = WL.channel_stack(**SMALL_STACK)
+    omega, sweeps = 1.6, 30
+    lat = P.from_workload(st, storage="f64", poisson=dict(rel_tol=0.0, max_sweeps=sweeps, omega=omega))
+    lat.step(10)
+    for c in range(len(st.widths)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="sor", sor_tol=0.0, sor_max=sweeps, sor_omega=omega)
+        o.step(10)
+        view = ChannelView(lat, st.planes(c), 3)
+        compare_fp64(view, o, wc)
+        check_potential(view.potential(), o.potential(), wc)
+
+
+def test_channel_stack_rejects_multigrid_and_charged_channels(P):
+    st = WL.channel_stack(**SMALL_STACK)
+    with pytest.raises(P.LbmixError):
+        P.from_workload(st, storage="f64", poisson=dict(method="multigrid"))
+    bad = WL.channel_stack(**SMALL_STACK)
+    bad.sigmas[1] = (-4e-4, -3e-4)   # the fluid no longer balances the walls of channel 1
+    lat = P.from_workload(bad, storage="f64", poisson=dict(method="direct"))
+    with pytest.raises(P.LbmixError) as e:
+        lat.step(1)
+    assert "channel 1" in str(e.value)
+
+
+def test_batched_channels_full_size_sampled(P, oracle_mod):
+    """The batched workload at full size (64 channels of 32 x 32 x W, W in 32..256, 9.2 M fluid
+    nodes, shifted FP32, direct solve): four sampled channels against their own oracle slits
+    after 3 steps, to the FP32 bar; all channels keep their mass."""
+    st = WL.batched_channels(lateral=0.2)
+    lat = P.from_workload(st, storage="f32s", poisson=dict(method="direct"))
+    lat.step(3)
+    n_all = [lat.moments(s)[0] for s in range(3)]
+    psi = lat.potential()
+    rng = np.random.default_rng(11)
+    for c in sorted(rng.choice(len(st.widths), size=4, replace=False)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="direct")
+        o.step(3)
+        sl = st.planes(c)
+        m = fluid(wc)
+        for s in range(3):
+            no, _ = o.moments(s)
+            assert rel_max(n_all[s][sl], no, m) <= 1e-5, (c, s)
+            assert rel_to_deviation(n_all[s][sl], no, wc.rho0[s], m) <= 1e-3, (c, s)
+        assert rel_max(psi[sl], o.potential(), m) <= 1e-5, c
+    tot = lat.mass_totals()
+    want = [sum(float(a[st.planes(c)].sum()) for c in range(len(st.widths))) for a in st.n]
+    np.testing.assert_allclose(tot, want, rtol=1e-9)

@@ -188,3 +188,85 @@ def bulk_electrolyte(n=4, n_solvent=1.0, ratio=1e-2, Ex=1e-4, tau_visc=1.0, tau_
                     tau_drag=tau_drag,
                     n=[np.full(shape, n_solvent), np.full(shape, ni), np.full(shape, ni)],
                     u=[None, None, None], E=(Ex, 0.0, 0.0))
+
+
+@dataclass
+class ChannelStack:
+    """Independent charged slit channels of the same lateral extent, stacked along z (each
+    with its own two wall planes): the batched form of the electro-osmosis experiment.
+    Arrays cover all nz = sum (W_c + 2) planes."""
+    name: str
+    nx: int
+    ny: int
+    widths: list                       # fluid width of each channel
+    rho0: list
+    valence: list
+    tau_visc: float
+    tau_drags: list                    # per channel
+    sigmas: list                       # per channel (sigma_lo, sigma_hi)
+    n: list                            # per species [nz][ny][nx]
+    u: list                            # per species [3][nz][ny][nx] or None
+    bjerrum: float = 0.0
+    E: tuple = (0.0, 0.0, 0.0)
+    extra: dict = field(default_factory=dict)
+    geometry: str = "channels"
+
+    @property
+    def nz(self) -> int:
+        return sum(w + 2 for w in self.widths)
+
+    @property
+    def nspecies(self) -> int:
+        return len(self.rho0)
+
+    def planes(self, c):
+        """Slice of the full-lattice planes of channel c (walls included)."""
+        z0 = sum(w + 2 for w in self.widths[:c])
+        return slice(z0, z0 + self.widths[c] + 2)
+
+    def channel(self, c) -> Workload:
+        """Channel c alone, as a slit workload with the same initial fields."""
+        sl = self.planes(c)
+        return Workload(name=f"{self.name}_ch{c}", nx=self.nx, ny=self.ny, nz=self.widths[c] + 2,
+                        geometry="slit", rho0=list(self.rho0), valence=list(self.valence),
+                        tau_visc=self.tau_visc, tau_drag=self.tau_drags[c],
+                        n=[a[sl].copy() for a in self.n],
+                        u=[None if v is None else v[:, sl].copy() for v in self.u],
+                        bjerrum=self.bjerrum, sigma=tuple(self.sigmas[c]), E=self.E)
+
+
+def channel_stack(nx=32, ny=32, widths=(32, 48), sigmas=(-1e-4, -5e-4), scs=(10.0, 100.0), n_solvent=1.0,
+                  n_ion=1e-3, debye_length=8.0, Ex=1e-4, tau_visc=1.0, lateral=0.0, seed=5):
+    """Stack of charged slits (ternary electrolyte as charged_slit, one sigma on both walls of
+    channel c, Schmidt number scs[c]).  lateral > 0 adds to the cation density of each
+    channel lateral * n_ion * sin(2 pi (x / nx + y / ny) + phase_c) (zero sum over every
+    plane: the channel stays neutral) with seeded random phases."""
+    rng = np.random.default_rng(seed)
+    parts = [charged_slit(nx=nx, ny=ny, nz=w + 2, n_solvent=n_solvent, n_ion=n_ion, debye_length=debye_length,
+                          sigma=sg, Ex=Ex, tau_visc=tau_visc, sc=sc)
+             for w, sg, sc in zip(widths, sigmas, scs)]
+    x = np.arange(nx)[None, None, :]
+    y = np.arange(ny)[None, :, None]
+    if lateral > 0.0:
+        for p in parts:
+            ph = rng.uniform(0.0, 2.0 * math.pi)
+            bump = lateral * n_ion * np.sin(2.0 * math.pi * (x / nx + y / ny) + ph) * np.ones((p.nz, 1, 1))
+            bump[0] = bump[-1] = 0.0
+            p.n[1] = p.n[1] + bump
+    n = [np.concatenate([p.n[s] for p in parts], axis=0) for s in range(3)]
+    return ChannelStack(name=f"channel_stack_{len(widths)}x{nx}x{ny}", nx=nx, ny=ny, widths=list(widths),
+                        rho0=[n_solvent, n_ion, n_ion], valence=[0, 1, -1], tau_visc=tau_visc,
+                        tau_drags=[p.tau_drag for p in parts], sigmas=[tuple(p.sigma) for p in parts],
+                        n=n, u=[None, None, None], bjerrum=parts[0].bjerrum, E=(Ex, 0.0, 0.0),
+                        extra={"scs": list(scs), "debye_length": debye_length, "n_ion": n_ion})
+
+
+def batched_channels(nch=64, nx=32, ny=32, wmin=32, wmax=256, seed=5, lateral=0.0):
+    """The batched electro-osmosis workload: nch channels of fluid width W ~ U{wmin..wmax},
+    lateral nx x ny, wall charge sigma ~ -U[1e-4, 1e-3], Schmidt number 10, 100, 1000 by
+    channel index mod 3, lambda_D = 8, ions 1e-3, E_x = 1e-4, tau_visc = 1 (seeded)."""
+    rng = np.random.default_rng(seed)
+    widths = [int(w) for w in rng.integers(wmin, wmax + 1, size=nch)]
+    sigmas = [-float(s) for s in rng.uniform(1e-4, 1e-3, size=nch)]
+    scs = [(10.0, 100.0, 1000.0)[c % 3] for c in range(nch)]
+    return channel_stack(nx=nx, ny=ny, widths=widths, sigmas=sigmas, scs=scs, lateral=lateral, seed=seed + 1)
