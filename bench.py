@@ -74,12 +74,14 @@ def cpu_baseline(w, target_s: float = 12.0):
                       f"{elapsed:.1f} s on {threads} OpenMP threads"}
 
 
-def time_storage(P, w, storage, steps, warmup):
-    """Time `steps` steps of the workload with one storage form; one fused launch per step."""
+def time_storage(P, w, storage, steps, warmup, autotune=True):
+    """Time `steps` steps of the workload with one storage form; one fused launch per step
+    (work-group shape picked by the library's autotuner unless disabled)."""
     import torch
 
     stream = torch.cuda.current_stream()
     lat = P.from_workload(w, storage=storage, stream=stream)
+    shape = lat.autotune(reps=5) if autotune else None
     lat.step(warmup)
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
@@ -99,7 +101,7 @@ def time_storage(P, w, storage, steps, warmup):
     ms_per_step = ms / steps
     achieved = 2 * Q * esize * sites / (ms_per_step * 1e-3) / 1e9   # 19 reads + 19 writes
     return {"glups": sites * steps / (ms * 1e-3) / 1e9, "ms_per_step": ms_per_step,
-            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS}
+            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "launch": shape}
 
 
 DTYPE = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f16", "bf16s": "bf16"}
@@ -124,6 +126,7 @@ def bench_slit(args):
     lat = P.from_workload(w, storage=args.storage, stream=stream,
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson, warm_start=args.warm_start))
+    out["launch"] = None if args.no_autotune else lat.autotune(reps=3)
     t0 = time.perf_counter()
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -161,6 +164,7 @@ def bench_channels(args):
     lat = P.from_workload(w, storage=args.storage, stream=stream,
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson))
+    shape = None if args.no_autotune else lat.autotune(reps=3)
     lat.step(args.warmup)
     torch.cuda.synchronize()
     st0 = lat.stats()
@@ -176,7 +180,7 @@ def bench_channels(args):
     sites = w.nspecies * nodes
     print(json.dumps({"workload": f"{len(w.widths)} charged slit channels {w.nx}x{w.ny}xW, W in "
                                   f"{min(w.widths)}..{max(w.widths)} (seed 5), {nodes} fluid nodes, Sc 10/100/1000",
-                      "storage": args.storage, "poisson_method": args.poisson,
+                      "storage": args.storage, "poisson_method": args.poisson, "launch": shape,
                       "ms_per_step": round(ms, 4), "glups": round(sites / (ms * 1e-3) / 1e9, 3),
                       "poisson_work_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 2),
                       "last_residual": st1["last_residual"]}), flush=True)
@@ -261,6 +265,7 @@ def main():
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default work-group shape")
     ap.add_argument("--workload", default="binary", choices=["binary", "slit", "channels", "precision"],
                     help="binary: the 256^3 throughput benchmark (default); slit: the charged slit; "
                          "channels: 64 charged slit channels in one lattice")
@@ -294,7 +299,7 @@ def main():
 
     torch.cuda.set_device(0)
     w = WL.binary_multimode(n=args.n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=args.sc, seed=2)
-    head = time_storage(P, w, args.storage, args.steps, args.warmup)
+    head = time_storage(P, w, args.storage, args.steps, args.warmup, autotune=not args.no_autotune)
     out = {
         "metric": "species-site updates/s (GLUPS), %HBM peak",
         "value": round(head["glups"], 4),
@@ -310,7 +315,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"neutral binary D3Q19 {args.n}^3 periodic, {args.storage} populations, "
                                f"Sc={args.sc:g}, tau_visc=1, multimode noise + shear wave (seed 2)",
-                   "species": 2, "lattice": [args.n] * 3, "storage": args.storage, "schmidt": args.sc},
+                   "species": 2, "lattice": [args.n] * 3, "storage": args.storage, "schmidt": args.sc,
+                   "launch": head["launch"]},
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": traffic_from_profile(args.storage, args.n)},
@@ -320,10 +326,10 @@ def main():
         for st in ("f32", "f16s", "bf16s"):
             if st == args.storage:
                 continue
-            r = time_storage(P, w, st, args.steps, args.warmup)
+            r = time_storage(P, w, st, args.steps, args.warmup, autotune=not args.no_autotune)
             var[st] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
                        "hbm_frac": round(r["frac"], 4),
-                       "speedup_vs_headline": round(r["glups"] / head["glups"], 3)}
+                       "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}
         out["variants"] = var
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 2 ** 30)

@@ -86,6 +86,7 @@ typedef struct {
     double last_residual;     /* ||b - A psi||_2 / ||b||_2 after the last solve */
     double fluid_nodes;       /* nx * ny * (nz, or nz - 2 for a slit) */
     double bytes_per_step;    /* algorithmic HBM bytes of one stream-collide launch */
+    int block_x, block_y;     /* work-group shape of the stream-collide launch */
 } lbmix_stats;
 
 /* Library version, major * 10000 + minor * 100 + patch. */
@@ -138,6 +139,27 @@ int lbmix_set_tau_drag(lbmix_ctx *ctx, double tau_drag);
 /* Schmidt number Sc = nu / D: tau_drag = 1/2 + (tau_visc - 1/2) / Sc, re-evaluated when
  * tau_visc changes.  Errors: EINVAL unless Sc > 0; ESTATE after the first step. */
 int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
+
+/* Time `reps` launches of the fused stream-collide step for each candidate work-group shape
+ * (64 to 512 threads: rows of 64, 128 or 256 nodes times 1 to 8 rows; for planes narrower
+ * than 64 nodes, whole rows filling 64 to 512 threads) on the current state, and keep the
+ * fastest for the following steps (lbmix_stats reports it).  The state does not advance:
+ * the launches write the buffer the next step overwrites.  Results do not depend on the
+ * shape.  Call after lbmix_set_state.  Errors: ESTATE without a state; EINVAL for reps < 1. */
+int lbmix_autotune(lbmix_ctx *ctx, int reps);
+
+/* Drag with one relaxation time per pair of species (Sec. II: the friction gamma^{ab} of the
+ * pair, here for equal masses and any molecular diameters), replacing the single omega_drag:
+ *   F^a / m = -sum_b omega^{ab} (n^b / n)(u^a - u^b),  omega^{ab} = 1 / tau[a * ns + b],
+ * on the mid-step velocities like the single-frequency drag.  tau is ns x ns row-major with
+ * ns the number of species added so far (add every species first); it must be symmetric
+ * (to 1e-12 relative: the pair forces then cancel) with off-diagonal entries > 1/2; the
+ * diagonal is ignored.  A binary's single pair gives D = v_T^2 (tau^{01} - 1/2).  NULL goes
+ * back to the single drag frequency.  A channel stack with a pair matrix takes no per-channel
+ * drag.  Errors: EINVAL for fewer than two species, an asymmetric matrix or an entry <= 1/2
+ * (lbmix_step: for a species count that changed since, or per-channel drags); ESTATE after
+ * the first step. */
+int lbmix_set_drag_pairs(lbmix_ctx *ctx, const double *tau_pairs);
 
 /* Electrostatics (Sec. II, eq. Poisson and its surface-charge condition): Bjerrum length
  * l_B >= 0 (0: no Poisson solve), surface charges of the walls z = 0 and z = nz-1 in units

@@ -116,12 +116,12 @@ struct SpecXY {
     uint32_t nx, ny, nplanes;
 };
 hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream);
-// Tridiagonal solves as launch_tridiag_z, the columns staged in LDS; segments of at most
-// TRI_LDS_MAX planes.  Both forms also remove the segment mean of mode 0 from the right-hand
-// side first (the projection onto consistent data of each channel).
+// Tridiagonal solves as launch_tridiag_z, the columns staged in LDS; `longest` = planes of
+// the longest segment, at most TRI_LDS_MAX.  Both forms also remove the segment mean of
+// mode 0 from the right-hand side first (the projection onto consistent data of each channel).
 constexpr uint32_t TRI_LDS_MAX = 256;
 hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
-                              const uint32_t *seg, uint32_t nseg, hipStream_t stream);
+                              const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream);
 // a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
 hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,
                                  uint32_t ny, uint32_t N, hipStream_t stream);

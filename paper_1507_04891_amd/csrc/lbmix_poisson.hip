@@ -465,52 +465,68 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
     }
 }
 
-// The same eliminations with the columns staged in LDS: one wave per 32 modes of one segment
-// (at most TRI_LDS_MAX planes); all 64 lanes stage the right-hand side and pivots with
-// coalesced loads, 32 lanes run the recurrences from LDS, all 64 write the result back.
-constexpr uint32_t TRI_MODES = 32;
+// The same eliminations with the columns staged in LDS: one work-group of 256 threads per
+// MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
+// and pivots with coalesced loads, issued eight at a time; MODES threads run the recurrences
+// from LDS; all threads write the result back.
+constexpr uint32_t TRI_CELLS = 8192;
 
-__global__ __launch_bounds__(64) void tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
-                                                  const uint32_t *seg) {
-    __shared__ double sb[TRI_LDS_MAX][TRI_MODES], sp[TRI_LDS_MAX][TRI_MODES];
-    const uint32_t m0 = blockIdx.x * TRI_MODES;
+template <uint32_t MODES>
+__global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
+                                                   const uint32_t *seg) {
+    __shared__ double sb[TRI_CELLS], sp[TRI_CELLS];   // [plane][MODES]
+    const uint32_t m0 = blockIdx.x * MODES;
     const uint32_t z0 = seg[blockIdx.y], L = seg[blockIdx.y + 1] - z0;
-    const uint32_t t = threadIdx.x;
-    for (uint32_t k = t; k < L * TRI_MODES; k += 64) {
-        const uint32_t z = k / TRI_MODES, m = k % TRI_MODES;
-        const bool in = m0 + m < nmodes;
-        const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
-        sb[z][m] = in ? b[i] : 0.0;
-        sp[z][m] = in ? piv[i] : 0.0;
+    const uint32_t t = threadIdx.x, cells = L * MODES;
+    for (uint32_t k0 = 0; k0 < cells; k0 += 256 * 8) {
+        double vb[8], vp[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t k = k0 + u * 256 + t, z = k / MODES, m = k % MODES;
+            const bool in = k < cells && m0 + m < nmodes;
+            const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
+            vb[u] = in ? b[i] : 0.0;
+            vp[u] = in ? piv[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t k = k0 + u * 256 + t;
+            if (k < cells) {
+                sb[k] = vb[u];
+                sp[k] = vp[u];
+            }
+        }
     }
     __syncthreads();
-    if (t < TRI_MODES && m0 + t < nmodes) {
+    if (t < MODES && m0 + t < nmodes) {
         double bm = 0.0;   // mode 0: project onto zero segment mean
         if (m0 + t == 0) {
-            for (uint32_t z = 0; z < L; ++z) bm += sb[z][0];
+            for (uint32_t z = 0; z < L; ++z) bm += sb[z * MODES];
             bm /= double(L);
         }
         double r = 0.0;
+#pragma unroll 8
         for (uint32_t z = 0; z < L; ++z) {
-            r = (sb[z][t] - bm - r) * sp[z][t];
-            sb[z][t] = r;
+            r = (sb[z * MODES + t] - bm - r) * sp[z * MODES + t];
+            sb[z * MODES + t] = r;
         }
         double x = 0.0;
+#pragma unroll 8
         for (uint32_t z = L; z-- > 0;) {
-            x = sb[z][t] - sp[z][t] * x;
-            sb[z][t] = x;
+            x = sb[z * MODES + t] - sp[z * MODES + t] * x;
+            sb[z * MODES + t] = x;
         }
         if (m0 + t == 0) {
             double sum = 0.0;
-            for (uint32_t z = 0; z < L; ++z) sum += sb[z][0];
+            for (uint32_t z = 0; z < L; ++z) sum += sb[z * MODES];
             const double mean = sum / double(L);
-            for (uint32_t z = 0; z < L; ++z) sb[z][0] -= mean;
+            for (uint32_t z = 0; z < L; ++z) sb[z * MODES] -= mean;
         }
     }
     __syncthreads();
-    for (uint32_t k = t; k < L * TRI_MODES; k += 64) {
-        const uint32_t z = k / TRI_MODES, m = k % TRI_MODES;
-        if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[z][m];
+    for (uint32_t k = t; k < cells; k += 256) {
+        const uint32_t z = k / MODES, m = k % MODES;
+        if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[k];
     }
 }
 
@@ -533,6 +549,7 @@ __device__ void lds_product(const double *A, int ar, int ak, const double *B, in
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll 4
         for (int k = 0; k < K; ++k) {
             double av[4], bv[4];
 #pragma unroll
@@ -552,38 +569,39 @@ __device__ void lds_product(const double *A, int ar, int ak, const double *B, in
     }
 }
 
-// Transform of one plane along x and y in LDS (one work-group per plane, nx, ny <= 64).
-constexpr int XY_LD = 65;   // row stride of the LDS arrays (64 + 1)
-
-template <bool FWD>
-__global__ __launch_bounds__(256) void spec_xy(const SpecXY a) {
-    __shared__ double P[64 * XY_LD], R[64 * XY_LD], Tx[64 * XY_LD], Ty[64 * XY_LD];
+// Transform of one plane along x and y in LDS, one work-group per plane: PM = 64 (256
+// threads, 133 KB of LDS) for planes up to 64 x 64, PM = 32 (one wave, 34 KB, four
+// work-groups per compute unit) for planes up to 32 x 32.
+template <bool FWD, int PM>
+__global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
+    constexpr int LD = PM + 1;   // row stride of the LDS arrays
+    __shared__ double P[PM * LD], R[PM * LD], Tx[PM * LD], Ty[PM * LD];
     const int nx = a.nx, ny = a.ny;
     const uint32_t z = blockIdx.x;
     const size_t base = (size_t)z * nx * ny;
-    for (int k = threadIdx.x; k < nx * nx; k += blockDim.x) Tx[(k / nx) * XY_LD + k % nx] = a.tx[k];
-    for (int k = threadIdx.x; k < ny * ny; k += blockDim.x) Ty[(k / ny) * XY_LD + k % ny] = a.ty[k];
+    for (int k = threadIdx.x; k < nx * nx; k += blockDim.x) Tx[(k / nx) * LD + k % nx] = a.tx[k];
+    for (int k = threadIdx.x; k < ny * ny; k += blockDim.x) Ty[(k / ny) * LD + k % ny] = a.ty[k];
     if (FWD && a.q) {
         const double lump = a.planes ? a.planes[z].lump : 0.0;
         for (int k = threadIdx.x; k < nx * ny; k += blockDim.x)
-            P[(k / nx) * XY_LD + k % nx] = -a.K * (a.q[base + k] + lump);
+            P[(k / nx) * LD + k % nx] = -a.K * (a.q[base + k] + lump);
     } else {
-        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) P[(k / nx) * XY_LD + k % nx] = a.in[base + k];
+        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) P[(k / nx) * LD + k % nx] = a.in[base + k];
     }
     __syncthreads();
     if (FWD) {
         // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
-        lds_product(P, XY_LD, 1, Tx, 1, XY_LD, R, XY_LD, ny, nx, nx);
+        lds_product(P, LD, 1, Tx, 1, LD, R, LD, ny, nx, nx);
         __syncthreads();
-        lds_product(Ty, XY_LD, 1, R, XY_LD, 1, P, XY_LD, ny, nx, ny);
+        lds_product(Ty, LD, 1, R, LD, 1, P, LD, ny, nx, ny);
     } else {
         // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
-        lds_product(Ty, 1, XY_LD, P, XY_LD, 1, R, XY_LD, ny, nx, ny);
+        lds_product(Ty, 1, LD, P, LD, 1, R, LD, ny, nx, ny);
         __syncthreads();
-        lds_product(R, XY_LD, 1, Tx, XY_LD, 1, P, XY_LD, ny, nx, nx);
+        lds_product(R, LD, 1, Tx, LD, 1, P, LD, ny, nx, nx);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * XY_LD + k % nx];
+    for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
 }
 
 // a <- -a / (mu_x + mu_y + mu_z) in the transformed basis of a periodic box (0 for the
@@ -722,17 +740,30 @@ hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const Plan
 
 hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     if (a.nx > 64 || a.ny > 64) return hipErrorInvalidValue;
-    if (forward)
-        hipLaunchKernelGGL(spec_xy<true>, dim3(a.nplanes), dim3(256), 0, stream, a);
-    else
-        hipLaunchKernelGGL(spec_xy<false>, dim3(a.nplanes), dim3(256), 0, stream, a);
+    const dim3 g(a.nplanes);
+    if (a.nx <= 32 && a.ny <= 32) {
+        if (forward)
+            hipLaunchKernelGGL((spec_xy<true, 32>), g, dim3(64), 0, stream, a);
+        else
+            hipLaunchKernelGGL((spec_xy<false, 32>), g, dim3(64), 0, stream, a);
+    } else {
+        if (forward)
+            hipLaunchKernelGGL((spec_xy<true, 64>), g, dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL((spec_xy<false, 64>), g, dim3(256), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
-                              uint32_t nseg, hipStream_t stream) {
-    hipLaunchKernelGGL(tridiag_lds, dim3((nmodes + TRI_MODES - 1) / TRI_MODES, nseg), dim3(64), 0, stream, b, piv,
-                       out, nmodes, seg);
+                              uint32_t nseg, uint32_t longest, hipStream_t stream) {
+    if (longest * 32 > TRI_CELLS) return hipErrorInvalidValue;
+    if (longest * 64 <= TRI_CELLS)
+        hipLaunchKernelGGL((tridiag_lds<64>), dim3((nmodes + 63) / 64, nseg), dim3(256), 0, stream, b, piv, out,
+                           nmodes, seg);
+    else
+        hipLaunchKernelGGL((tridiag_lds<32>), dim3((nmodes + 31) / 32, nseg), dim3(256), 0, stream, b, piv, out,
+                           nmodes, seg);
     return hipGetLastError();
 }
 

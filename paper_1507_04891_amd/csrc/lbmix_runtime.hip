@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 using namespace lbmix;
@@ -58,6 +59,8 @@ struct lbmix_ctx {
     double rel_range[MAXS] = {};      // FP16 scale: bound of |f - w rho0| / (w rho0)
     double tau_v = 1.0, tau_d = 1.0, sc = 1.0;
     bool drag_from_sc = true;
+    int pair_ns = 0;                  // > 0: drag relaxation time per pair of species
+    double tau_pair[MAXS][MAXS] = {};
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
     int poisson_method = 0;           // 0 red-black SOR, 1 multigrid, 2 direct (spectral)
@@ -77,7 +80,8 @@ struct lbmix_ctx {
     double *partials = nullptr;       // per-block partial sums
     size_t partials_cap = 0;
     double *step_partials = nullptr;  // mass partials of the last stream-collide
-    uint32_t step_nb = 0;
+    uint32_t step_nb = 0;             // capacity in blocks (the largest candidate launch)
+    uint32_t blk_x = 0, blk_y = 0;    // launch shape of stream_collide (0: default)
     double *dred = nullptr;           // device results of reductions (16 doubles)
     double *hred = nullptr;           // pinned host mirror
     double *scratch = nullptr;        // readback staging
@@ -126,7 +130,10 @@ struct lbmix_ctx {
         return false;
     }
     bool field() const { return charged() || E[0] != 0.0 || E[1] != 0.0 || E[2] != 0.0; }
-    double omega_drag() const { return drag_from_sc ? 1.0 / (0.5 + (tau_v - 0.5) / sc) : 1.0 / tau_d; }
+    double omega_drag() const {
+        if (pair_ns == 2) return 1.0 / tau_pair[0][1];   // a binary has a single pair
+        return drag_from_sc ? 1.0 / (0.5 + (tau_v - 0.5) / sc) : 1.0 / tau_d;
+    }
     double sor_w() const {
         if (sor_omega > 0.0) return sor_omega;
         const int L = std::max(nx, std::max(ny, nzf));
@@ -140,10 +147,31 @@ struct lbmix_ctx {
         const dim3 g = node_grid(nx, ny, nzf, &b);
         return g.x * g.y * g.z;
     }
-    uint32_t step_blocks() const {
+    // candidate launch shapes of stream_collide (bx x by threads, 64..512 threads)
+    std::vector<std::pair<uint32_t, uint32_t>> step_shapes() const {
+        std::vector<std::pair<uint32_t, uint32_t>> v;
+        if (nx >= 64) {
+            const uint32_t cap = std::min<uint32_t>(BLOCK, ((nx + 63) / 64) * 64);
+            for (uint32_t bx = 64; bx <= cap; bx *= 2)
+                for (uint32_t by = 1; bx * by <= (uint32_t)STEP_BLOCK; by *= 2)
+                    if (by <= (uint32_t)ny || by == 1) v.push_back({bx, by});
+        } else {
+            for (uint32_t t = 64; t <= (uint32_t)STEP_BLOCK; t *= 2) {
+                const uint32_t by = std::min<uint32_t>(std::max<uint32_t>(t / nx, 1), ny);
+                if (nx * by <= (uint32_t)STEP_BLOCK && (v.empty() || v.back().second != by)) v.push_back({(uint32_t)nx, by});
+            }
+        }
+        return v;
+    }
+    uint32_t step_blocks() const {   // the most blocks any candidate (or the default) launches
         dim3 b;
-        const dim3 g = step_grid(nx, ny, nzf, &b);
-        return g.x * g.y * g.z;
+        dim3 g = step_grid(nx, ny, nzf, &b);
+        uint32_t m = g.x * g.y * g.z;
+        for (auto &sh : step_shapes()) {
+            g = step_grid(nx, ny, nzf, &b, sh.first, sh.second);
+            m = std::max(m, g.x * g.y * g.z);
+        }
+        return m;
     }
     StepArgs args() const {
         StepArgs a;
@@ -167,6 +195,10 @@ struct lbmix_ctx {
         }
         a.omega_v = 1.0 / tau_v;
         a.omega_d = omega_drag();
+        a.pair_drag = pair_ns >= 3 ? 1 : 0;
+        for (int s = 0; s < MAXS; ++s)
+            for (int b = 0; b < MAXS; ++b)
+                a.omega_pair[s][b] = (pair_ns >= 3 && s < ns && b < ns && s != b) ? 1.0 / tau_pair[s][b] : 0.0;
         for (int d = 0; d < 3; ++d) a.E[d] = E[d];
         a.psi = psi;
         a.q = q;
@@ -175,6 +207,8 @@ struct lbmix_ctx {
         a.nzfull = (uint32_t)nz;
         a.partials = step_partials;
         a.stochastic = rounding;
+        a.block_x = blk_x;
+        a.block_y = blk_y;
         {   // per-step seed: a splitmix64 finaliser of (seed, step), folded to 32 bits
             unsigned long long z = round_seed + 0x9e3779b97f4a7c15ull * (unsigned long long)(steps + 1);
             z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
@@ -677,7 +711,8 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
         int longest = 0;
         for (int w : c->ch_width) longest = std::max(longest, w);
         if (longest <= (int)TRI_LDS_MAX)
-            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_lds");
+            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, (uint32_t)longest, c->stream),
+                        "tridiag_lds");
         else
             rc = c->hip(launch_tridiag_z(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_z");
         if (rc) return rc;
@@ -864,6 +899,11 @@ bool redblack_extents(const lbmix_ctx *c) {
 }
 
 int validate_start(lbmix_ctx *c) {
+    if (c->pair_ns && c->pair_ns != c->ns)
+        return c->fail(LBMIX_EINVAL, "the pair drag matrix was set for %d species, the lattice has %d", c->pair_ns, c->ns);
+    for (int ch = 0; c->pair_ns && ch < c->nch; ++ch)
+        if (c->ch_tau_d[ch] > 0.0)
+            return c->fail(LBMIX_EINVAL, "channel %d has its own drag; a pair drag matrix applies to all channels", ch);
     if (!c->charged()) return LBMIX_OK;
     if (c->poisson_method != 2 && !redblack_extents(c))
         return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR and "
@@ -910,6 +950,8 @@ struct Header {
     uint64_t round_seed;
     double lB, sig_lo, sig_hi, E[3], sor_tol, sor_omega;
     int64_t steps;
+    int32_t pair_ns, pad;
+    double tau_pair[MAXS * MAXS];
 };
 
 }  // namespace
@@ -1052,6 +1094,30 @@ int lbmix_set_schmidt(lbmix_ctx *c, double sc) {
     if (!(sc > 0.0) || !std::isfinite(sc)) return c->fail(LBMIX_EINVAL, "Schmidt number must be positive");
     c->sc = sc;
     c->drag_from_sc = true;
+    c->tables_dirty = true;
+    return LBMIX_OK;
+}
+
+int lbmix_set_drag_pairs(lbmix_ctx *c, const double *tau) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (!tau) {
+        c->pair_ns = 0;
+        c->tables_dirty = true;
+        return LBMIX_OK;
+    }
+    const int ns = c->ns;
+    if (ns < 2) return c->fail(LBMIX_EINVAL, "a pair drag matrix needs at least two species");
+    for (int a = 0; a < ns; ++a)
+        for (int b = 0; b < ns; ++b) {
+            if (a == b) continue;
+            const double t = tau[a * ns + b], u = tau[b * ns + a];
+            if (!std::isfinite(t) || !(t > 0.5) || std::fabs(t - u) > 1e-12 * std::fabs(t))
+                return c->fail(LBMIX_EINVAL, "pair drag times must be symmetric and exceed 1/2 (pair %d, %d)", a, b);
+        }
+    for (int a = 0; a < MAXS; ++a)
+        for (int b = 0; b < MAXS; ++b) c->tau_pair[a][b] = (a < ns && b < ns) ? tau[a * ns + b] : 0.0;
+    c->pair_ns = ns;
     c->tables_dirty = true;
     return LBMIX_OK;
 }
@@ -1213,6 +1279,54 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
     return LBMIX_OK;
 }
 
+int lbmix_autotune(lbmix_ctx *c, int reps) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (reps < 1) return c->fail(LBMIX_EINVAL, "reps must be positive");
+    if (c->latched) return c->fail(c->latched, "context latched an earlier error (%d)", c->latched);
+    Guard g(c);
+    if ((rc = ensure_tables(c))) return rc;
+    const bool charged = c->charged(), field = c->field();
+    if (charged && (rc = ensure_field_buffers(c))) return rc;
+    hipEvent_t e0, e1;
+    if ((rc = c->hip(hipEventCreate(&e0), "hipEventCreate"))) return rc;
+    if ((rc = c->hip(hipEventCreate(&e1), "hipEventCreate"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    // the launches read the current state and write the other buffer, which the next step
+    // overwrites: the state does not advance
+    std::vector<std::pair<uint32_t, uint32_t>> cand = c->step_shapes();
+    cand.insert(cand.begin(), {0u, 0u});
+    float best = -1.0f;
+    uint32_t bx = 0, by = 0;
+    for (auto &sh : cand) {
+        StepArgs a = c->args();
+        a.block_x = sh.first;
+        a.block_y = sh.second;
+        rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
+        if (!rc) rc = c->hip(hipEventRecord(e0, c->stream), "hipEventRecord");
+        for (int k = 0; !rc && k < reps; ++k)
+            rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
+        if (!rc) rc = c->hip(hipEventRecord(e1, c->stream), "hipEventRecord");
+        if (!rc) rc = c->hip(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.0f;
+        if (!rc) rc = c->hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        if (rc) break;
+        if (best < 0.0f || ms < best) {
+            best = ms;
+            bx = sh.first;
+            by = sh.second;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    c->blk_x = bx;
+    c->blk_y = by;
+    return LBMIX_OK;
+}
+
 int lbmix_get_moments_device(lbmix_ctx *c, int s, double *n_dev, double *j_dev) {
     int rc = check_ready(c);
     if (rc) return rc;
@@ -1369,6 +1483,10 @@ int lbmix_get_stats(lbmix_ctx *c, lbmix_stats *out) {
     out->last_residual = c->last_resid;
     out->fluid_nodes = (double)c->Nf;
     out->bytes_per_step = 2.0 * Q * c->ns * (double)c->esize * c->Nf;
+    dim3 b;
+    (void)step_grid(c->nx, c->ny, c->nzf, &b, c->blk_x, c->blk_y);
+    out->block_x = (int)b.x;
+    out->block_y = (int)b.y;
     return LBMIX_OK;
 }
 
@@ -1387,9 +1505,12 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 2;
+    h.version = 3;
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
     h.nch = c->nch;
+    h.pair_ns = c->pair_ns;
+    for (int a = 0; a < MAXS; ++a)
+        for (int b = 0; b < MAXS; ++b) h.tau_pair[a * MAXS + b] = c->tau_pair[a][b];
     for (int s = 0; s < MAXS; ++s) {
         h.valence[s] = c->valence[s];
         h.rho0[s] = c->rho0[s];
@@ -1434,7 +1555,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 2;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 3;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
          h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
     constexpr int kPerChan = 4 + MAXS;
@@ -1466,6 +1587,9 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     c->rounding = h.rounding; c->round_seed = h.round_seed; c->poisson_method = h.poisson_method;
     c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
+    c->pair_ns = h.pair_ns;
+    for (int a = 0; a < MAXS; ++a)
+        for (int b = 0; b < MAXS; ++b) c->tau_pair[a][b] = h.tau_pair[a * MAXS + b];
     for (int ch = 0; ch < c->nch; ++ch) {
         const double *v = chan.data() + (size_t)kPerChan * ch;
         c->ch_tau_d[ch] = v[1];

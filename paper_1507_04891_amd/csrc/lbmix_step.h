@@ -40,6 +40,8 @@ struct StepArgs {
     float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
     float inv_scale[MAXS][Q];
     double omega_v, omega_d;
+    int pair_drag;                   // 1: drag frequency per pair (three or more species)
+    double omega_pair[MAXS][MAXS];   // symmetric; the diagonal is not used
     double valence[MAXS];
     double E[3];                     // applied field, acceleration per unit valence
     const double *psi;               // potential on fluid nodes (charged runs)
@@ -51,12 +53,14 @@ struct StepArgs {
     double *partials;                // out: [species][block] FP64 sums of n - rho_bar
     int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
     uint32_t seed;                   // per-step seed of the rounding hash
+    uint32_t block_x, block_y;       // launch shape of stream_collide (0: the default shape)
 };
 
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
-// Work-group shape of stream_collide: rows of up to 256 nodes along x, two rows per
-// work-group; a plane narrower than 64 nodes packs 512 / nx rows into one work-group.
-dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block);
+// Work-group shape of stream_collide: bx x by threads (bx x by <= STEP_BLOCK), or by default
+// rows of up to 256 nodes along x, two rows per work-group, and for a plane narrower than 64
+// nodes 512 / nx whole rows per work-group.
+dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx = 0, uint32_t by = 0);
 
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
                                  const StepArgs &a, hipStream_t stream);

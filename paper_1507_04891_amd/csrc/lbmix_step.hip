@@ -225,7 +225,7 @@ struct Pull {
 // ---------------------------------------------------------------------------------------
 // The fused step.
 
-template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED>
+template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED, bool PAIR>
 __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     using CD = Codec<T>;
     using C = typename CD::C;
@@ -331,15 +331,48 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         uax[s] = jx[s] * inv_n;
         uay[s] = jy[s] * inv_n;
         uaz[s] = jz[s] * inv_n;
-        Fx[s] = -od * (uax[s] - ux);
-        Fy[s] = -od * (uay[s] - uy);
-        Fz[s] = -od * (uaz[s] - uz);
-        if constexpr (FIELD) {
-            const C k = C(a.valence[s]) * (C(1) - C(0.5) * od) + C(0.5) * od * qn * inv_ntot;
-            Fx[s] += k * fx;
-            Fy[s] += k * fy;
-            Fz[s] += k * fz;
+        if constexpr (!PAIR) {
+            Fx[s] = -od * (uax[s] - ux);
+            Fy[s] = -od * (uay[s] - uy);
+            Fz[s] = -od * (uaz[s] - uz);
+            if constexpr (FIELD) {
+                const C k = C(a.valence[s]) * (C(1) - C(0.5) * od) + C(0.5) * od * qn * inv_ntot;
+                Fx[s] += k * fx;
+                Fy[s] += k * fy;
+                Fz[s] += k * fz;
+            }
         }
+    }
+    if constexpr (PAIR) {
+        // one drag frequency per pair (Sec. II, equal masses), on the mid-step velocities
+        // v_b = u_b + a_b / 2:  F_s = a_s - sum_b omega_sb (n_b / n)(v_s - v_b)
+        C vx[NS], vy[NS], vz[NS];
+#pragma unroll
+        for (int b = 0; b < NS; ++b) {
+            const C h = FIELD ? C(0.5) * C(a.valence[b]) : C(0);
+            vx[b] = uax[b] + h * fx;
+            vy[b] = uay[b] + h * fy;
+            vz[b] = uaz[b] + h * fz;
+        }
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            C gx = 0, gy = 0, gz = 0;
+#pragma unroll
+            for (int b = 0; b < NS; ++b) {
+                if (b == s) continue;
+                const C w = C(a.omega_pair[s][b]) * n[b] * inv_ntot;
+                gx += w * (vx[s] - vx[b]);
+                gy += w * (vy[s] - vy[b]);
+                gz += w * (vz[s] - vz[b]);
+            }
+            const C zs = FIELD ? C(a.valence[s]) : C(0);
+            Fx[s] = zs * fx - gx;
+            Fy[s] = zs * fy - gy;
+            Fz[s] = zs * fz - gz;
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
         const C uu = uax[s] * uax[s] + uay[s] * uay[s] + uaz[s] * uaz[s];
         const C Fu = Fx[s] * ux + Fy[s] * uy + Fz[s] * uz;
         // f*_p = [(1 - ov) d_p + w (base + ov45 (c.u_s)^2 + n9 (c.F)(c.u)) +- w n3 (ov c.u_s + c.F)]
@@ -526,21 +559,27 @@ dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block) {
     return dim3((nx + bx - 1) / bx, ny, nz);
 }
 
-template <int NS, class T, bool SLIT>
+template <int NS, class T, bool SLIT, bool PAIR>
 static hipError_t sc_fields(bool field, bool charged, const StepArgs &a, dim3 g, dim3 b, hipStream_t st) {
     if (charged)
-        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, true>), g, b, 0, st, a);
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, true, PAIR>), g, b, 0, st, a);
     else if (field)
-        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, false>), g, b, 0, st, a);
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, true, false, PAIR>), g, b, 0, st, a);
     else
-        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, false, false>), g, b, 0, st, a);
+        hipLaunchKernelGGL((stream_collide<NS, T, SLIT, false, false, PAIR>), g, b, 0, st, a);
     return hipGetLastError();
 }
 
 template <int NS, class T>
 static hipError_t sc_geom(bool slit, bool field, bool charged, const StepArgs &a, dim3 g, dim3 b, hipStream_t st) {
-    return slit ? sc_fields<NS, T, true>(field, charged, a, g, b, st)
-                : sc_fields<NS, T, false>(field, charged, a, g, b, st);
+    // pair frequencies only matter with three or more species (a binary has one pair)
+    if constexpr (NS >= 3) {
+        if (a.pair_drag)
+            return slit ? sc_fields<NS, T, true, true>(field, charged, a, g, b, st)
+                        : sc_fields<NS, T, false, true>(field, charged, a, g, b, st);
+    }
+    return slit ? sc_fields<NS, T, true, false>(field, charged, a, g, b, st)
+                : sc_fields<NS, T, false, false>(field, charged, a, g, b, st);
 }
 
 template <class T>
@@ -555,8 +594,11 @@ static hipError_t sc_ns(int ns, bool slit, bool field, bool charged, const StepA
     }
 }
 
-dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block) {
-    uint32_t bx, by;
+dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx, uint32_t by) {
+    if (bx > 0 && by > 0 && bx * by <= (uint32_t)STEP_BLOCK) {
+        *block = dim3(bx, by, 1);
+        return dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nzf);
+    }
     if (nx < 64) {   // narrow plane: whole rows, as many as fill the work-group
         bx = nx;
         by = STEP_BLOCK / nx;
@@ -573,7 +615,7 @@ dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block) {
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged, const StepArgs &a,
                                  hipStream_t stream) {
     dim3 b;
-    const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b);
+    const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b, a.block_x, a.block_y);
     switch (st) {
         case Store::F64: return sc_ns<double>(ns, slit, field, charged, a, g, b, stream);
         case Store::F32: return sc_ns<float>(ns, slit, field, charged, a, g, b, stream);

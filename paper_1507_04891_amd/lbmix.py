@@ -26,9 +26,10 @@ Q = 19
 MAX_SPECIES = 4
 EXPORTS = (
     "lbmix_version", "lbmix_create", "lbmix_create_channels", "lbmix_set_channel", "lbmix_add_species",
-    "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_electrostatics",
+    "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_drag_pairs",
+    "lbmix_set_electrostatics",
     "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
-    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_autotune", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
@@ -45,7 +46,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_longlong), ("poisson_solves", ctypes.c_longlong),
                 ("total_sweeps", ctypes.c_longlong), ("last_sweeps", ctypes.c_int),
                 ("last_status", ctypes.c_int), ("last_residual", ctypes.c_double),
-                ("fluid_nodes", ctypes.c_double), ("bytes_per_step", ctypes.c_double)]
+                ("fluid_nodes", ctypes.c_double), ("bytes_per_step", ctypes.c_double),
+                ("block_x", ctypes.c_int), ("block_y", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,6 +77,7 @@ def load_library():
         "lbmix_set_tau_visc": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_tau_drag": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_schmidt": ([vp, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_drag_pairs": ([vp, dp], ctypes.c_int),
         "lbmix_set_electrostatics": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
         "lbmix_set_poisson": ([vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "lbmix_set_poisson_method": ([vp, ctypes.c_int], ctypes.c_int),
@@ -83,6 +86,7 @@ def load_library():
         "lbmix_set_storage_range": ([vp, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_step": ([vp, ctypes.c_int], ctypes.c_int),
+        "lbmix_autotune": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_get_moments": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_get_moments_device": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
         "lbmix_get_populations": ([vp, ctypes.c_int, dp], ctypes.c_int),
@@ -186,6 +190,14 @@ class Lattice:
     def set_schmidt(self, sc):
         self._check(self._L.lbmix_set_schmidt(self._h, float(sc)))
 
+    def set_drag_pairs(self, tau):
+        """tau: [ns][ns] symmetric drag relaxation times per pair, or None for one drag frequency."""
+        if tau is None:
+            self._check(self._L.lbmix_set_drag_pairs(self._h, None))
+            return
+        t = _f64(tau, (self.nspecies, self.nspecies))
+        self._check(self._L.lbmix_set_drag_pairs(self._h, _dp(t)))
+
     def set_electrostatics(self, bjerrum, sigma_lo=0.0, sigma_hi=0.0, E=(0.0, 0.0, 0.0)):
         e = (ctypes.c_double * 3)(*[float(v) for v in E])
         self._check(self._L.lbmix_set_electrostatics(self._h, float(bjerrum), float(sigma_lo),
@@ -215,6 +227,12 @@ class Lattice:
     # -- stepping -------------------------------------------------------------------------
     def step(self, n=1):
         return self._check(self._L.lbmix_step(self._h, int(n)))
+
+    def autotune(self, reps=5):
+        """Pick the fastest work-group shape of the step kernel; returns (block_x, block_y)."""
+        self._check(self._L.lbmix_autotune(self._h, int(reps)))
+        st = self.stats()
+        return st["block_x"], st["block_y"]
 
     def step_status(self, n=1):
         """Like step() but returns the status code instead of raising on ENOCONV."""
@@ -278,7 +296,7 @@ class Lattice:
         self._check(self._L.lbmix_load(self._h, str(path).encode()))
 
 
-def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0):
+def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None):
     """Build a Lattice from a workloads.Workload or workloads.ChannelStack description
     (parameters and initial fields).  stochastic: rounding of the 16-bit forms (default:
     stochastic for them)."""
@@ -299,6 +317,8 @@ def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, 
         lat.set_tau_drag(w.tau_drag)
         if w.bjerrum > 0 or any(w.E):
             lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
+    if drag_pairs is not None:
+        lat.set_drag_pairs(drag_pairs)
     if poisson:
         lat.set_poisson(**poisson)
     for s in range(w.nspecies):

@@ -513,3 +513,96 @@ def test_batched_channels_full_size_sampled(P, oracle_mod):
     tot = lat.mass_totals()
     want = [sum(float(a[st.planes(c)].sum()) for c in range(len(st.widths))) for a in st.n]
     np.testing.assert_allclose(tot, want, rtol=1e-9)
+
+
+def pair_taus(ns, seed):
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.52, 3.0, (ns, ns))
+    t = 0.5 * (t + t.T)
+    np.fill_diagonal(t, 1.0)
+    return t
+
+
+@pytest.mark.parametrize("case", ["periodic_ternary_field", "slit_charged", "periodic_four"])
+def test_pair_drag_fp64_matches_oracle(P, oracle_mod, case):
+    """Drag with one relaxation time per species pair against the oracle at the FP64 bar."""
+    if case == "periodic_ternary_field":
+        w = WL.random_state(20, 6, 8, 3, seed=21, rho0=[0.6, 0.25, 0.15], valence=[0, 1, -1], bjerrum=0.0,
+                            E=(2e-3, -1e-3, 5e-4), dn=0.05, du=0.02)
+        poisson = None
+    elif case == "slit_charged":
+        w = WL.charged_slit(nx=8, ny=6, nz=18, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+        poisson = dict(method="direct")
+    else:
+        w = WL.random_state(10, 4, 6, 4, seed=22, rho0=[0.5, 0.2, 0.2, 0.1], valence=[0, 1, -1, 0], bjerrum=0.4,
+                            E=(1e-3, 0, 0), dn=0.0, du=0.02)
+        poisson = dict(method="direct")
+    taus = pair_taus(w.nspecies, 5)
+    lat = P.from_workload(w, storage="f64", poisson=poisson, drag_pairs=taus)
+    o = oracle_for(oracle_mod, w, drag_pairs=taus)
+    lat.step(30)
+    o.step(30)
+    compare_fp64(lat, o, w)
+    if w.bjerrum > 0:
+        check_potential(lat.potential(), o.potential(), w)
+
+
+def test_pair_drag_fp32_and_binary_reduction(P, oracle_mod):
+    w = WL.random_state(40, 4, 6, 3, seed=23, rho0=[0.6, 0.25, 0.15], valence=[0, 1, -1], bjerrum=0.0,
+                        E=(2e-3, 0, 0), dn=0.05, du=0.02)
+    taus = pair_taus(3, 6)
+    lat = P.from_workload(w, storage="f32s", drag_pairs=taus)
+    o = oracle_for(oracle_mod, w, drag_pairs=taus)
+    lat.step(20)
+    o.step(20)
+    for s in range(3):
+        ng, _ = lat.moments(s)
+        no, _ = o.moments(s)
+        assert rel_max(ng, no) <= 1e-5
+        assert rel_to_deviation(ng, no, w.rho0[s]) <= 1e-3
+    # a binary's pair matrix is its single drag frequency
+    wb = WL.binary_multimode(n=16, amp=1e-2, nmodes=3, shear=1e-2, sc=30.0, seed=4)
+    t01 = wb.tau_drag
+    a = P.from_workload(wb, storage="f64", drag_pairs=[[3.0, t01], [t01, 0.9]])
+    b = P.from_workload(wb, storage="f64")
+    a.step(20)
+    b.step(20)
+    for s in range(2):
+        assert np.array_equal(a.populations(s), b.populations(s))
+
+
+def test_pair_drag_errors(P):
+    w = WL.random_state(8, 4, 4, 3, seed=1, rho0=[0.6, 0.25, 0.15], valence=[0, 0, 0])
+    lat = P.Lattice(8, 4, 4, storage="f64")
+    for s in range(3):
+        lat.add_species(w.rho0[s])
+    t = pair_taus(3, 1)
+    bad = t.copy()
+    bad[0, 1] += 0.1
+    with pytest.raises(P.LbmixError):
+        lat.set_drag_pairs(bad)
+    low = t.copy()
+    low[1, 2] = low[2, 1] = 0.5
+    with pytest.raises(P.LbmixError):
+        lat.set_drag_pairs(low)
+    lat.set_drag_pairs(t)
+    st = WL.channel_stack(**SMALL_STACK)
+    lat2 = P.from_workload(st, storage="f64", poisson=dict(method="direct"), drag_pairs=pair_taus(3, 2))
+    with pytest.raises(P.LbmixError) as e:
+        lat2.step(1)
+    assert "own drag" in str(e.value)
+
+
+@pytest.mark.parametrize("dims,geometry", [((256, 8, 4), "periodic"), ((32, 32, 12), "slit"), ((7, 5, 6), "periodic")])
+def test_autotuned_launch_gives_identical_results(P, dims, geometry):
+    """The tuned work-group shape changes nothing but speed: populations bitwise equal."""
+    nx, ny, nz = dims
+    w = WL.random_state(nx, ny, nz, 2, geometry=geometry, seed=31, dn=0.05, du=0.02)
+    a = P.from_workload(w, storage="f32s")
+    b = P.from_workload(w, storage="f32s")
+    bx, by = a.autotune(reps=3)
+    assert 1 <= bx * by <= 512 and (bx >= 64 or bx == nx)
+    a.step(6)
+    b.step(6)
+    for s in range(2):
+        assert np.array_equal(a.populations(s), b.populations(s))
