@@ -74,9 +74,9 @@ def cpu_baseline(w, target_s: float = 12.0):
                       f"{elapsed:.1f} s on {threads} OpenMP threads"}
 
 
-def time_storage(P, w, storage, steps, warmup, autotune=True):
+def time_storage(P, w, storage, steps, warmup, autotune=False):
     """Time `steps` steps of the workload with one storage form; one fused launch per step
-    (work-group shape picked by the library's autotuner unless disabled)."""
+    (work-group shape: the library's default, or its autotuner's pick)."""
     import torch
 
     stream = torch.cuda.current_stream()
@@ -126,7 +126,7 @@ def bench_slit(args):
     lat = P.from_workload(w, storage=args.storage, stream=stream,
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson, warm_start=args.warm_start))
-    out["launch"] = None if args.no_autotune else lat.autotune(reps=3)
+    out["launch"] = lat.autotune(reps=3) if args.autotune else None
     t0 = time.perf_counter()
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -164,7 +164,7 @@ def bench_channels(args):
     lat = P.from_workload(w, storage=args.storage, stream=stream,
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson))
-    shape = None if args.no_autotune else lat.autotune(reps=3)
+    shape = lat.autotune(reps=3) if args.autotune else None
     lat.step(args.warmup)
     torch.cuda.synchronize()
     st0 = lat.stats()
@@ -184,6 +184,54 @@ def bench_channels(args):
                       "ms_per_step": round(ms, 4), "glups": round(sites / (ms * 1e-3) / 1e9, 3),
                       "poisson_work_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 2),
                       "last_residual": st1["last_residual"]}), flush=True)
+
+
+def bench_warmstart(args):
+    """Learned warm start on the charged ternary slit 64 x 64 x 130 (f32s): train the network
+    (2 -> 16 -> 16 -> 16 -> 1, 3 x 3 x 3) for --train-steps steps on exact corrections of the
+    extrapolated guess, then time multigrid to 1e-8 per step from the previous potential, the
+    extrapolation and the learned guess (the direct solve alongside).  Prints one JSON line."""
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    stream = torch.cuda.current_stream()
+    net = P.Net(2, 16, 4, seed=1)
+    lat = P.from_workload(w, storage=args.storage, stream=stream, poisson=dict(method="direct"))
+    lat.step(200)   # train on developed dynamics, not on the first transient
+    t0 = time.perf_counter()
+    losses = lat.train_warm_start(net, args.train_steps, lr=1e-3)
+    torch.cuda.synchronize()
+    out = {"workload": "charged ternary slit 64x64x130, Sc=100, lambda_D=8, multigrid to rel. residual 1e-8",
+           "storage": args.storage, "network": "2-16-16-16-1, 3x3x3, %d parameters" % net.num_params,
+           "train_steps": args.train_steps, "train_s": round(time.perf_counter() - t0, 2),
+           "output_scale": net.output_scale(),
+           "loss_first50": float(losses[:50].mean()), "loss_last50": float(losses[-50:].mean())}
+    for name, method, warm in [("direct", "direct", "previous"), ("previous", "multigrid", "previous"),
+                               ("extrapolated", "multigrid", "extrapolated"), ("learned", "multigrid", "learned")]:
+        lat = P.from_workload(w, storage=args.storage, stream=stream,
+                              poisson=dict(method=method, rel_tol=1e-8, max_sweeps=100000))
+        if warm == "learned":
+            lat.set_warm_start_net(net)
+        lat.set_poisson(method=method, rel_tol=1e-8, max_sweeps=100000, warm_start=warm)
+        lat.step(args.warmup)
+        torch.cuda.synchronize()
+        st0 = lat.stats()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        lat.step(args.steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        st1 = lat.stats()
+        out[name] = {"ms_per_step": round(start.elapsed_time(end) / args.steps, 4),
+                     "cycles_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 3),
+                     "last_residual": st1["last_residual"]}
+        print(f"{name} done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 def bench_precision(args):
@@ -265,12 +313,15 @@ def main():
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="keep the default work-group shape")
-    ap.add_argument("--workload", default="binary", choices=["binary", "slit", "channels", "precision"],
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library pick the work-group shape of the step (default: its default shape)")
+    ap.add_argument("--workload", default="binary",
+                    choices=["binary", "slit", "channels", "precision", "warmstart"],
                     help="binary: the 256^3 throughput benchmark (default); slit: the charged slit; "
                          "channels: 64 charged slit channels in one lattice")
     ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid", "direct"])
     ap.add_argument("--check-every", type=int, default=10)
+    ap.add_argument("--train-steps", type=int, default=300, help="training steps of the warm-start network")
     ap.add_argument("--warm-start", default="previous", choices=["previous", "extrapolated"])
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (3 times), the reference "
@@ -291,6 +342,9 @@ def main():
     if args.workload == "precision":
         bench_precision(args)
         return
+    if args.workload == "warmstart":
+        bench_warmstart(args)
+        return
 
     import torch
 
@@ -299,7 +353,7 @@ def main():
 
     torch.cuda.set_device(0)
     w = WL.binary_multimode(n=args.n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=args.sc, seed=2)
-    head = time_storage(P, w, args.storage, args.steps, args.warmup, autotune=not args.no_autotune)
+    head = time_storage(P, w, args.storage, args.steps, args.warmup, autotune=args.autotune)
     out = {
         "metric": "species-site updates/s (GLUPS), %HBM peak",
         "value": round(head["glups"], 4),
@@ -326,7 +380,7 @@ def main():
         for st in ("f32", "f16s", "bf16s"):
             if st == args.storage:
                 continue
-            r = time_storage(P, w, st, args.steps, args.warmup, autotune=not args.no_autotune)
+            r = time_storage(P, w, st, args.steps, args.warmup, autotune=args.autotune)
             var[st] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
                        "hbm_frac": round(r["frac"], 4),
                        "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}

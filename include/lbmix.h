@@ -76,6 +76,7 @@ enum lbmix_storage {
 };
 
 typedef struct lbmix_ctx lbmix_ctx;
+typedef struct lbmix_net lbmix_net;
 
 typedef struct {
     long long steps;          /* completed time steps */
@@ -142,8 +143,9 @@ int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
 
 /* Time `reps` launches of the fused stream-collide step for each candidate work-group shape
  * (64 to 512 threads: rows of 64, 128 or 256 nodes times 1 to 8 rows; for planes narrower
- * than 64 nodes, whole rows filling 64 to 512 threads) on the current state, and keep the
- * fastest for the following steps (lbmix_stats reports it).  The state does not advance:
+ * than 64 nodes, whole rows filling 64 to 512 threads) on the current state, twice, and keep
+ * the fastest for the following steps if it beats the default shape by more than 1.5 %
+ * (lbmix_stats reports the shape in use).  The state does not advance:
  * the launches write the buffer the next step overwrites.  Results do not depend on the
  * shape.  Call after lbmix_set_state.  Errors: ESTATE without a state; EINVAL for reps < 1. */
 int lbmix_autotune(lbmix_ctx *ctx, int reps);
@@ -210,9 +212,62 @@ int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
  * extrapolation psi(t-1) + psi(t-2) - psi(t-3), exact for a potential that changes linearly
  * in time plus an oscillation of period two steps (the interdiffusion flux relaxes with the
  * factor 1 - omega_drag per step, which is close to -1 at large Schmidt number).  A plain
- * linear extrapolation 2 psi(t-1) - psi(t-2) triples that oscillation instead.  Errors:
- * EINVAL. */
+ * linear extrapolation 2 psi(t-1) - psi(t-2) triples that oscillation instead.  2 learned:
+ * the extrapolation, then psi += alpha s net(r / s, wall mask) with r = b - A psi the
+ * residual of the extrapolated guess, s its root mean square and alpha the network's output
+ * scale (the network of lbmix_set_warm_start_net).  Applies to SOR and multigrid; the direct solve needs none.
+ * Errors: EINVAL for another mode, or 2 without a network. */
 int lbmix_set_poisson_warm_start(lbmix_ctx *ctx, int mode);
+
+/* ---- learned warm start ---------------------------------------------------------------
+ * A fully convolutional network: `layers` 3 x 3 x 3 convolutions (periodic in x and y; in z
+ * periodic, or zero beyond the end planes for a slit), in_channels -> hidden -> ... -> hidden
+ * -> 1 channels, bias and ReLU on every layer but the last; FP32 parameters [layer][cout][cin]
+ * [27] then [cout], tap k = (dz + 1) 9 + (dy + 1) 3 + (dx + 1).  It lives on the device
+ * current at creation.  The warm start uses in_channels = 2 (scaled residual, wall mask). */
+
+/* Create a network, weights uniform in +-sqrt(6 / fan_in) (+-1 / sqrt(fan_in) for the last
+ * layer) from a splitmix64 stream of `seed`, biases 0.  Errors: EINVAL for channels outside
+ * 1..16 or layers outside 1..16; ENOMEM; EDEVICE. */
+int lbmix_net_create(lbmix_net **out, int in_channels, int hidden, int layers, unsigned long long seed);
+/* Number of FP32 parameters, or EINVAL for a null network. */
+int lbmix_net_num_params(const lbmix_net *net);
+/* Copy the parameters out / in (host arrays of lbmix_net_num_params floats); setting them
+ * resets the Adam moments.  Errors: EINVAL for null pointers or a non-finite parameter. */
+int lbmix_net_get_params(lbmix_net *net, float *params);
+int lbmix_net_set_params(lbmix_net *net, const float *params);
+/* Gradient of the last lbmix_net_gradient call (host array of lbmix_net_num_params floats). */
+int lbmix_net_get_gradient(lbmix_net *net, float *grad);
+/* y_dev[nz][ny][nx] = net(x_dev[in_channels][nz][ny][nx]) on the hipStream_t `stream` (NULL:
+ * the null stream); device pointers.  z_walls: 1 zero beyond the end planes, 0 periodic.
+ * Errors: EINVAL for null pointers or bad extents. */
+int lbmix_net_forward(lbmix_net *net, const float *x_dev, float *y_dev, int nx, int ny, int nz, int z_walls,
+                      void *stream);
+/* Mean-square loss mean((net(x) - t)^2) and its gradient with respect to every parameter by
+ * back-propagation (kept on the device for lbmix_net_adam; lbmix_net_get_gradient copies it
+ * out).  loss may be NULL (else the call synchronises the stream). */
+int lbmix_net_gradient(lbmix_net *net, const float *x_dev, const float *t_dev, int nx, int ny, int nz,
+                       int z_walls, double *loss, void *stream);
+/* One Adam update with the last gradient: beta1 0.9, beta2 0.999, eps 1e-8, step size lr > 0. */
+int lbmix_net_adam(lbmix_net *net, float lr, void *stream);
+/* Output scale alpha of the warm start (the correction is alpha s net(...)): scale > 0 sets
+ * it; *current (may be NULL) receives the value in use (0: not set, then 1 is used; training
+ * sets it from the root mean square of the first target).  Errors: EINVAL. */
+int lbmix_net_output_scale(lbmix_net *net, double scale, double *current);
+const char *lbmix_net_last_error(const lbmix_net *net);
+void lbmix_net_destroy(lbmix_net *net);
+
+/* Network of the learned warm start (borrowed: it must outlive its use; NULL detaches it
+ * and falls back to warm start 1).  Errors: EINVAL unless it takes 2 input channels and
+ * lives on the lattice's device. */
+int lbmix_set_warm_start_net(lbmix_ctx *ctx, lbmix_net *net);
+/* Advance the lattice `nsteps` steps with the direct Poisson solve, training `net` on the
+ * way: at each step the sample is the scaled residual of the extrapolated guess (and the
+ * wall mask) and the target the exact correction (psi - guess) / (alpha s); one Adam step of
+ * size lr per sample.  A network without an output scale gets the root mean square of its
+ * first target.  losses (may be NULL) receives the loss of every sample.  Errors: EINVAL
+ * without charged species, for a bad network or arguments; ESTATE without a state. */
+int lbmix_train_warm_start(lbmix_ctx *ctx, lbmix_net *net, int nsteps, float lr, double *losses);
 
 /* Rounding of the 16-bit storage forms (LBMIX_BF16_SHIFTED, LBMIX_F16_SHIFTED): mode 0
  * rounds to nearest-even (default); mode 1 rounds stochastically, each stored value going

@@ -1,0 +1,232 @@
+// gfx950 kernels of the learned warm start of the Poisson solve: 3 x 3 x 3 convolutions with
+// bias and ReLU (forward, transposed for the input gradient, weight gradient), mean-square
+// loss, Adam, and the glue between the FP64 potential and the FP32 network.  The network
+// works on lattices of a few hundred thousand nodes with at most 16 channels: one thread per
+// node accumulates every output channel, with the weights of the layer in LDS (read by all
+// lanes at once).
+#include "lbmix_net.h"
+
+namespace lbmix {
+
+namespace {
+
+// Neighbour of node (x, y, z) at tap k, or -1 beyond a zero-padded z end.
+__device__ __forceinline__ int64_t tap(int k, uint32_t x, uint32_t y, uint32_t z, uint32_t nx, uint32_t ny,
+                                       uint32_t nz, int zwalls) {
+    const int dz = k / 9 - 1, dy = (k / 3) % 3 - 1, dx = k % 3 - 1;
+    const uint32_t xx = dx < 0 ? (x == 0 ? nx - 1 : x - 1) : (dx > 0 ? (x + 1 == nx ? 0 : x + 1) : x);
+    const uint32_t yy = dy < 0 ? (y == 0 ? ny - 1 : y - 1) : (dy > 0 ? (y + 1 == ny ? 0 : y + 1) : y);
+    int64_t zz = (int64_t)z + dz;
+    if (zz < 0 || zz >= (int64_t)nz) {
+        if (zwalls) return -1;
+        zz = zz < 0 ? nz - 1 : 0;
+    }
+    return ((int64_t)zz * ny + yy) * nx + xx;
+}
+
+}  // namespace
+
+constexpr int NET_BLOCK = 256;
+
+__global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
+    __shared__ float sw[NET_MAXC * NET_MAXC * NET_K];
+    __shared__ float sb[NET_MAXC];
+    const int nw = a.cout * a.cin * NET_K;
+    for (int i = threadIdx.x; i < nw; i += NET_BLOCK) sw[i] = a.w[i];
+    if ((int)threadIdx.x < a.cout) sb[threadIdx.x] = a.b ? a.b[threadIdx.x] : 0.0f;
+    __syncthreads();
+    const uint32_t v = blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (v >= a.N) return;
+    const uint32_t x = v % a.nx, y = (v / a.nx) % a.ny, z = v / (a.nx * a.ny);
+    float acc[NET_MAXC];
+#pragma unroll
+    for (int co = 0; co < NET_MAXC; ++co) acc[co] = co < a.cout ? sb[co] : 0.0f;
+    for (int k = 0; k < NET_K; ++k) {
+        const int64_t nb = tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls);
+        if (nb < 0) continue;
+        for (int ci = 0; ci < a.cin; ++ci) {
+            const float xv = a.x[(size_t)ci * a.N + nb];
+            const float *wk = sw + ci * NET_K + k;
+#pragma unroll
+            for (int co = 0; co < NET_MAXC; ++co)
+                if (co < a.cout) acc[co] = fmaf(wk[co * a.cin * NET_K], xv, acc[co]);
+        }
+    }
+    for (int co = 0; co < a.cout; ++co) {
+        const float r = acc[co];
+        a.y[(size_t)co * a.N + v] = (a.relu && r < 0.0f) ? 0.0f : r;
+    }
+}
+
+__global__ void flip_weights(const float *w, float *wt, int cout, int cin) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cout * cin * NET_K) return;
+    const int co = i / (cin * NET_K), ci = (i / NET_K) % cin, k = i % NET_K;
+    wt[(ci * cout + co) * NET_K + (NET_K - 1 - k)] = w[i];
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void relu_mask(float *g, const float *y, uint32_t n) {
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (i < n && !(y[i] > 0.0f)) g[i] = 0.0f;
+}
+
+// One work-group per weight (co, ci, k), or per bias when k == NET_K: the sum over all nodes
+// in a fixed order (strided per thread, then a tree), accumulated in FP64.
+__global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad(const ConvArgs a, const float *g, float *gw, float *gb) {
+    __shared__ double red[NET_BLOCK];
+    const int idx = blockIdx.x;
+    const int per_co = a.cin * NET_K + 1;
+    const int co = idx / per_co, r = idx % per_co;
+    const bool bias = r == a.cin * NET_K;
+    const int ci = bias ? 0 : r / NET_K, k = bias ? 0 : r % NET_K;
+    const float *gc = g + (size_t)co * a.N;
+    const float *xc = a.x + (size_t)ci * a.N;
+    double s = 0.0;
+    for (uint32_t v = threadIdx.x; v < a.N; v += NET_BLOCK) {
+        if (bias) {
+            s += gc[v];
+        } else {
+            const uint32_t x = v % a.nx, y = (v / a.nx) % a.ny, z = v / (a.nx * a.ny);
+            const int64_t nb = tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls);
+            if (nb >= 0) s += (double)gc[v] * (double)xc[nb];
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = NET_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (bias)
+            gb[co] = (float)red[0];
+        else
+            gw[(co * a.cin + ci) * NET_K + k] = (float)red[0];
+    }
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void mse(const float *y, const float *t, float *g, uint32_t n,
+                                                 double *partials) {
+    __shared__ double red[NET_BLOCK];
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    double d = 0.0;
+    if (i < n) {
+        d = (double)y[i] - (double)t[i];
+        g[i] = (float)(2.0 * d / (double)n);
+    }
+    red[threadIdx.x] = d * d;
+    __syncthreads();
+    for (int w = NET_BLOCK / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void adam(float *p, const float *g, float *m, float *v, uint32_t n, float lr,
+                                                  float beta1, float beta2, float eps, float c1, float c2) {
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+__global__ void finish_scale(double *s, uint32_t N) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double r = sqrt(*s / (double)N);
+        *s = r > 0.0 ? r : 1.0;
+    }
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void net_input(const double *r, const double *scale, float *x, uint32_t nxy,
+                                                       uint32_t nzf, const float *mask) {
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    const uint32_t N = nxy * nzf;
+    if (i >= N) return;
+    x[i] = (float)(r[i] / *scale);
+    x[N + i] = mask ? mask[i / nxy] : 0.0f;
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void add_correction(double *psi, const float *y, const double *scale,
+                                                            double alpha, uint32_t N) {
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (i < N) psi[i] += alpha * *scale * (double)y[i];
+}
+
+__global__ __launch_bounds__(NET_BLOCK) void correction_target(const double *psi, const double *guess,
+                                                               const double *scale, double alpha, float *t,
+                                                               uint32_t N) {
+    const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
+    if (i < N) t[i] = (float)((psi[i] - guess[i]) / (alpha * *scale));
+}
+
+// ---------------------------------------------------------------------------------------
+// Launchers.
+
+static dim3 grid_of(uint32_t n) { return dim3((n + NET_BLOCK - 1) / NET_BLOCK); }
+
+hipError_t launch_conv3(const ConvArgs &a, hipStream_t stream) {
+    if (a.cin < 1 || a.cin > NET_MAXC || a.cout < 1 || a.cout > NET_MAXC) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(conv3, grid_of(a.N), dim3(NET_BLOCK), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_weights(const float *w, float *wt, int cout, int cin, hipStream_t stream) {
+    hipLaunchKernelGGL(flip_weights, grid_of((uint32_t)(cout * cin * NET_K)), dim3(NET_BLOCK), 0, stream, w, wt, cout,
+                       cin);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(float *g, const float *y, uint32_t n, hipStream_t stream) {
+    hipLaunchKernelGGL(relu_mask, grid_of(n), dim3(NET_BLOCK), 0, stream, g, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, hipStream_t stream) {
+    const uint32_t blocks = (uint32_t)(a.cout * (a.cin * NET_K + 1));
+    hipLaunchKernelGGL(conv3_wgrad, dim3(blocks), dim3(NET_BLOCK), 0, stream, a, g, gw, gb);
+    return hipGetLastError();
+}
+
+hipError_t launch_mse(const float *y, const float *t, float *g, uint32_t n, double *partials, uint32_t *nb,
+                      hipStream_t stream) {
+    *nb = grid_of(n).x;
+    hipLaunchKernelGGL(mse, grid_of(n), dim3(NET_BLOCK), 0, stream, y, t, g, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint32_t n, float lr, float beta1, float beta2,
+                       float eps, int step, hipStream_t stream) {
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(adam, grid_of(n), dim3(NET_BLOCK), 0, stream, p, g, m, v, n, lr, beta1, beta2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_scale(double *scale, uint32_t N, hipStream_t stream) {
+    hipLaunchKernelGGL(finish_scale, dim3(1), dim3(64), 0, stream, scale, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_net_input(const double *r, const double *scale, float *x, uint32_t nxy, uint32_t nzf,
+                            const float *plane_mask, hipStream_t stream) {
+    hipLaunchKernelGGL(net_input, grid_of(nxy * nzf), dim3(NET_BLOCK), 0, stream, r, scale, x, nxy, nzf, plane_mask);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_correction(double *psi, const float *y, const double *scale, double alpha, uint32_t N,
+                                 hipStream_t stream) {
+    hipLaunchKernelGGL(add_correction, grid_of(N), dim3(NET_BLOCK), 0, stream, psi, y, scale, alpha, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_correction_target(const double *psi, const double *guess, const double *scale, double alpha, float *t,
+                                    uint32_t N, hipStream_t stream) {
+    hipLaunchKernelGGL(correction_target, grid_of(N), dim3(NET_BLOCK), 0, stream, psi, guess, scale, alpha, t, N);
+    return hipGetLastError();
+}
+
+}  // namespace lbmix

@@ -47,6 +47,10 @@ hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream);
 hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb,
                            hipStream_t stream);
 
+// r = b - A psi into r[N], per-block partials of sum r^2; nblocks written to *nb.
+hipError_t launch_residual_field(const PoissonArgs &a, double *r, double *partials, uint32_t *nb,
+                                 hipStream_t stream);
+
 // Per-block partials of sum q over the fluid; nblocks written to *nb.
 hipError_t launch_qsum(const double *q, uint32_t N, double *partials, uint32_t *nb,
                        hipStream_t stream);

@@ -81,6 +81,22 @@ __global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *p
     block_sum_store<3>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
 }
 
+// r = b - A psi on every fluid node, and per-block partial sums of r^2.
+__global__ __launch_bounds__(BLOCK) void residual_field(const PoissonArgs a, double *r, double *partials) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    double v[1] = {0.0};
+    if (x < a.nx) {
+        const uint32_t y = blockIdx.y, z = blockIdx.z;
+        const uint32_t i = (z * a.ny + y) * a.nx + x;
+        const Stencil st = neighbours(a, a.psi, x, y, z);
+        const double ri = rhs(a, i, z) - (st.sum - st.deg * a.psi[i]);
+        r[i] = ri;
+        v[0] = ri * ri;
+    }
+    const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    block_sum_store<1>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
+}
+
 __global__ __launch_bounds__(BLOCK) void qsum(const double *q, uint32_t N, double *partials) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     double v[1] = {i < N ? q[i] : 0.0};
@@ -653,6 +669,14 @@ hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb,
     const dim3 g = node_grid(a.nx, a.ny, (a.nzf + RES_PLANES - 1) / RES_PLANES, &b);
     *nb = g.x * g.y * g.z;
     hipLaunchKernelGGL(residual, g, b, 0, stream, a, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual_field(const PoissonArgs &a, double *r, double *partials, uint32_t *nb, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
+    *nb = g.x * g.y * g.z;
+    hipLaunchKernelGGL(residual_field, g, b, 0, stream, a, r, partials);
     return hipGetLastError();
 }
 

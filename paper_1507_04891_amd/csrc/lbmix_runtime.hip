@@ -6,6 +6,8 @@
 // launch, then for charged runs the Poisson solve of the new charge density, used by the
 // next collision.
 #include "lbmix.h"
+#include "lbmix_net.h"
+#include "lbmix_netobj.h"
 #include "lbmix_poisson.h"
 #include "lbmix_step.h"
 
@@ -64,7 +66,10 @@ struct lbmix_ctx {
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
     int poisson_method = 0;           // 0 red-black SOR, 1 multigrid, 2 direct (spectral)
-    int warm_start = 0;               // 0 previous potential, 1 linear extrapolation in time
+    int warm_start = 0;               // 0 previous potential, 1 extrapolation in time, 2 learned
+    lbmix_net *ws_net = nullptr;      // borrowed network of the learned warm start
+    double *ws_r = nullptr, *ws_guess = nullptr, *ws_scale = nullptr;   // residual, guess, rms (device)
+    float *ws_x = nullptr, *ws_y = nullptr, *ws_t = nullptr, *ws_mask = nullptr;
     double *psi_prev = nullptr;       // two previous solutions (warm_start 1)
     int have_prev = 0;
     int mg_last = 0;                  // V-cycles of the last multigrid solve
@@ -732,6 +737,72 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     return spec_x(c, a, c->psi, true);
 }
 
+// Warm start psi(t-1) + psi(t-2) - psi(t-3) once three solutions exist (exact for a linear
+// trend plus a period-two oscillation in time); before that, the previous potential.
+int extrapolated_guess(lbmix_ctx *c) {
+    int rc;
+    const size_t bytes = (size_t)c->Nf * sizeof(double);
+    if (!c->psi_prev) {
+        if ((rc = c->hip(hipMalloc((void **)&c->psi_prev, 2 * bytes), "hipMalloc(psi_prev)"))) return rc;
+        c->have_prev = 0;
+    }
+    double *p1 = c->psi_prev, *p2 = c->psi_prev + c->Nf;
+    if (c->have_prev >= 2) return c->hip(launch_extrapolate(c->psi, p1, p2, c->Nf, c->stream), "extrapolate");
+    // history not complete: shift it, keep the previous potential as the guess
+    if (c->have_prev == 1 &&
+        (rc = c->hip(hipMemcpyAsync(p2, p1, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi")))
+        return rc;
+    if ((rc = c->hip(hipMemcpyAsync(p1, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi"))) return rc;
+    c->have_prev++;
+    return LBMIX_OK;
+}
+
+int ensure_ws_buffers(lbmix_ctx *c) {
+    if (c->ws_r) return LBMIX_OK;
+    const size_t N = c->Nf;
+    int rc;
+    if ((rc = c->hip(hipMalloc((void **)&c->ws_r, N * sizeof(double)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_guess, N * sizeof(double)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_scale, sizeof(double)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_x, 2 * N * sizeof(float)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_y, N * sizeof(float)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_t, N * sizeof(float)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_mask, (size_t)c->nzf * sizeof(float)), "hipMalloc(warm start)")))
+        return rc;
+    std::vector<float> mask(c->nzf, 0.0f);   // second input channel: planes next to a wall
+    if (c->slit)
+        for (int ch = 0; ch < c->nch; ++ch) {
+            mask[c->ch_first[ch]] = 1.0f;
+            mask[c->ch_first[ch] + c->ch_width[ch] - 1] = 1.0f;
+        }
+    return c->hip(hipMemcpy(c->ws_mask, mask.data(), mask.size() * sizeof(float), hipMemcpyHostToDevice),
+                  "copy mask");
+}
+
+// Network input from the residual of the current guess: x = (r / s, wall mask), s = rms(r).
+int net_sample_input(lbmix_ctx *c, const PoissonArgs &pa) {
+    int rc = ensure_ws_buffers(c);
+    if (rc) return rc;
+    uint32_t nb = 0;
+    if ((rc = c->hip(launch_residual_field(pa, c->ws_r, c->partials, &nb, c->stream), "residual_field")) ||
+        (rc = c->hip(launch_finalize(c->partials, nb, 1, c->ws_scale, 0, 0.0, 0.0, 1.0, c->stream), "finalize")) ||
+        (rc = c->hip(launch_finish_scale(c->ws_scale, c->Nf, c->stream), "finish_scale")))
+        return rc;
+    return c->hip(launch_net_input(c->ws_r, c->ws_scale, c->ws_x, (uint32_t)c->nx * c->ny, (uint32_t)c->nzf,
+                                   c->ws_mask, c->stream),
+                  "net_input");
+}
+
+// Learned warm start: psi += s net(r / s, mask) on top of the extrapolated guess.
+int learned_correction(lbmix_ctx *c, const PoissonArgs &pa) {
+    int rc = net_sample_input(c, pa);
+    if (rc) return rc;
+    if ((rc = net_forward(c->ws_net, c->ws_x, c->ws_y, c->nx, c->ny, c->nzf, c->slit ? 1 : 0, c->stream)))
+        return c->fail(rc, "warm-start network: %s", lbmix_net_last_error(c->ws_net));
+    const double alpha = net_output_scale(c->ws_net) > 0.0 ? net_output_scale(c->ws_net) : 1.0;
+    return c->hip(launch_add_correction(c->psi, c->ws_y, c->ws_scale, alpha, c->Nf, c->stream), "add_correction");
+}
+
 // Poisson solve of the charge in c->q into c->psi (warm start), then zero-mean gauge.
 int finish_zero_rhs(lbmix_ctx *c) {   // b == 0: the solution is psi = 0
     int rc = c->hip(hipMemsetAsync(c->psi, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(psi)");
@@ -770,26 +841,9 @@ int solve(lbmix_ctx *c) {
         return LBMIX_OK;
     }
     if ((rc = channel_means(c, c->q, 0, 0))) return rc;
-    // warm start: the previous potential, or psi(t-1) + psi(t-2) - psi(t-3) once three
-    // solutions exist (exact for a linear trend plus a period-two oscillation in time)
-    if (c->warm_start == 1 && c->psi_valid && c->poisson_method != 2) {
-        const size_t bytes = (size_t)c->Nf * sizeof(double);
-        if (!c->psi_prev) {
-            if ((rc = c->hip(hipMalloc((void **)&c->psi_prev, 2 * bytes), "hipMalloc(psi_prev)"))) return rc;
-            c->have_prev = 0;
-        }
-        double *p1 = c->psi_prev, *p2 = c->psi_prev + c->Nf;
-        if (c->have_prev >= 2) {
-            if ((rc = c->hip(launch_extrapolate(c->psi, p1, p2, c->Nf, c->stream), "extrapolate"))) return rc;
-        } else {
-            // history not complete: shift it, keep the previous potential as the guess
-            if (c->have_prev == 1 &&
-                (rc = c->hip(hipMemcpyAsync(p2, p1, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi")))
-                return rc;
-            if ((rc = c->hip(hipMemcpyAsync(p1, c->psi, bytes, hipMemcpyDeviceToDevice, c->stream), "copy psi")))
-                return rc;
-            c->have_prev++;
-        }
+    if (c->warm_start >= 1 && c->psi_valid) {
+        if ((rc = extrapolated_guess(c))) return rc;
+        if (c->warm_start == 2 && (rc = learned_correction(c, pa))) return rc;
     }
     int work = 0, status = LBMIX_OK;
     if (c->poisson_method == 1) {
@@ -1169,9 +1223,78 @@ int lbmix_set_poisson_method(lbmix_ctx *c, int method) {
 
 int lbmix_set_poisson_warm_start(lbmix_ctx *c, int mode) {
     if (!c) return LBMIX_EINVAL;
-    if (mode != 0 && mode != 1) return c->fail(LBMIX_EINVAL, "warm start is 0 (previous) or 1 (extrapolated)");
+    if (mode < 0 || mode > 2)
+        return c->fail(LBMIX_EINVAL, "warm start is 0 (previous), 1 (extrapolated) or 2 (learned)");
+    if (mode == 2 && !c->ws_net) return c->fail(LBMIX_EINVAL, "the learned warm start needs lbmix_set_warm_start_net");
     c->warm_start = mode;
     c->have_prev = 0;
+    return LBMIX_OK;
+}
+
+int lbmix_set_warm_start_net(lbmix_ctx *c, lbmix_net *net) {
+    if (!c) return LBMIX_EINVAL;
+    if (net && net_in_channels(net) != 2)
+        return c->fail(LBMIX_EINVAL, "the warm-start network takes 2 input channels (residual, wall mask)");
+    if (net && c->allocated && net_device(net) != c->device)
+        return c->fail(LBMIX_EINVAL, "the network lives on device %d, the lattice on %d", net_device(net), c->device);
+    if (!net && c->warm_start == 2) c->warm_start = 1;
+    c->ws_net = net;
+    return LBMIX_OK;
+}
+
+int lbmix_train_warm_start(lbmix_ctx *c, lbmix_net *net, int nsteps, float lr, double *losses) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!net || net_in_channels(net) != 2 || nsteps < 0 || !(lr > 0.0f))
+        return c->fail(LBMIX_EINVAL, "training needs a 2-channel network, nsteps >= 0 and lr > 0");
+    if (!c->charged()) return c->fail(LBMIX_EINVAL, "no charged species: there is no Poisson solve to learn");
+    if (c->latched) return c->fail(c->latched, "context latched an earlier error (%d)", c->latched);
+    Guard g(c);
+    if ((rc = ensure_tables(c))) return rc;
+    if (!c->started) {
+        if ((rc = validate_start(c))) return rc;
+        c->started = true;
+    }
+    if (!c->psi_valid && (rc = initial_potential(c))) return rc;
+    const bool field = c->field();
+    for (int k = 0; k < nsteps; ++k) {
+        const StepArgs a = c->args();
+        if ((rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, true, a, c->stream), "stream_collide")))
+            return rc;
+        c->cur ^= 1;
+        c->steps++;
+        // sample: the residual of the extrapolated guess and the exact correction to it
+        const PoissonArgs pa = c->pargs();
+        if ((rc = channel_means(c, c->q, 0, 0)) || (rc = extrapolated_guess(c)) || (rc = net_sample_input(c, pa)))
+            return rc;
+        if ((rc = c->hip(hipMemcpyAsync(c->ws_guess, c->psi, (size_t)c->Nf * sizeof(double), hipMemcpyDeviceToDevice,
+                                        c->stream),
+                         "copy guess")))
+            return rc;
+        if ((rc = spec_solve(c, pa))) return rc;
+        c->solves++;
+        c->total_sweeps++;
+        c->last_sweeps = 1;
+        if (!(net_output_scale(net) > 0.0)) {
+            // output scale of a fresh network: the root mean square of its first target
+            double rms = 0.0;
+            if ((rc = c->hip(launch_correction_target(c->psi, c->ws_guess, c->ws_scale, 1.0, c->ws_t, c->Nf, c->stream),
+                             "correction_target")))
+                return rc;
+            if ((rc = net_rms(net, c->ws_t, c->Nf, &rms, c->stream))) return c->fail(rc, "%s", lbmix_net_last_error(net));
+            net_set_output_scale(net, rms > 0.0 ? rms : 1.0);
+        }
+        if ((rc = c->hip(launch_correction_target(c->psi, c->ws_guess, c->ws_scale, net_output_scale(net), c->ws_t,
+                                                  c->Nf, c->stream),
+                         "correction_target")))
+            return rc;
+        double loss = 0.0;
+        if ((rc = net_gradient(net, c->ws_x, c->ws_t, c->nx, c->ny, c->nzf, c->slit ? 1 : 0, losses ? &loss : nullptr,
+                               c->stream)) ||
+            (rc = net_adam(net, lr, c->stream)))
+            return c->fail(rc, "training: %s", lbmix_net_last_error(net));
+        if (losses) losses[k] = loss;
+    }
     return LBMIX_OK;
 }
 
@@ -1295,30 +1418,37 @@ int lbmix_autotune(lbmix_ctx *c, int reps) {
         return rc;
     }
     // the launches read the current state and write the other buffer, which the next step
-    // overwrites: the state does not advance
+    // overwrites: the state does not advance.  Two sweeps over the candidates, the best time
+    // of each kept; a candidate replaces the default shape only when it is faster by more
+    // than 1.5 % (launch times of a bandwidth-bound kernel vary by about that much)
     std::vector<std::pair<uint32_t, uint32_t>> cand = c->step_shapes();
     cand.insert(cand.begin(), {0u, 0u});
-    float best = -1.0f;
-    uint32_t bx = 0, by = 0;
-    for (auto &sh : cand) {
-        StepArgs a = c->args();
-        a.block_x = sh.first;
-        a.block_y = sh.second;
-        rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
-        if (!rc) rc = c->hip(hipEventRecord(e0, c->stream), "hipEventRecord");
-        for (int k = 0; !rc && k < reps; ++k)
+    std::vector<float> best_ms(cand.size(), -1.0f);
+    for (int sweep = 0; sweep < 2 && !rc; ++sweep) {
+        for (size_t i = 0; i < cand.size() && !rc; ++i) {
+            StepArgs a = c->args();
+            a.block_x = cand[i].first;
+            a.block_y = cand[i].second;
             rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
-        if (!rc) rc = c->hip(hipEventRecord(e1, c->stream), "hipEventRecord");
-        if (!rc) rc = c->hip(hipEventSynchronize(e1), "hipEventSynchronize");
-        float ms = 0.0f;
-        if (!rc) rc = c->hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-        if (rc) break;
-        if (best < 0.0f || ms < best) {
-            best = ms;
-            bx = sh.first;
-            by = sh.second;
+            if (!rc) rc = c->hip(hipEventRecord(e0, c->stream), "hipEventRecord");
+            for (int k = 0; !rc && k < reps; ++k)
+                rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream),
+                            "stream_collide");
+            if (!rc) rc = c->hip(hipEventRecord(e1, c->stream), "hipEventRecord");
+            if (!rc) rc = c->hip(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0.0f;
+            if (!rc) rc = c->hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            if (!rc && (best_ms[i] < 0.0f || ms < best_ms[i])) best_ms[i] = ms;
         }
     }
+    uint32_t bx = 0, by = 0;
+    float best = best_ms[0];
+    for (size_t i = 1; i < cand.size(); ++i)
+        if (best_ms[i] >= 0.0f && best_ms[i] < 0.985f * best_ms[0] && best_ms[i] < best) {
+            best = best_ms[i];
+            bx = cand[i].first;
+            by = cand[i].second;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
@@ -1636,6 +1766,9 @@ void lbmix_destroy(lbmix_ctx *c) {
         if (c->mg_b) (void)hipFree(c->mg_b);
         if (c->mg_cinv) (void)hipFree(c->mg_cinv);
         if (c->psi_prev) (void)hipFree(c->psi_prev);
+        for (void *p : {(void *)c->ws_r, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
+                        (void *)c->ws_t, (void *)c->ws_mask})
+            if (p) (void)hipFree(p);
         for (double *p : {c->sp_tx, c->sp_ty, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);

@@ -20,7 +20,7 @@ F64, F32, F32_SHIFTED, BF16_SHIFTED, F16_SHIFTED = 0, 1, 2, 3, 4
 STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "f16s": F16_SHIFTED}
 GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z, "channels": CHANNELS}
 POISSON = {"sor": 0, "multigrid": 1, "direct": 2}
-WARM_START = {"previous": 0, "extrapolated": 1}
+WARM_START = {"previous": 0, "extrapolated": 1, "learned": 2}
 ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
 Q = 19
 MAX_SPECIES = 4
@@ -33,6 +33,9 @@ EXPORTS = (
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
+    "lbmix_net_create", "lbmix_net_num_params", "lbmix_net_get_params", "lbmix_net_set_params",
+    "lbmix_net_get_gradient", "lbmix_net_forward", "lbmix_net_gradient", "lbmix_net_adam",
+    "lbmix_net_output_scale", "lbmix_net_last_error", "lbmix_net_destroy", "lbmix_set_warm_start_net", "lbmix_train_warm_start",
 )
 
 
@@ -66,6 +69,7 @@ def load_library():
                            "(or __graft_entry__.build()); there is no CPU fallback")
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+    fp = ctypes.POINTER(ctypes.c_float)
     sig = {
         "lbmix_version": ([], ctypes.c_int),
         "lbmix_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -99,6 +103,21 @@ def load_library():
         "lbmix_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "lbmix_last_error": ([vp], ctypes.c_char_p),
         "lbmix_destroy": ([vp], None),
+        "lbmix_net_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_ulonglong],
+                             ctypes.c_int),
+        "lbmix_net_num_params": ([vp], ctypes.c_int),
+        "lbmix_net_get_params": ([vp, fp], ctypes.c_int),
+        "lbmix_net_set_params": ([vp, fp], ctypes.c_int),
+        "lbmix_net_get_gradient": ([vp, fp], ctypes.c_int),
+        "lbmix_net_forward": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "lbmix_net_gradient": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, vp],
+                               ctypes.c_int),
+        "lbmix_net_adam": ([vp, ctypes.c_float, vp], ctypes.c_int),
+        "lbmix_net_output_scale": ([vp, ctypes.c_double, dp], ctypes.c_int),
+        "lbmix_net_last_error": ([vp], ctypes.c_char_p),
+        "lbmix_net_destroy": ([vp], None),
+        "lbmix_set_warm_start_net": ([vp, vp], ctypes.c_int),
+        "lbmix_train_warm_start": ([vp, vp, ctypes.c_int, ctypes.c_float, dp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -234,6 +253,18 @@ class Lattice:
         st = self.stats()
         return st["block_x"], st["block_y"]
 
+    def set_warm_start_net(self, net):
+        """Attach a Net for the learned warm start (kept alive by this lattice)."""
+        self._ws_net = net
+        self._check(self._L.lbmix_set_warm_start_net(self._h, net._h if net is not None else None))
+
+    def train_warm_start(self, net, steps, lr=1e-3):
+        """Advance `steps` steps with the direct solve, training `net` on exact corrections;
+        returns the loss of every step."""
+        losses = np.zeros(max(int(steps), 1))
+        self._check(self._L.lbmix_train_warm_start(self._h, net._h, int(steps), float(lr), _dp(losses)))
+        return losses[:int(steps)]
+
     def step_status(self, n=1):
         """Like step() but returns the status code instead of raising on ENOCONV."""
         rc = self._L.lbmix_step(self._h, int(n))
@@ -294,6 +325,95 @@ class Lattice:
 
     def load(self, path):
         self._check(self._L.lbmix_load(self._h, str(path).encode()))
+
+
+class Net:
+    """Network of the learned warm start (lbmix_net): 3 x 3 x 3 convolutions, in_channels ->
+    hidden -> ... -> 1.  Device data are torch float32 CUDA tensors shaped [c][nz][ny][nx]."""
+
+    def __init__(self, in_channels=2, hidden=16, layers=4, seed=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the lbmix library has no CPU path")
+        self._L = load_library()
+        h = ctypes.c_void_p()
+        rc = self._L.lbmix_net_create(ctypes.byref(h), int(in_channels), int(hidden), int(layers), int(seed))
+        if rc:
+            raise LbmixError(rc, "lbmix_net_create failed")
+        self._h = h
+        self.in_channels = in_channels
+
+    def _check(self, rc):
+        if rc:
+            msg = self._L.lbmix_net_last_error(self._h)
+            raise LbmixError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.lbmix_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return self._L.lbmix_net_num_params(self._h)
+
+    def params(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        self._check(self._L.lbmix_net_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        if p.size != self.num_params:
+            raise ValueError("wrong parameter count")
+        self._check(self._L.lbmix_net_set_params(self._h, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def output_scale(self, scale=0.0):
+        """The warm start's output scale alpha (sets it when scale > 0)."""
+        cur = ctypes.c_double(0.0)
+        self._check(self._L.lbmix_net_output_scale(self._h, float(scale), ctypes.byref(cur)))
+        return cur.value
+
+    def gradient(self):
+        out = np.empty(self.num_params, dtype=np.float32)
+        self._check(self._L.lbmix_net_get_gradient(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    @staticmethod
+    def _dims(x):
+        if x.dim() != 4 or not x.is_cuda or not x.is_contiguous() or str(x.dtype) != "torch.float32":
+            raise ValueError("expected a contiguous float32 CUDA tensor [c][nz][ny][nx]")
+        return x.shape[3], x.shape[2], x.shape[1]
+
+    def forward(self, x, z_walls=False, stream=None):
+        import torch
+        nx, ny, nz = self._dims(x)
+        y = torch.empty((1, nz, ny, nx), dtype=torch.float32, device=x.device)
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self._check(self._L.lbmix_net_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                              nx, ny, nz, 1 if z_walls else 0, ctypes.c_void_p(s)))
+        return y
+
+    def loss_and_gradient(self, x, t, z_walls=False, stream=None):
+        import torch
+        nx, ny, nz = self._dims(x)
+        self._dims(t)
+        loss = ctypes.c_double(0.0)
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self._check(self._L.lbmix_net_gradient(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                               nx, ny, nz, 1 if z_walls else 0, ctypes.byref(loss), ctypes.c_void_p(s)))
+        return loss.value
+
+    def adam(self, lr, stream=None):
+        import torch
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self._check(self._L.lbmix_net_adam(self._h, ctypes.c_float(lr), ctypes.c_void_p(s)))
 
 
 def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None):

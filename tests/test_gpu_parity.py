@@ -606,3 +606,56 @@ def test_autotuned_launch_gives_identical_results(P, dims, geometry):
     b.step(6)
     for s in range(2):
         assert np.array_equal(a.populations(s), b.populations(s))
+
+
+EPS16 = {"f16s": 2.0 ** -11, "bf16s": 2.0 ** -8, "f32s": 2.0 ** -24}
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s", "f32s"])
+def test_full_size_binary_512cubed_sampled(P, oracle_mod, storage):
+    """The precision configuration at full size: 512^3 periodic binary, shifted storage
+    (stochastic rounding for 16 bits), Sc 100, multimode noise and shear (seed 4).  After k
+    steps the GPU moments at sampled nodes equal the oracle's on light-cone patches within
+    k units in the last place per population and step bound: |dn| <= 19 * 2 k eps * dev, dev
+    the largest deviation of a population from rest on the patch."""
+    k = 4
+    w = WL.binary_multimode(n=512, amp=1e-3, nmodes=8, shear=1e-3, sc=100.0, seed=4)
+    lat = gpu_for(P, w, storage)
+    lat.step(k)
+    n_all = [lat.moments(s)[0] for s in range(2)]
+    del lat
+    rng = np.random.default_rng(4)
+    centres = [(0, 0, 0), (511, 511, 511)] + [tuple(rng.integers(0, 512, 3)) for _ in range(4)]
+    for c in centres:
+        pw, h = patch_workload(w, c, k)
+        o = oracle_for(oracle_mod, pw)
+        o.step(k)
+        for s in range(2):
+            fo = o.populations(s)
+            dev = np.abs(fo - (WQ * 0.5)[:, None, None, None]).max()
+            no, _ = o.moments(s)
+            err = abs(n_all[s][c] - no[h, h, h])
+            assert err <= max(19 * 2 * k * EPS16[storage] * dev, 1e-5 * 0.5 if storage == "f32s" else 0.0), (c, s, err)
+
+
+@pytest.mark.parametrize("storage", ["f16s", "bf16s"])
+def test_full_size_ternary_slit_128x128x258_sixteen_bit(P, oracle_mod, storage):
+    """The precision slit at full size (128 x 128 x 258, ternary, lambda_D 8, sigma -1e-4,
+    Sc 100), direct Poisson solve on both sides: densities on the whole lattice after k steps
+    within the stochastic-rounding bound.  The rounding of every species' stored deviations
+    reaches the others within a step through the drag and the barycentric velocity, so the
+    bound uses the largest deviation of any species (the solvent itself barely leaves rest)."""
+    k = 3
+    w = WL.charged_slit(nx=128, ny=128, nz=258, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    lat = gpu_for(P, w, storage, poisson=dict(method="direct"))
+    lat.step(k)
+    o = oracle_for(oracle_mod, w, poisson="direct")
+    o.step(k)
+    m = fluid(w)
+    dev = max(np.abs(o.populations(s) - (WQ * w.rho0[s])[:, None, None, None])[:, m].max() for s in range(3))
+    for s in range(3):
+        ng, _ = lat.moments(s)
+        no, _ = o.moments(s)
+        err = np.abs(ng - no)[m].max()
+        assert err <= 19 * 2 * k * EPS16[storage] * dev, (s, err, dev)
+        assert err > 0.0
