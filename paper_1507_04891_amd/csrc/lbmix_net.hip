@@ -142,13 +142,17 @@ __global__ void finish_scale(double *s, uint32_t N) {
     }
 }
 
-__global__ __launch_bounds__(NET_BLOCK) void net_input(const double *r, const double *scale, float *x, uint32_t nxy,
-                                                       uint32_t nzf, const float *mask) {
+__global__ __launch_bounds__(NET_BLOCK) void net_input(const double *r, const double *p1, const double *p2,
+                                                       const double *guess, const double *scale, float *x,
+                                                       uint32_t nxy, uint32_t nzf, const float *mask) {
     const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
     const uint32_t N = nxy * nzf;
     if (i >= N) return;
-    x[i] = (float)(r[i] / *scale);
-    x[N + i] = mask ? mask[i / nxy] : 0.0f;
+    const double inv = 1.0 / *scale, a = p1[i];
+    x[i] = (float)(r[i] * inv);
+    x[N + i] = (float)((a - p2[i]) * inv);
+    x[2 * N + i] = (float)((guess[i] - a) * inv);
+    x[3 * N + i] = mask ? mask[i / nxy] : 0.0f;
 }
 
 __global__ __launch_bounds__(NET_BLOCK) void add_correction(double *psi, const float *y, const double *scale,
@@ -211,9 +215,11 @@ hipError_t launch_finish_scale(double *scale, uint32_t N, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_net_input(const double *r, const double *scale, float *x, uint32_t nxy, uint32_t nzf,
-                            const float *plane_mask, hipStream_t stream) {
-    hipLaunchKernelGGL(net_input, grid_of(nxy * nzf), dim3(NET_BLOCK), 0, stream, r, scale, x, nxy, nzf, plane_mask);
+hipError_t launch_net_input(const double *r, const double *p1, const double *p2, const double *guess,
+                            const double *scale, float *x, uint32_t nxy, uint32_t nzf, const float *plane_mask,
+                            hipStream_t stream) {
+    hipLaunchKernelGGL(net_input, grid_of(nxy * nzf), dim3(NET_BLOCK), 0, stream, r, p1, p2, guess, scale, x, nxy, nzf,
+                       plane_mask);
     return hipGetLastError();
 }
 

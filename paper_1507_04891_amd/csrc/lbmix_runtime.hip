@@ -764,7 +764,7 @@ int ensure_ws_buffers(lbmix_ctx *c) {
     if ((rc = c->hip(hipMalloc((void **)&c->ws_r, N * sizeof(double)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_guess, N * sizeof(double)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_scale, sizeof(double)), "hipMalloc(warm start)")) ||
-        (rc = c->hip(hipMalloc((void **)&c->ws_x, 2 * N * sizeof(float)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_x, WS_CHANNELS * N * sizeof(float)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_y, N * sizeof(float)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_t, N * sizeof(float)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_mask, (size_t)c->nzf * sizeof(float)), "hipMalloc(warm start)")))
@@ -779,7 +779,9 @@ int ensure_ws_buffers(lbmix_ctx *c) {
                   "copy mask");
 }
 
-// Network input from the residual of the current guess: x = (r / s, wall mask), s = rms(r).
+// Network input after the extrapolation (history complete): the residual of the guess, the
+// last two increments of the potential (psi(t-1) - psi(t-2), psi(t-2) - psi(t-3) = guess -
+// psi(t-1)), all over s = rms(r), and the wall mask.
 int net_sample_input(lbmix_ctx *c, const PoissonArgs &pa) {
     int rc = ensure_ws_buffers(c);
     if (rc) return rc;
@@ -788,8 +790,8 @@ int net_sample_input(lbmix_ctx *c, const PoissonArgs &pa) {
         (rc = c->hip(launch_finalize(c->partials, nb, 1, c->ws_scale, 0, 0.0, 0.0, 1.0, c->stream), "finalize")) ||
         (rc = c->hip(launch_finish_scale(c->ws_scale, c->Nf, c->stream), "finish_scale")))
         return rc;
-    return c->hip(launch_net_input(c->ws_r, c->ws_scale, c->ws_x, (uint32_t)c->nx * c->ny, (uint32_t)c->nzf,
-                                   c->ws_mask, c->stream),
+    return c->hip(launch_net_input(c->ws_r, c->psi_prev, c->psi_prev + c->Nf, c->psi, c->ws_scale, c->ws_x,
+                                   (uint32_t)c->nx * c->ny, (uint32_t)c->nzf, c->ws_mask, c->stream),
                   "net_input");
 }
 
@@ -842,8 +844,9 @@ int solve(lbmix_ctx *c) {
     }
     if ((rc = channel_means(c, c->q, 0, 0))) return rc;
     if (c->warm_start >= 1 && c->psi_valid) {
+        const bool history = c->have_prev >= 2;   // the extrapolation below is the full one
         if ((rc = extrapolated_guess(c))) return rc;
-        if (c->warm_start == 2 && (rc = learned_correction(c, pa))) return rc;
+        if (c->warm_start == 2 && history && (rc = learned_correction(c, pa))) return rc;
     }
     int work = 0, status = LBMIX_OK;
     if (c->poisson_method == 1) {
@@ -1233,8 +1236,8 @@ int lbmix_set_poisson_warm_start(lbmix_ctx *c, int mode) {
 
 int lbmix_set_warm_start_net(lbmix_ctx *c, lbmix_net *net) {
     if (!c) return LBMIX_EINVAL;
-    if (net && net_in_channels(net) != 2)
-        return c->fail(LBMIX_EINVAL, "the warm-start network takes 2 input channels (residual, wall mask)");
+    if (net && net_in_channels(net) != WS_CHANNELS)
+        return c->fail(LBMIX_EINVAL, "the warm-start network takes %d input channels", WS_CHANNELS);
     if (net && c->allocated && net_device(net) != c->device)
         return c->fail(LBMIX_EINVAL, "the network lives on device %d, the lattice on %d", net_device(net), c->device);
     if (!net && c->warm_start == 2) c->warm_start = 1;
@@ -1245,8 +1248,8 @@ int lbmix_set_warm_start_net(lbmix_ctx *c, lbmix_net *net) {
 int lbmix_train_warm_start(lbmix_ctx *c, lbmix_net *net, int nsteps, float lr, double *losses) {
     int rc = check_ready(c);
     if (rc) return rc;
-    if (!net || net_in_channels(net) != 2 || nsteps < 0 || !(lr > 0.0f))
-        return c->fail(LBMIX_EINVAL, "training needs a 2-channel network, nsteps >= 0 and lr > 0");
+    if (!net || net_in_channels(net) != WS_CHANNELS || nsteps < 0 || !(lr > 0.0f))
+        return c->fail(LBMIX_EINVAL, "training needs a %d-channel network, nsteps >= 0 and lr > 0", WS_CHANNELS);
     if (!c->charged()) return c->fail(LBMIX_EINVAL, "no charged species: there is no Poisson solve to learn");
     if (c->latched) return c->fail(c->latched, "context latched an earlier error (%d)", c->latched);
     Guard g(c);
@@ -1263,10 +1266,19 @@ int lbmix_train_warm_start(lbmix_ctx *c, lbmix_net *net, int nsteps, float lr, d
             return rc;
         c->cur ^= 1;
         c->steps++;
-        // sample: the residual of the extrapolated guess and the exact correction to it
+        // sample: the residual of the extrapolated guess and the exact correction to it (once
+        // the history is complete; before that the step only solves)
         const PoissonArgs pa = c->pargs();
-        if ((rc = channel_means(c, c->q, 0, 0)) || (rc = extrapolated_guess(c)) || (rc = net_sample_input(c, pa)))
-            return rc;
+        const bool history = c->have_prev >= 2;
+        if ((rc = channel_means(c, c->q, 0, 0)) || (rc = extrapolated_guess(c))) return rc;
+        if (!history) {
+            if ((rc = spec_solve(c, pa))) return rc;
+            c->solves++;
+            c->total_sweeps++;
+            if (losses) losses[k] = 0.0;
+            continue;
+        }
+        if ((rc = net_sample_input(c, pa))) return rc;
         if ((rc = c->hip(hipMemcpyAsync(c->ws_guess, c->psi, (size_t)c->Nf * sizeof(double), hipMemcpyDeviceToDevice,
                                         c->stream),
                          "copy guess")))
