@@ -127,6 +127,9 @@ def bench_slit(args):
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson, warm_start=args.warm_start))
     out["launch"] = lat.autotune(reps=3) if args.autotune else None
+    out["graph"] = bool(args.graph)
+    if args.graph:
+        lat.set_step_graph(True)
     t0 = time.perf_counter()
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -165,6 +168,8 @@ def bench_channels(args):
                           poisson=dict(rel_tol=1e-8, max_sweeps=1000000, check_every=args.check_every,
                                        method=args.poisson))
     shape = lat.autotune(reps=3) if args.autotune else None
+    if args.graph:
+        lat.set_step_graph(True)
     lat.step(args.warmup)
     torch.cuda.synchronize()
     st0 = lat.stats()
@@ -180,7 +185,7 @@ def bench_channels(args):
     sites = w.nspecies * nodes
     print(json.dumps({"workload": f"{len(w.widths)} charged slit channels {w.nx}x{w.ny}xW, W in "
                                   f"{min(w.widths)}..{max(w.widths)} (seed 5), {nodes} fluid nodes, Sc 10/100/1000",
-                      "storage": args.storage, "poisson_method": args.poisson, "launch": shape,
+                      "storage": args.storage, "poisson_method": args.poisson, "launch": shape, "graph": args.graph,
                       "ms_per_step": round(ms, 4), "glups": round(sites / (ms * 1e-3) / 1e9, 3),
                       "poisson_work_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 2),
                       "last_residual": st1["last_residual"]}), flush=True)
@@ -231,6 +236,59 @@ def bench_warmstart(args):
                      "cycles_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 3),
                      "last_residual": st1["last_residual"]}
         print(f"{name} done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision_large(args):
+    """Transport coefficients at the precision configuration's full size: 512^3 periodic
+    binary, multimode noise (8 modes, seed 4) and shear wave, Sc 100.  D from the decay of
+    concentration mode m = 7 (wavenumber 2 pi 7 / 512 along x, which the shear flow u_y(x)
+    does not advect), nu from the shear wave u_y(x), each storage form against FP64 storage
+    over the same steps."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    n = 512
+    w = WL.binary_multimode(n=n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=100.0, seed=4)
+    ax = np.arange(n)
+    km, kx = 2 * math.pi * 7 / n, 2 * math.pi / n
+    t1, t2 = 200, args.steps
+    out = {"workload": f"binary 512^3 multimode (seed 4), Sc 100; D from mode m=7 along x, nu from the shear "
+                       f"wave; steps {t1}..{t2}"}
+
+    def amps(lat):
+        n0, j0 = lat.moments(0)
+        _, j1 = lat.moments(1)
+        c = np.cos(km * ax)[None, None, :]
+        sn = np.sin(km * ax)[None, None, :]
+        dn = n0 - 0.5
+        a_m = math.hypot(float((dn * c).sum()), float((dn * sn).sum()))
+        a_s = float(((j0[1] + j1[1]) * np.sin(kx * ax)[None, None, :]).sum())
+        return a_m, a_s
+
+    for st, sr in [("f64", None), ("f32s", None), ("f16s", True), ("bf16s", True), ("f32", None)]:
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
+        lat.step(t1)
+        a1 = amps(lat)
+        lat.step(t2 - t1)
+        a2 = amps(lat)
+        del lat
+        torch.cuda.empty_cache()
+        key = st + ("" if sr is None else " SR")
+        out[f"D {key}"] = -math.log(a2[0] / a1[0]) / (t2 - t1) / km ** 2 if a2[0] > 0 and a1[0] > 0 else None
+        out[f"nu {key}"] = -math.log(a2[1] / a1[1]) / (t2 - t1) / kx ** 2
+        print(f"{key} done", file=sys.stderr, flush=True)
+    for key in list(out):
+        if key == "workload" or " f64" in key or out[key] is None:
+            continue
+        ref = out[key.split(" ")[0] + " f64"]
+        out["err " + key] = out[key] / ref - 1.0 if ref else None
     print(json.dumps(out), flush=True)
 
 
@@ -313,6 +371,7 @@ def main():
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--graph", action="store_true", help="replay steps as captured HIP graphs")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library pick the work-group shape of the step (default: its default shape)")
     ap.add_argument("--workload", default="binary",
@@ -322,6 +381,8 @@ def main():
     ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid", "direct"])
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--train-steps", type=int, default=300, help="training steps of the warm-start network")
+    ap.add_argument("--size", default="small", choices=["small", "large"],
+                    help="precision workload: small lattices (default) or the 512^3 configuration")
     ap.add_argument("--warm-start", default="previous", choices=["previous", "extrapolated"])
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (3 times), the reference "
@@ -340,7 +401,10 @@ def main():
         bench_channels(args)
         return
     if args.workload == "precision":
-        bench_precision(args)
+        if args.size == "large":
+            bench_precision_large(args)
+        else:
+            bench_precision(args)
         return
     if args.workload == "warmstart":
         bench_warmstart(args)

@@ -141,6 +141,14 @@ int lbmix_set_tau_drag(lbmix_ctx *ctx, double tau_drag);
  * tau_visc changes.  Errors: EINVAL unless Sc > 0; ESTATE after the first step. */
 int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
 
+/* enable != 0: replay each step as a captured HIP graph (the fused step, the direct Poisson
+ * solve and the step count from which the stochastic-rounding seed is derived, captured
+ * once per buffer parity) when a step needs no host decision: no Poisson solve, or the
+ * direct one.  Other steps run as before.  Results are bitwise those of uncaptured steps;
+ * the stats residual is then evaluated once per lbmix_step call.  Default 0.  Errors:
+ * EINVAL for a null context. */
+int lbmix_set_step_graph(lbmix_ctx *ctx, int enable);
+
 /* Time `reps` launches of the fused stream-collide step for each candidate work-group shape
  * (64 to 512 threads: rows of 64, 128 or 256 nodes times 1 to 8 rows; for planes narrower
  * than 64 nodes, whole rows filling 64 to 512 threads) on the current state, twice, and keep

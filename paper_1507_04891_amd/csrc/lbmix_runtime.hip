@@ -98,6 +98,12 @@ struct lbmix_ctx {
     hipStream_t cap_stream = nullptr;  // capture-only stream (graphs replay on `stream`)
     hipGraph_t vgraph = nullptr;
     hipGraphExec_t vexec = nullptr;
+    // captured steps (fused step + direct solve), one per buffer parity, and the device step
+    // count they derive the rounding seed from
+    int use_graph = 0;
+    hipGraph_t sgraph[2] = {nullptr, nullptr};
+    hipGraphExec_t sexec[2] = {nullptr, nullptr};
+    unsigned long long *step_dev = nullptr;
     // direct solve: orthonormal bases of the periodic axes, their eigenvalues, the inverse
     // pivots of the z systems (slit), segment bounds, two work arrays
     double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
@@ -214,13 +220,9 @@ struct lbmix_ctx {
         a.stochastic = rounding;
         a.block_x = blk_x;
         a.block_y = blk_y;
-        {   // per-step seed: a splitmix64 finaliser of (seed, step), folded to 32 bits
-            unsigned long long z = round_seed + 0x9e3779b97f4a7c15ull * (unsigned long long)(steps + 1);
-            z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-            z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-            z ^= z >> 31;
-            a.seed = (uint32_t)(z ^ (z >> 32));
-        }
+        a.seed = step_seed(round_seed, (unsigned long long)(steps + 1));
+        a.step_dev = nullptr;
+        a.round_seed = round_seed;
         return a;
     }
     PoissonArgs pargs() const {
@@ -257,12 +259,18 @@ struct lbmix_ctx {
 
 namespace {
 
-// A captured V-cycle holds the Poisson arguments by value; drop it when they change.
+// Captured graphs hold their arguments by value; drop them when these change.
 void drop_graph(lbmix_ctx *c) {
     if (c->vexec) (void)hipGraphExecDestroy(c->vexec);
     if (c->vgraph) (void)hipGraphDestroy(c->vgraph);
     c->vexec = nullptr;
     c->vgraph = nullptr;
+    for (int k = 0; k < 2; ++k) {
+        if (c->sexec[k]) (void)hipGraphExecDestroy(c->sexec[k]);
+        if (c->sgraph[k]) (void)hipGraphDestroy(c->sgraph[k]);
+        c->sexec[k] = nullptr;
+        c->sgraph[k] = nullptr;
+    }
 }
 
 int ensure_scratch(lbmix_ctx *c, size_t bytes) {
@@ -932,6 +940,49 @@ int solve(lbmix_ctx *c) {
     return status;
 }
 
+// A step needs no host decision when there is no Poisson solve or it is the direct one.
+bool step_capturable(const lbmix_ctx *c) { return !c->charged() || c->poisson_method == 2; }
+
+// Capture the step that reads buffer `par`: fused step, direct solve, step count + 1.
+int capture_step(lbmix_ctx *c, int par) {
+    int rc;
+    if (!c->cap_stream &&
+        (rc = c->hip(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate")))
+        return rc;
+    if (!c->step_dev && (rc = c->hip(hipMalloc((void **)&c->step_dev, sizeof(unsigned long long)), "hipMalloc(step)")))
+        return rc;
+    const bool charged = c->charged(), field = c->field();
+    if (charged && (rc = spec_build(c))) return rc;   // allocations stay out of the capture
+    const int save_cur = c->cur;
+    hipStream_t save = c->stream;
+    c->cur = par;
+    c->stream = c->cap_stream;
+    if ((rc = c->hip(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal), "capture"))) {
+        c->cur = save_cur;
+        c->stream = save;
+        return rc;
+    }
+    StepArgs a = c->args();
+    a.step_dev = c->step_dev;
+    int r1 = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->cap_stream), "stream_collide");
+    if (!r1 && charged) {
+        c->cur = par ^ 1;   // the solve sees the state the step writes (q is written by the step)
+        r1 = spec_solve(c, c->pargs());
+    }
+    if (!r1) r1 = c->hip(launch_advance_step(c->step_dev, c->cap_stream), "advance_step");
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+    c->cur = save_cur;
+    c->stream = save;
+    if (r1) {
+        if (g) (void)hipGraphDestroy(g);
+        return r1;
+    }
+    if ((rc = c->hip(e, "hipStreamEndCapture"))) return rc;
+    c->sgraph[par] = g;
+    return c->hip(hipGraphInstantiate(&c->sexec[par], g, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
 int initial_potential(lbmix_ctx *c) {
     int rc = ensure_field_buffers(c);
     if (rc) return rc;
@@ -1395,6 +1446,29 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
     }
     int status = LBMIX_OK;
     const bool field = c->field();
+    if (c->use_graph && step_capturable(c) && nsteps > 0) {
+        for (int par = 0; par < 2; ++par)
+            if (!c->sexec[par] && (rc = capture_step(c, par))) return rc;
+        if ((rc = c->hip(launch_set_step(c->step_dev, (unsigned long long)c->steps, c->stream), "set_step"))) return rc;
+        for (int k = 0; k < nsteps; ++k) {
+            if ((rc = c->hip(hipGraphLaunch(c->sexec[c->cur], c->stream), "hipGraphLaunch"))) return rc;
+            c->cur ^= 1;
+            c->steps++;
+            if (charged) {
+                c->solves++;
+                c->total_sweeps++;
+                c->last_sweeps = 1;
+                c->last_status = LBMIX_OK;
+                c->direct_count++;
+            }
+        }
+        if (charged) {   // the residual of the last solve, for the stats
+            const PoissonArgs pa = c->pargs();
+            if ((rc = channel_means(c, c->q, 0, 0)) || (rc = residual(c, pa))) return rc;
+            c->resid_on_device = true;
+        }
+        return LBMIX_OK;
+    }
     for (int k = 0; k < nsteps; ++k) {
         const StepArgs a = c->args();
         rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
@@ -1411,6 +1485,12 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
     }
     if (status == LBMIX_ENOCONV)
         return c->fail(LBMIX_ENOCONV, "Poisson solve reached %d sweeps at residual %.3e", c->sor_max, c->last_resid);
+    return LBMIX_OK;
+}
+
+int lbmix_set_step_graph(lbmix_ctx *c, int enable) {
+    if (!c) return LBMIX_EINVAL;
+    c->use_graph = enable ? 1 : 0;
     return LBMIX_OK;
 }
 
@@ -1464,6 +1544,7 @@ int lbmix_autotune(lbmix_ctx *c, int reps) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
+    if (bx != c->blk_x || by != c->blk_y) drop_graph(c);   // captured steps hold the launch shape
     c->blk_x = bx;
     c->blk_y = by;
     return LBMIX_OK;
@@ -1784,6 +1865,7 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (double *p : {c->sp_tx, c->sp_ty, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
+        if (c->step_dev) (void)hipFree(c->step_dev);
         for (void *p : {(void *)c->d_planes, (void *)c->d_fof, (void *)c->d_first, (void *)c->d_chan,
                         (void *)c->d_psums})
             if (p) (void)hipFree(p);

@@ -53,6 +53,8 @@ struct StepArgs {
     double *partials;                // out: [species][block] FP64 sums of n - rho_bar
     int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
     uint32_t seed;                   // per-step seed of the rounding hash
+    const unsigned long long *step_dev;  // non-null (captured steps): seed from the step count
+    unsigned long long round_seed;       // ... here, as the host derives it
     uint32_t block_x, block_y;       // launch shape of stream_collide (0: the default shape)
 };
 
@@ -64,6 +66,20 @@ dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx 
 
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
                                  const StepArgs &a, hipStream_t stream);
+
+// Per-step rounding seed: a splitmix64 finaliser of seed + golden-ratio increment x step,
+// folded to 32 bits (step = completed steps + 1).
+__host__ __device__ inline uint32_t step_seed(unsigned long long seed, unsigned long long step) {
+    unsigned long long z = seed + 0x9e3779b97f4a7c15ull * step;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    z ^= z >> 31;
+    return (uint32_t)(z ^ (z >> 32));
+}
+
+// *step += 1 (one thread): the step count of captured steps; set_step: *step = value.
+hipError_t launch_advance_step(unsigned long long *step, hipStream_t stream);
+hipError_t launch_set_step(unsigned long long *step, unsigned long long value, hipStream_t stream);
 
 // Equilibrium of species s from host-layout device arrays n[N_full], u[3][N_full] (u may
 // be null), scattered into the slots the first pull reads.

@@ -396,7 +396,8 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     const C keep = C(1) - ov;
     auto collide_store = [&](auto sr_tag) {
         constexpr bool SR = decltype(sr_tag)::value;
-        uint32_t rs = SR ? (mix32(own ^ a.seed) | 1u) : 0u;
+        const uint32_t seed = a.step_dev ? step_seed(a.round_seed, *a.step_dev + 1ull) : a.seed;
+        uint32_t rs = SR ? (mix32(own ^ seed) | 1u) : 0u;
         auto rbits = [&](int s) -> uint32_t {     // the conversions use the high bits
             if constexpr (!SR) return 0u;
             if ((s & 1) == 0) rs = xorshift32(rs);
@@ -669,6 +670,24 @@ template <class T, bool SLIT> struct ChargeK {
         return hipGetLastError();
     }
 };
+
+__global__ void advance_step(unsigned long long *step) {
+    if (threadIdx.x == 0) *step += 1ull;
+}
+
+__global__ void set_step(unsigned long long *step, unsigned long long value) {
+    if (threadIdx.x == 0) *step = value;
+}
+
+hipError_t launch_advance_step(unsigned long long *step, hipStream_t stream) {
+    hipLaunchKernelGGL(advance_step, dim3(1), dim3(64), 0, stream, step);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_step(unsigned long long *step, unsigned long long value, hipStream_t stream) {
+    hipLaunchKernelGGL(set_step, dim3(1), dim3(64), 0, stream, step, value);
+    return hipGetLastError();
+}
 
 hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n, const double *u,
                        hipStream_t stream) {

@@ -29,7 +29,7 @@ EXPORTS = (
     "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_drag_pairs",
     "lbmix_set_electrostatics",
     "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
-    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_autotune", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_autotune", "lbmix_set_step_graph", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
@@ -91,6 +91,7 @@ def load_library():
         "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_step": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_autotune": ([vp, ctypes.c_int], ctypes.c_int),
+        "lbmix_set_step_graph": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_get_moments": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_get_moments_device": ([vp, ctypes.c_int, vp, vp], ctypes.c_int),
         "lbmix_get_populations": ([vp, ctypes.c_int, dp], ctypes.c_int),
@@ -246,6 +247,10 @@ class Lattice:
     # -- stepping -------------------------------------------------------------------------
     def step(self, n=1):
         return self._check(self._L.lbmix_step(self._h, int(n)))
+
+    def set_step_graph(self, enable=True):
+        """Replay steps as captured HIP graphs where no host decision is needed."""
+        self._check(self._L.lbmix_set_step_graph(self._h, 1 if enable else 0))
 
     def autotune(self, reps=5):
         """Pick the fastest work-group shape of the step kernel; returns (block_x, block_y)."""

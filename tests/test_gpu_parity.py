@@ -659,3 +659,27 @@ def test_full_size_ternary_slit_128x128x258_sixteen_bit(P, oracle_mod, storage):
         err = np.abs(ng - no)[m].max()
         assert err <= 19 * 2 * k * EPS16[storage] * dev, (s, err, dev)
         assert err > 0.0
+
+
+@pytest.mark.parametrize("case", ["binary_f32s", "slit_direct_f32s", "channels_bf16s"])
+def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
+    """Captured steps (fused step + direct solve + step count) replay exactly the uncaptured
+    sequence, including the stochastic-rounding stream of the 16-bit forms."""
+    if case == "binary_f32s":
+        w, storage, poisson = WL.binary_multimode(n=24, amp=1e-2, nmodes=4, shear=1e-2, sc=30.0, seed=3), "f32s", None
+    elif case == "slit_direct_f32s":
+        w = WL.charged_slit(nx=16, ny=8, nz=34, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+        storage, poisson = "f32s", dict(method="direct")
+    else:
+        w, storage, poisson = WL.channel_stack(**SMALL_STACK), "bf16s", dict(method="direct")
+    a = P.from_workload(w, storage=storage, poisson=poisson)
+    b = P.from_workload(w, storage=storage, poisson=poisson)
+    a.set_step_graph(True)
+    a.step(3)
+    a.step(9)
+    b.step(12)
+    for s in range(w.nspecies):
+        assert np.array_equal(a.populations(s), b.populations(s)), s
+    assert np.array_equal(a.potential(), b.potential())
+    sa, sb = a.stats(), b.stats()
+    assert sa["steps"] == sb["steps"] == 12 and sa["poisson_solves"] == sb["poisson_solves"]
