@@ -54,6 +54,7 @@ class _Params(ctypes.Structure):
         ("sor_omega", ctypes.c_double), ("sor_tol", ctypes.c_double),
         ("sor_max", ctypes.c_int), ("sor_check", ctypes.c_int),
         ("pair_drag", ctypes.c_int), ("drag_pair", ctypes.c_double * (MAXS * MAXS)),
+        ("forcing", ctypes.c_int),
     ]
 
 
@@ -154,7 +155,7 @@ class Oracle:
     def __init__(self, nx, ny, nz, nspecies, omega_visc, omega_drag, geometry="periodic",
                  valence=None, bjerrum=0.0, sigma=(0.0, 0.0), E=(0.0, 0.0, 0.0),
                  poisson="direct", lagged=True, sor_omega=None, sor_tol=1e-8,
-                 sor_max=100000, sor_check=10, drag_pair=None):
+                 sor_max=100000, sor_check=10, drag_pair=None, forcing="paper"):
         if nspecies > MAXS:
             raise ValueError("too many species")
         p = _Params()
@@ -176,6 +177,7 @@ class Oracle:
         p.sor_tol = sor_tol
         p.sor_max = sor_max
         p.sor_check = sor_check
+        p.forcing = {"paper": 0, "guo": 1}[forcing]
         if drag_pair is not None:   # [ns][ns] drag frequencies omega^{ab}
             om = np.asarray(drag_pair, dtype=np.float64).reshape(nspecies, nspecies)
             p.pair_drag = 1

@@ -49,6 +49,12 @@
  *        step t uses the potential solved from q(t-1); before the first step the potential
  *        is solved from q(0).
  *   [R8] Initial populations are the discrete equilibrium of the given n^alpha, u^alpha.
+ *
+ * Forcing variant (forcing = 1), a second-order scheme of the Guo type: every species moves
+ * with v^alpha = u^alpha + F^alpha / 2 in the equilibrium and in the drag, the drag is then
+ * implicit in F, F^alpha = a^alpha - omega_drag sum_b (n^b / n)(v^alpha - v^b), and the
+ * forcing term is (1 - omega_visc / 2) g_p(F^alpha, v) with v the barycentric average of the
+ * v^alpha.  The implicit drag is solved per node as the dense linear system it is.
  */
 #include <math.h>
 #include <stdio.h>
@@ -104,6 +110,7 @@ typedef struct {
     int sor_check;         /* sweeps between residual evaluations */
     int pair_drag;         /* 1: drag frequency per pair of species from drag_pair */
     double drag_pair[ORA_MAXS * ORA_MAXS]; /* omega^{ab} at [a * ORA_MAXS + b], symmetric */
+    int forcing;           /* 0: g with u^alpha, drag on mid-step velocities; 1: the Guo-type variant */
 } ora_params;
 
 typedef struct {
@@ -208,6 +215,48 @@ void ora_drag_pair(int ns, const double *n, const double *ua, const double *omeg
                 for (int b = 0; b < ns; ++b)
                     acc += omega[a * ld + b] * (n[b] / ntot) * (ua[3 * a + d] - ua[3 * b + d]);
             F[3 * a + d] = -acc;
+        }
+    }
+}
+
+/* Force of the Guo-type variant: F^a = a^a - omega sum_b (n^b / n)(v^a - v^b) with
+ * v^a = u^a + F^a / 2, i.e. per Cartesian component the linear system
+ *   sum_b [delta_ab + (omega / 2) M_ab] F^b = a^a - omega sum_b M_ab u^b,
+ *   M_ab = delta_ab - n^b / n,
+ * solved by Gaussian elimination with partial pivoting.  ua, acc, F are [ns][3]. */
+void ora_guo_force(int ns, const double *n, const double *ua, const double *acc, double omega, double *F) {
+    double ntot = 0.0;
+    for (int b = 0; b < ns; ++b) ntot += n[b];
+    for (int d = 0; d < 3; ++d) {
+        double A[ORA_MAXS][ORA_MAXS + 1];
+        for (int a = 0; a < ns; ++a) {
+            double rhs = acc[3 * a + d];
+            for (int b = 0; b < ns; ++b) {
+                const double M = (a == b ? 1.0 : 0.0) - (ntot != 0.0 ? n[b] / ntot : 0.0);
+                A[a][b] = (a == b ? 1.0 : 0.0) + 0.5 * omega * M;
+                rhs -= omega * M * ua[3 * b + d];
+            }
+            A[a][ns] = rhs;
+        }
+        for (int k = 0; k < ns; ++k) {
+            int piv = k;
+            for (int r = k + 1; r < ns; ++r)
+                if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+            if (piv != k)
+                for (int j = 0; j <= ns; ++j) {
+                    const double t = A[k][j];
+                    A[k][j] = A[piv][j];
+                    A[piv][j] = t;
+                }
+            for (int r = k + 1; r < ns; ++r) {
+                const double m = A[r][k] / A[k][k];
+                for (int j = k; j <= ns; ++j) A[r][j] -= m * A[k][j];
+            }
+        }
+        for (int a = ns - 1; a >= 0; --a) {
+            double v = A[a][ns];
+            for (int j = a + 1; j < ns; ++j) v -= A[a][j] * F[3 * j + d];
+            F[3 * a + d] = v / A[a][a];
         }
     }
 }
@@ -490,6 +539,8 @@ static int solve_potential(ora_ctx *c, const double *q) {
 ora_ctx *ora_create(const ora_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->ns < 1 || p->ns > ORA_MAXS) return NULL;
     if (p->slit && p->nz < 3) return NULL;
+    if (p->forcing != 0 && p->forcing != 1) return NULL;
+    if (p->forcing == 1 && p->pair_drag) return NULL;
     ora_ctx *c = (ora_ctx *)calloc(1, sizeof(ora_ctx));
     c->p = *p;
     c->N = (long)p->nx * p->ny * p->nz;
@@ -660,13 +711,29 @@ static int one_step(ora_ctx *c) {
                 acc[3 * s + d] = P->valence[s] * (P->E[d] - VT2 * gp[d]);
                 umid[3 * s + d] = ua[3 * s + d] + 0.5 * acc[3 * s + d];
             }
-        /* drag on the mid-step velocities [R3b], then the total force */
-        if (P->pair_drag)
-            ora_drag_pair(ns, n, umid, P->drag_pair, ORA_MAXS, F);
-        else
-            ora_drag(ns, n, umid, P->omega_drag, F);
-        for (int s = 0; s < ns; ++s)
-            for (int d = 0; d < 3; ++d) F[3 * s + d] += acc[3 * s + d];
+        double gscale = 1.0;
+        if (P->forcing == 1) {
+            /* Guo-type variant: solve F = a - omega (I - 1 w^T)(u + F/2) per component, w_b =
+             * n^b / n, then move every species (and the barycentric velocity) half a force
+             * step */
+            ora_guo_force(ns, n, ua, acc, P->omega_drag, F);
+            for (int s = 0; s < ns; ++s)
+                for (int d = 0; d < 3; ++d) ua[3 * s + d] += 0.5 * F[3 * s + d];
+            for (int d = 0; d < 3; ++d) {
+                double sum = 0.0;
+                for (int s = 0; s < ns; ++s) sum += n[s] * ua[3 * s + d];
+                u[d] = ntot != 0.0 ? sum / ntot : 0.0;
+            }
+            gscale = 1.0 - 0.5 * P->omega_visc;
+        } else {
+            /* drag on the mid-step velocities [R3b], then the total force */
+            if (P->pair_drag)
+                ora_drag_pair(ns, n, umid, P->drag_pair, ORA_MAXS, F);
+            else
+                ora_drag(ns, n, umid, P->omega_drag, F);
+            for (int s = 0; s < ns; ++s)
+                for (int d = 0; d < 3; ++d) F[3 * s + d] += acc[3 * s + d];
+        }
 
         for (int s = 0; s < ns; ++s) {
             double phi[ORA_Q], g[ORA_Q];
@@ -674,7 +741,7 @@ static int one_step(ora_ctx *c) {
             ora_forcing(n[s], &F[3 * s], u, g);
             for (int p = 0; p < ORA_Q; ++p) {
                 double f = c->f[((long)s * ORA_Q + p) * N + i];
-                double post = f - P->omega_visc * (f - phi[p]) + g[p];
+                double post = f - P->omega_visc * (f - phi[p]) + gscale * g[p];
                 int xd = wrap(x + CV[p][0], P->nx), yd = wrap(y + CV[p][1], P->ny), zd = z + CV[p][2];
                 if (P->slit && is_wall_plane(c, zd)) {
                     /* half-way bounce-back: returns to the same node, reversed [R5] */

@@ -92,3 +92,20 @@ def test_channel_stack_validation_without_device(L):
     assert L.lbmix_create(ctypes.byref(h), 8, 8, 10, 1, 2, None) == 0
     assert L.lbmix_set_channel(h, 0, 0.6, 0, 0) == -1              # not a stack
     L.lbmix_destroy(h)
+
+
+def test_network_validation_without_device(L):
+    h = ctypes.c_void_p()
+    for args in [(0, 16, 4), (17, 16, 4), (2, 0, 4), (2, 17, 4), (2, 16, 0), (2, 16, 17)]:
+        assert L.lbmix_net_create(ctypes.byref(h), *args, 0) == -1, args
+    assert L.lbmix_net_num_params(None) == -1
+    assert L.lbmix_net_adam(None, ctypes.c_float(1e-3), None) == -1
+    assert L.lbmix_net_output_scale(None, ctypes.c_double(1.0), None) == -1
+    assert L.lbmix_set_warm_start_net(None, None) == -1
+    # a lattice without a network rejects the learned warm start
+    assert L.lbmix_create(ctypes.byref(h), 8, 8, 10, 1, 2, None) == 0
+    assert L.lbmix_set_poisson_warm_start(h, 2) == -1
+    assert L.lbmix_set_poisson_warm_start(h, 3) == -1
+    assert L.lbmix_set_step_graph(h, 1) == 0
+    L.lbmix_destroy(h)
+    L.lbmix_net_destroy(None)

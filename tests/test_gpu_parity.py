@@ -683,3 +683,41 @@ def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
     assert np.array_equal(a.potential(), b.potential())
     sa, sb = a.stats(), b.stats()
     assert sa["steps"] == sb["steps"] == 12 and sa["poisson_solves"] == sb["poisson_solves"]
+
+
+def test_degenerate_cases(P, oracle_mod):
+    """A species absent everywhere stays absent and leaves the others exactly as without it;
+    step(0) changes nothing; a single-node lattice and the stiffest drag (Sc = 1000, omega_drag
+    = 1.998) follow the oracle at the FP64 bar."""
+    # absent species (R12: its velocity is 0 where its density is 0)
+    w3 = WL.random_state(10, 6, 4, 3, seed=41, rho0=[0.6, 0.4, 0.3], dn=0.05, du=0.02)
+    w3.n[2] = np.zeros_like(w3.n[2])
+    w2 = WL.Workload("two", 10, 6, 4, "periodic", w3.rho0[:2], w3.valence[:2], w3.tau_visc, w3.tau_drag,
+                     w3.n[:2], w3.u[:2])
+    a = gpu_for(P, w3, "f64")
+    b = gpu_for(P, w2, "f64")
+    a.step(0)
+    assert a.stats()["steps"] == 0
+    a.step(15)
+    b.step(15)
+    n2, j2 = a.moments(2)
+    assert np.all(n2 == 0.0) and np.all(j2 == 0.0)
+    o = oracle_for(oracle_mod, w3)
+    o.step(15)
+    compare_fp64(a, o, w3)
+    for s in range(2):
+        np.testing.assert_allclose(a.moments(s)[0], b.moments(s)[0], rtol=0, atol=1e-15)
+    # one node
+    w1 = WL.random_state(1, 1, 1, 2, seed=42, dn=0.05, du=0.02)
+    a = gpu_for(P, w1, "f64")
+    o = oracle_for(oracle_mod, w1)
+    a.step(25)
+    o.step(25)
+    compare_fp64(a, o, w1)
+    # stiffest drag of the benchmark range
+    ws = WL.binary_sine(16, 4, 4, amp=0.01, tau_visc=1.0, sc=1000.0)
+    a = gpu_for(P, ws, "f64")
+    o = oracle_for(oracle_mod, ws)
+    a.step(60)
+    o.step(60)
+    compare_fp64(a, o, ws)
