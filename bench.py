@@ -31,7 +31,7 @@ Q = 19
 def kernel_source_hash() -> str:
     """Hash of the sources of the fused step kernel (its counters are void once they change)."""
     h = hashlib.sha256()
-    for name in ("lbmix_step.hip", "lbmix_step.h", "lbmix_device.h"):
+    for name in ("lbmix_step_kernel.h", "lbmix_step.hip", "lbmix_step.h", "lbmix_device.h"):
         with open(os.path.join(ROOT, "paper_1507_04891_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

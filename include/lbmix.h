@@ -62,6 +62,9 @@ enum lbmix_status {
 
 enum lbmix_geometry { LBMIX_PERIODIC = 0, LBMIX_SLIT_Z = 1, LBMIX_CHANNELS = 2 };
 
+/* Forcing schemes (lbmix_set_forcing). */
+enum lbmix_forcing { LBMIX_FORCING_PAPER = 0, LBMIX_FORCING_GUO = 1 };
+
 /* Population storage.  F64 and F32 store f.  The SHIFTED forms store the deviation
  * f_p - w_p rho0 (rho0 = the species' rest density given to lbmix_add_species), in FP32,
  * or in BF16 / FP16 times a power-of-two scale per species and direction; the collision
@@ -137,8 +140,10 @@ int lbmix_set_tau_visc(lbmix_ctx *ctx, double tau_visc);
  * after the first step. */
 int lbmix_set_tau_drag(lbmix_ctx *ctx, double tau_drag);
 
-/* Schmidt number Sc = nu / D: tau_drag = 1/2 + (tau_visc - 1/2) / Sc, re-evaluated when
- * tau_visc changes.  Errors: EINVAL unless Sc > 0; ESTATE after the first step. */
+/* Schmidt number Sc = nu / D: tau_drag = 1/2 + (tau_visc - 1/2) / Sc (with the Guo-type
+ * forcing variant, where D = v_T^2 tau_drag: tau_drag = (tau_visc - 1/2) / Sc), evaluated at
+ * the first step.  Errors: EINVAL unless Sc > 0 (lbmix_step: for the Guo-type variant unless
+ * tau_visc > 1/2 + Sc / 2, which keeps tau_drag > 1/2); ESTATE after the first step. */
 int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
 
 /* enable != 0: replay each step as a captured HIP graph (the fused step, the direct Poisson
@@ -170,6 +175,22 @@ int lbmix_autotune(lbmix_ctx *ctx, int reps);
  * (lbmix_step: for a species count that changed since, or per-channel drags); ESTATE after
  * the first step. */
 int lbmix_set_drag_pairs(lbmix_ctx *ctx, const double *tau_pairs);
+
+/* Forcing scheme of the collision.
+ *   LBMIX_FORCING_PAPER (default): the equilibrium phi_perp at the species velocity u^a and
+ *     the forcing term g_p of the Appendix (eq. ourforc), with the drag of Sec. II taken on
+ *     the mid-step velocities u^a + a^a / 2 (a^a the field acceleration).
+ *   LBMIX_FORCING_GUO: a second-order scheme of the Guo type.  Every species moves with
+ *     v^a = u^a + F^a / 2 in the equilibrium and in the drag, so the drag is implicit,
+ *     F^a = a^a - omega_drag sum_b (n^b / n)(v^a - v^b); it is solved in closed form per
+ *     node.  The forcing term is (1 - omega_visc / 2) g_p(F^a, v), v the barycentric mean of
+ *     the v^a.  The velocity difference then relaxes by (1 - omega/2) / (1 + omega/2) per
+ *     step, which gives D = v_T^2 tau_drag (the continuum expression, instead of
+ *     v_T^2 (tau_drag - 1/2)) and an electric mobility tau_drag; the viscosity is unchanged.
+ *     D >= v_T^2 / 2 here, so high Schmidt numbers need large viscosities.
+ * Errors: EINVAL for an unknown scheme (lbmix_step: for the Guo variant with a pair drag
+ * matrix of three or more species); ESTATE after the first step. */
+int lbmix_set_forcing(lbmix_ctx *ctx, int scheme);
 
 /* Electrostatics (Sec. II, eq. Poisson and its surface-charge condition): Bjerrum length
  * l_B >= 0 (0: no Poisson solve), surface charges of the walls z = 0 and z = nz-1 in units

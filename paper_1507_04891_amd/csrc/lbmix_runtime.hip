@@ -63,6 +63,7 @@ struct lbmix_ctx {
     bool drag_from_sc = true;
     int pair_ns = 0;                  // > 0: drag relaxation time per pair of species
     double tau_pair[MAXS][MAXS] = {};
+    int forcing = 0;                  // 0: forcing of the Appendix; 1: the Guo-type variant
     double lB = 0.0, sig_lo = 0.0, sig_hi = 0.0, E[3] = {0.0, 0.0, 0.0};
     double sor_tol = 1e-8, sor_omega = -1.0;
     int poisson_method = 0;           // 0 red-black SOR, 1 multigrid, 2 direct (spectral)
@@ -143,7 +144,9 @@ struct lbmix_ctx {
     bool field() const { return charged() || E[0] != 0.0 || E[1] != 0.0 || E[2] != 0.0; }
     double omega_drag() const {
         if (pair_ns == 2) return 1.0 / tau_pair[0][1];   // a binary has a single pair
-        return drag_from_sc ? 1.0 / (0.5 + (tau_v - 0.5) / sc) : 1.0 / tau_d;
+        if (!drag_from_sc) return 1.0 / tau_d;
+        // D = nu / Sc with D = v_T^2 (tau_drag - 1/2), or v_T^2 tau_drag for the Guo-type variant
+        return forcing == 1 ? sc / (tau_v - 0.5) : 1.0 / (0.5 + (tau_v - 0.5) / sc);
     }
     double sor_w() const {
         if (sor_omega > 0.0) return sor_omega;
@@ -207,6 +210,7 @@ struct lbmix_ctx {
         a.omega_v = 1.0 / tau_v;
         a.omega_d = omega_drag();
         a.pair_drag = pair_ns >= 3 ? 1 : 0;
+        a.forcing = forcing;
         for (int s = 0; s < MAXS; ++s)
             for (int b = 0; b < MAXS; ++b)
                 a.omega_pair[s][b] = (pair_ns >= 3 && s < ns && b < ns && s != b) ? 1.0 / tau_pair[s][b] : 0.0;
@@ -1009,6 +1013,10 @@ bool redblack_extents(const lbmix_ctx *c) {
 int validate_start(lbmix_ctx *c) {
     if (c->pair_ns && c->pair_ns != c->ns)
         return c->fail(LBMIX_EINVAL, "the pair drag matrix was set for %d species, the lattice has %d", c->pair_ns, c->ns);
+    if (c->forcing == 1 && c->pair_ns >= 3)
+        return c->fail(LBMIX_EINVAL, "the Guo-type forcing variant has one drag frequency; it excludes a pair drag matrix");
+    if (c->forcing == 1 && c->pair_ns == 0 && c->drag_from_sc && !(c->omega_drag() < 2.0))
+        return c->fail(LBMIX_EINVAL, "with the Guo-type variant, Sc = %g needs tau_visc > 1/2 + Sc / 2", c->sc);
     for (int ch = 0; c->pair_ns && ch < c->nch; ++ch)
         if (c->ch_tau_d[ch] > 0.0)
             return c->fail(LBMIX_EINVAL, "channel %d has its own drag; a pair drag matrix applies to all channels", ch);
@@ -1058,7 +1066,7 @@ struct Header {
     uint64_t round_seed;
     double lB, sig_lo, sig_hi, E[3], sor_tol, sor_omega;
     int64_t steps;
-    int32_t pair_ns, pad;
+    int32_t pair_ns, forcing;
     double tau_pair[MAXS * MAXS];
 };
 
@@ -1227,6 +1235,15 @@ int lbmix_set_drag_pairs(lbmix_ctx *c, const double *tau) {
         for (int b = 0; b < MAXS; ++b) c->tau_pair[a][b] = (a < ns && b < ns) ? tau[a * ns + b] : 0.0;
     c->pair_ns = ns;
     c->tables_dirty = true;
+    return LBMIX_OK;
+}
+
+int lbmix_set_forcing(lbmix_ctx *c, int scheme) {
+    if (!c) return LBMIX_EINVAL;
+    if (c->started) return c->fail(LBMIX_ESTATE, "parameters are fixed once stepping has started");
+    if (scheme != LBMIX_FORCING_PAPER && scheme != LBMIX_FORCING_GUO)
+        return c->fail(LBMIX_EINVAL, "unknown forcing scheme %d", scheme);
+    c->forcing = scheme;
     return LBMIX_OK;
 }
 
@@ -1728,10 +1745,11 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 3;
+    h.version = 4;
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
     h.nch = c->nch;
     h.pair_ns = c->pair_ns;
+    h.forcing = c->forcing;
     for (int a = 0; a < MAXS; ++a)
         for (int b = 0; b < MAXS; ++b) h.tau_pair[a * MAXS + b] = c->tau_pair[a][b];
     for (int s = 0; s < MAXS; ++s) {
@@ -1778,7 +1796,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 3;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 4;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
          h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
     constexpr int kPerChan = 4 + MAXS;
@@ -1811,6 +1829,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     c->lB = h.lB; c->sig_lo = h.sig_lo; c->sig_hi = h.sig_hi;
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
     c->pair_ns = h.pair_ns;
+    c->forcing = h.forcing;
     for (int a = 0; a < MAXS; ++a)
         for (int b = 0; b < MAXS; ++b) c->tau_pair[a][b] = h.tau_pair[a * MAXS + b];
     for (int ch = 0; ch < c->nch; ++ch) {

@@ -42,6 +42,7 @@ struct StepArgs {
     double omega_v, omega_d;
     int pair_drag;                   // 1: drag frequency per pair (three or more species)
     double omega_pair[MAXS][MAXS];   // symmetric; the diagonal is not used
+    int forcing;                     // 0: forcing of the Appendix; 1: the Guo-type variant
     double valence[MAXS];
     double E[3];                     // applied field, acceleration per unit valence
     const double *psi;               // potential on fluid nodes (charged runs)

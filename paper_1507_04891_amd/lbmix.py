@@ -21,12 +21,13 @@ STORAGE = {"f64": F64, "f32": F32, "f32s": F32_SHIFTED, "bf16s": BF16_SHIFTED, "
 GEOMETRY = {"periodic": PERIODIC, "slit": SLIT_Z, "channels": CHANNELS}
 POISSON = {"sor": 0, "multigrid": 1, "direct": 2}
 WARM_START = {"previous": 0, "extrapolated": 1, "learned": 2}
+FORCING = {"paper": 0, "guo": 1}
 ELEMENT_BYTES = {F64: 8, F32: 4, F32_SHIFTED: 4, BF16_SHIFTED: 2, F16_SHIFTED: 2}
 Q = 19
 MAX_SPECIES = 4
 EXPORTS = (
     "lbmix_version", "lbmix_create", "lbmix_create_channels", "lbmix_set_channel", "lbmix_add_species",
-    "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_drag_pairs",
+    "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_drag_pairs", "lbmix_set_forcing",
     "lbmix_set_electrostatics",
     "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
     "lbmix_set_storage_range", "lbmix_set_state", "lbmix_autotune", "lbmix_set_step_graph", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
@@ -82,6 +83,7 @@ def load_library():
         "lbmix_set_tau_drag": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_schmidt": ([vp, ctypes.c_double], ctypes.c_int),
         "lbmix_set_drag_pairs": ([vp, dp], ctypes.c_int),
+        "lbmix_set_forcing": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_set_electrostatics": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp], ctypes.c_int),
         "lbmix_set_poisson": ([vp, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_double], ctypes.c_int),
         "lbmix_set_poisson_method": ([vp, ctypes.c_int], ctypes.c_int),
@@ -217,6 +219,13 @@ class Lattice:
             return
         t = _f64(tau, (self.nspecies, self.nspecies))
         self._check(self._L.lbmix_set_drag_pairs(self._h, _dp(t)))
+
+    def set_forcing(self, scheme):
+        """scheme: "paper" (the forcing of the Appendix, drag on mid-step velocities) or "guo"
+        (the second-order Guo-type variant)."""
+        if scheme not in FORCING:
+            raise ValueError(f"forcing must be one of {sorted(FORCING)}")
+        self._check(self._L.lbmix_set_forcing(self._h, FORCING[scheme]))
 
     def set_electrostatics(self, bjerrum, sigma_lo=0.0, sigma_hi=0.0, E=(0.0, 0.0, 0.0)):
         e = (ctypes.c_double * 3)(*[float(v) for v in E])
@@ -421,10 +430,11 @@ class Net:
         self._check(self._L.lbmix_net_adam(self._h, ctypes.c_float(lr), ctypes.c_void_p(s)))
 
 
-def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None):
+def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None,
+                  forcing="paper"):
     """Build a Lattice from a workloads.Workload or workloads.ChannelStack description
     (parameters and initial fields).  stochastic: rounding of the 16-bit forms (default:
-    stochastic for them)."""
+    stochastic for them); forcing: "paper" or "guo"."""
     stack = w.geometry == "channels"
     lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream,
                   widths=w.widths if stack else None)
@@ -444,6 +454,8 @@ def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, 
             lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
     if drag_pairs is not None:
         lat.set_drag_pairs(drag_pairs)
+    if forcing != "paper":
+        lat.set_forcing(forcing)
     if poisson:
         lat.set_poisson(**poisson)
     for s in range(w.nspecies):

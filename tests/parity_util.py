@@ -18,9 +18,9 @@ W = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
 
 
 def oracle_for(oracle_mod, w, poisson="direct", lagged=True, sor_tol=1e-8, sor_max=100000,
-               sor_check=10, sor_omega=None, drag_pairs=None):
+               sor_check=10, sor_omega=None, drag_pairs=None, forcing="paper"):
     """The oracle for a workload; drag_pairs: [ns][ns] drag relaxation times per pair (the
-    library's convention), passed on as frequencies 1 / tau."""
+    library's convention), passed on as frequencies 1 / tau; forcing: "paper" or "guo"."""
     pair = None
     if drag_pairs is not None:
         t = np.asarray(drag_pairs, dtype=np.float64)
@@ -28,7 +28,8 @@ def oracle_for(oracle_mod, w, poisson="direct", lagged=True, sor_tol=1e-8, sor_m
     o = oracle_mod.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag,
                           geometry=w.geometry, valence=w.valence, bjerrum=w.bjerrum,
                           sigma=w.sigma, E=w.E, poisson=poisson, lagged=lagged, sor_omega=sor_omega,
-                          sor_tol=sor_tol, sor_max=sor_max, sor_check=sor_check, drag_pair=pair)
+                          sor_tol=sor_tol, sor_max=sor_max, sor_check=sor_check, drag_pair=pair,
+                          forcing=forcing)
     for s in range(w.nspecies):
         o.set_state(s, w.n[s], w.u[s])
     return o

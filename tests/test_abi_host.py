@@ -109,3 +109,15 @@ def test_network_validation_without_device(L):
     assert L.lbmix_set_step_graph(h, 1) == 0
     L.lbmix_destroy(h)
     L.lbmix_net_destroy(None)
+
+
+def test_forcing_validation_without_device(L):
+    h = ctypes.c_void_p()
+    assert L.lbmix_set_forcing(None, 1) == -1
+    assert L.lbmix_create(ctypes.byref(h), 8, 8, 8, 0, 0, None) == 0
+    assert L.lbmix_set_forcing(h, 2) == -1
+    assert b"forcing" in L.lbmix_last_error(h)
+    assert L.lbmix_set_forcing(h, -1) == -1
+    assert L.lbmix_set_forcing(h, 1) == 0
+    assert L.lbmix_set_forcing(h, 0) == 0
+    L.lbmix_destroy(h)
