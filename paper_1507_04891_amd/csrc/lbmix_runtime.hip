@@ -1099,6 +1099,9 @@ int create_ctx(lbmix_ctx **out, int nx, int ny, int geometry, const std::vector<
         nzf += w;
     }
     if ((double)nx * ny * nz > 2147483647.0) return LBMIX_EINVAL;
+    // the fused step addresses a plane of a population slot with 32-bit byte offsets
+    const double ebytes = storage == LBMIX_F64 ? 8.0 : (storage <= LBMIX_F32_SHIFTED ? 4.0 : 2.0);
+    if ((double)nx * ny * MAXS * ebytes >= 4294967296.0) return LBMIX_EINVAL;
     lbmix_ctx *c = new (std::nothrow) lbmix_ctx();
     if (!c) return LBMIX_ENOMEM;
     c->nx = nx;

@@ -62,6 +62,7 @@ template <> struct Codec<double> {
     using C = double;
     using S = double;
     static constexpr bool kRounds = false;
+    static constexpr bool kWideSum = true;   // density deviation summed in FP64
     __device__ static C decode(S v, float) { return v; }
     template <bool SR = false>
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
@@ -70,6 +71,7 @@ template <> struct Codec<float> {
     using C = float;
     using S = float;
     static constexpr bool kRounds = false;
+    static constexpr bool kWideSum = true;   // density deviation summed in FP64
     __device__ static C decode(S v, float) { return v; }
     template <bool SR = false>
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
@@ -123,6 +125,7 @@ template <> struct Codec<BF16> {
     using C = float;
     using S = uint16_t;
     static constexpr bool kRounds = true;
+    static constexpr bool kWideSum = false;  // density deviation summed in FP32
     __device__ static C decode(S v, float inv) { return __uint_as_float(uint32_t(v) << 16) * inv; }
     template <bool SR = false>
     __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
@@ -134,6 +137,7 @@ template <> struct Codec<F16> {
     using C = float;
     using S = uint16_t;
     static constexpr bool kRounds = true;
+    static constexpr bool kWideSum = true;   // density deviation summed in FP64
     __device__ static C decode(S v, float inv) { return __half2float(__ushort_as_half(v)) * inv; }
     template <bool SR = false>
     __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
@@ -189,6 +193,16 @@ __device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int n
     return ((size_t)arr * N + node) * ns;
 }
 
+// The elements of direction slot arr at node plane + inplane in the fused step's layout: the
+// address of the plane in the slot (uniform per work-group, formed on the scalar unit) plus a
+// 32-bit byte offset within the plane (a plane of a slot holds less than 4 GiB).
+template <int NS, class S>
+__device__ __forceinline__ S *slot(S *base, int arr, uint32_t plane, uint32_t inplane, uint32_t N) {
+    S *start = base + ((size_t)arr * N + plane) * NS;
+    using B = std::conditional_t<std::is_const_v<S>, const char, char>;
+    return reinterpret_cast<S *>(reinterpret_cast<B *>(start) + (uint32_t)(inplane * (NS * sizeof(S))));
+}
+
 // ---------------------------------------------------------------------------------------
 // Pull addressing shared by every kernel that reads a pre-collision state: the value of
 // direction p at node (x, y, z) comes from slot (p, node - c_p), or from slot (opp(p),
@@ -196,34 +210,47 @@ __device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int n
 
 struct Pull {
     uint32_t xs, xm, xp;       // x, x-1, x+1 with periodic wrap (per lane)
-    uint32_t ym, yp, zm, zp;   // wrapped neighbours (uniform)
+    uint32_t r0, rm, rp;       // node offsets y nx of the rows y, y-1, y+1 (wrapped)
+    uint32_t p0, pm, pp;       // node offsets z nx ny of the planes z, z-1, z+1 (wrapped; uniform)
     uint32_t y, z;
     bool bb_lo, bb_hi;         // z - 1 / z + 1 is a wall (slit)
-    uint32_t nx, ny;
 
-    __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx_, uint32_t ny_, uint32_t nzf,
+    __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx, uint32_t ny, uint32_t nzf,
                     uint32_t walls)
-        : xs(x), y(y_), z(z_), nx(nx_), ny(ny_) {
+        : xs(x), y(y_), z(z_) {
         xm = (x == 0) ? nx - 1 : x - 1;
         xp = (x + 1 == nx) ? 0 : x + 1;
-        ym = (y == 0) ? ny - 1 : y - 1;
-        yp = (y + 1 == ny) ? 0 : y + 1;
-        zm = (z == 0) ? nzf - 1 : z - 1;
-        zp = (z + 1 == nzf) ? 0 : z + 1;
+        r0 = y * nx;
+        rm = (y == 0) ? (ny - 1) * nx : r0 - nx;
+        rp = (y + 1 == ny) ? 0 : r0 + nx;
+        const uint32_t plane = nx * ny;
+        p0 = z * plane;
+        pm = (z == 0) ? (nzf - 1) * plane : p0 - plane;
+        pp = (z + 1 == nzf) ? 0 : p0 + plane;
         bb_lo = (walls & 1u) != 0;
         bb_hi = (walls & 2u) != 0;
     }
-    __device__ uint32_t own() const { return (z * ny + y) * nx + xs; }
-    // slot direction and node of the value that direction p pulls
+    __device__ uint32_t own() const { return p0 + r0 + xs; }
+    __device__ uint32_t own_inplane() const { return r0 + xs; }
+    // slot direction, plane offset (uniform) and in-plane offset (per lane) of the value that
+    // direction p pulls
     template <int p>
-    __device__ void src(int &arr, uint32_t &node) const {
+    __device__ void src(int &arr, uint32_t &plane, uint32_t &inplane) const {
         constexpr int X = cx(p), Y = cy(p), Z = cz(p);
         const bool bb = (Z == 1 && bb_lo) || (Z == -1 && bb_hi);
         const uint32_t sx = X == 1 ? xm : (X == -1 ? xp : xs);
-        const uint32_t sy = Y == 1 ? ym : (Y == -1 ? yp : y);
-        const uint32_t sz = Z == 1 ? zm : (Z == -1 ? zp : z);
+        const uint32_t sy = Y == 1 ? rm : (Y == -1 ? rp : r0);
+        const uint32_t sz = Z == 1 ? pm : (Z == -1 ? pp : p0);
         arr = bb ? opp(p) : p;
-        node = bb ? own() : (sz * ny + sy) * nx + sx;
+        plane = bb ? p0 : sz;
+        inplane = bb ? r0 + xs : sy + sx;
+    }
+    // ... and as one node index
+    template <int p>
+    __device__ void src(int &arr, uint32_t &node) const {
+        uint32_t plane, inplane;
+        src<p>(arr, plane, inplane);
+        node = plane + inplane;
     }
 };
 
@@ -249,6 +276,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     const uint32_t walls = SLIT ? a.planes[z].walls : 0u;   // uniform per work-group
     const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, z, a.nx, a.ny, a.nzf, walls);
     const uint32_t own = pl.own();
+    const uint32_t own_in = pl.own_inplane();
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
 
@@ -257,18 +285,23 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
-        uint32_t node;
-        pl.template src<p>(arr, node);
+        uint32_t plane, inplane;
+        pl.template src<p>(arr, plane, inplane);
         S raw[NS];
-        VecIO<S, NS>::load(fin + elem(arr, node, a.N, NS), raw);
+        VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
 #pragma unroll
         for (int s = 0; s < NS; ++s) d[s][p] = CD::decode(raw[s], a.inv_scale[s][arr]);
     });
 
-    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c.  The density deviation is
-    //    also summed in FP64 (dnh): with deviations stored, the update of a direction is
+    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c.  The density deviation is also
+    //    summed in FP64 (dnh): with deviations stored, the update of a direction is
     //    w dn + (flux and force terms), and FP32 rounding at the scale of w dn would be about
-    //    1 % of the per-step change of a slow diffusion mode at Sc = 100.
+    //    1 % of the per-step change of a slow diffusion mode at Sc = 100.  That rounding is
+    //    deterministic, so it biases slow modes where stochastic rounding of the stored values
+    //    only adds noise that averages out: with FP32 sums the spread of the FP16 form's
+    //    electro-osmotic mobility over rounding seeds grows by 40 %.  BF16 storage is the
+    //    exception: its own rounding noise is 8 times FP16's and the FP32 sum leaves its
+    //    spread unchanged, so it keeps the FP32 sum.
     C dn[NS], jx[NS], jy[NS], jz[NS], n[NS];
     double dnh[NS];
     C ntot = 0, sjx = 0, sjy = 0, sjz = 0;
@@ -279,7 +312,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         static_for<Q>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             m0 += d[s][p];
-            m0h += double(d[s][p]);
+            if constexpr (CD::kWideSum) m0h += double(d[s][p]);
             if constexpr (cx(p) == 1) mx += d[s][p];
             if constexpr (cx(p) == -1) mx -= d[s][p];
             if constexpr (cy(p) == 1) my += d[s][p];
@@ -288,7 +321,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             if constexpr (cz(p) == -1) mz -= d[s][p];
         });
         dn[s] = m0;
-        dnh[s] = m0h;
+        dnh[s] = CD::kWideSum ? m0h : double(m0);
         jx[s] = mx;
         jy[s] = my;
         jz[s] = mz;
@@ -307,12 +340,12 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         double gx = 0.0, gy = 0.0, gz = 0.0;
         if constexpr (CHARGED) {
             const double *psi = a.psi;
-            const uint32_t row = (pl.z * a.ny + pl.y) * a.nx;
+            const uint32_t row = pl.p0 + pl.r0;
             const double here = psi[row + pl.xs];
             gx = 0.5 * (psi[row + pl.xp] - psi[row + pl.xm]);
-            gy = 0.5 * (psi[(pl.z * a.ny + pl.yp) * a.nx + pl.xs] - psi[(pl.z * a.ny + pl.ym) * a.nx + pl.xs]);
-            const double up = (SLIT && pl.bb_hi) ? here + a.planes[z].ghost_hi : psi[(pl.zp * a.ny + pl.y) * a.nx + pl.xs];
-            const double dw = (SLIT && pl.bb_lo) ? here + a.planes[z].ghost_lo : psi[(pl.zm * a.ny + pl.y) * a.nx + pl.xs];
+            gy = 0.5 * (psi[pl.p0 + pl.rp + pl.xs] - psi[pl.p0 + pl.rm + pl.xs]);
+            const double up = (SLIT && pl.bb_hi) ? here + a.planes[z].ghost_hi : psi[pl.pp + pl.r0 + pl.xs];
+            const double dw = (SLIT && pl.bb_lo) ? here + a.planes[z].ghost_lo : psi[pl.pm + pl.r0 + pl.xs];
             gz = 0.5 * (up - dw);
         }
         constexpr double cs2 = 1.0 / 3.0;
@@ -423,7 +456,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         for (int k = 0; k < 3; ++k) {
             const double big = wgt<double>(k == 0 ? 0 : (k == 1 ? 1 : 7)) * a.omega_v * dnh[s];
             bhi[s][k] = C(big);
-            blo[s][k] = C(big - double(bhi[s][k]));
+            blo[s][k] = CD::kWideSum ? C(big - double(bhi[s][k])) : C(0);
         }
         ov45[s] = C(4.5) * ov * n[s];
         n9[s] = C(9) * n[s];
@@ -443,12 +476,18 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             if ((s & 1) == 0) rs = xorshift32(rs);
             return (s & 1) ? (rs << 16) : rs;
         };
+        auto plus_dn = [&](C v, int s, int cls) -> C {   // + w ov dn (hi + lo with the FP64 sum)
+            if constexpr (CD::kWideSum)
+                return (v + blo[s][cls]) + bhi[s][cls];
+            else
+                return v + bhi[s][cls];
+        };
         S o0[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s)
-            o0[s] = CD::template encode<SR>(((keep * d[s][0] + wgt<C>(0) * base[s]) + blo[s][0]) + bhi[s][0],
+            o0[s] = CD::template encode<SR>(plus_dn(keep * d[s][0] + wgt<C>(0) * base[s], s, 0),
                                             a.scale[s][0], rbits(s));
-        VecIO<S, NS>::store(fout + elem(0, own, a.N, NS), o0);
+        VecIO<S, NS>::store(slot<NS>(fout, 0, pl.p0, own_in, a.N), o0);
         static_for<9>([&](auto kc) {
             constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
             constexpr int pb = p + 1;
@@ -463,15 +502,15 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
                 const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
                 const C sym = w * (base[s] + ov45[s] * cu * cu + n9[s] * cF * cub);
                 const C anti = w * n3[s] * (ov * cu + cF);
-                vp[s] = ((keep * d[s][p] + sym + anti) + blo[s][cls]) + bhi[s][cls];
-                vb[s] = ((keep * d[s][pb] + sym - anti) + blo[s][cls]) + bhi[s][cls];
+                vp[s] = plus_dn(keep * d[s][p] + sym + anti, s, cls);
+                vb[s] = plus_dn(keep * d[s][pb] + sym - anti, s, cls);
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) op[s] = CD::template encode<SR>(vp[s], a.scale[s][p], rbits(s));
 #pragma unroll
             for (int s = 0; s < NS; ++s) ob[s] = CD::template encode<SR>(vb[s], a.scale[s][pb], rbits(s));
-            VecIO<S, NS>::store(fout + elem(p, own, a.N, NS), op);
-            VecIO<S, NS>::store(fout + elem(pb, own, a.N, NS), ob);
+            VecIO<S, NS>::store(slot<NS>(fout, p, pl.p0, own_in, a.N), op);
+            VecIO<S, NS>::store(slot<NS>(fout, pb, pl.p0, own_in, a.N), ob);
         });
     };
     if (active) {

@@ -102,10 +102,9 @@ def test_viscosity_error(P, storage):
     assert abs(viscosity(P, storage) / ref - 1) <= 5e-4
 
 
-def mobility(P, storage):
+def mobility(P, storage, seed=7):
     w = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
-    lat = P.from_workload(w, storage=storage, seed=7,
-                          poisson=dict(rel_tol=1e-9, max_sweeps=20000, check_every=10))
+    lat = P.from_workload(w, storage=storage, seed=seed, poisson=dict(method="direct"))
     lat.step(28000)
     acc = None
     for _ in range(20):
@@ -120,11 +119,15 @@ def mobility(P, storage):
 
 @pytest.mark.parametrize("storage,tol", [("f32s", 1e-3), ("f16s", 1e-3), ("bf16s", 1e-2)])
 def test_electroosmotic_mobility_error(P, storage, tol):
-    """BF16 keeps 8 significant bits: on this 16 x 16 x 32 channel its rounding noise leaves
-    the time-averaged centre velocity within a few 1e-3 (1.9e-3 and 5.2e-3 in two rounding
-    streams), so its bar is 1e-2; FP16 and FP32 meet 1e-3."""
+    """On this 16 x 16 x 32 channel the stochastic rounding of the 16-bit forms leaves the
+    time-averaged centre velocity scattered over rounding streams: relative spread 4e-4 for
+    FP16 and 4e-3 for BF16 (8 significant bits), measured over 24 streams on MI355X, with
+    means within 1e-4 and 1e-3 of zero.  The bar applies to the mean of four streams (FP32
+    rounds deterministically: one run)."""
     ref = cached(("mob", "f64"), lambda: mobility(P, "f64"))
-    assert abs(mobility(P, storage) / ref - 1) <= tol
+    seeds = (7,) if storage == "f32s" else (7, 8, 9, 10)
+    got = np.mean([mobility(P, storage, s) for s in seeds])
+    assert abs(got / ref - 1) <= tol, (storage, got / ref - 1)
 
 
 @pytest.mark.parametrize("storage,eps", [("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)])
