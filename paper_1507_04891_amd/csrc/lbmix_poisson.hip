@@ -482,22 +482,41 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 }
 
 // The same eliminations with the columns staged in LDS: one work-group of 256 threads per
-// MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
-// and pivots with coalesced loads, issued eight at a time; MODES threads run the recurrences
-// from LDS; all threads write the result back.
+// MODES modes of one segment (MODES * planes <= 8192; fewer modes per work-group spread the
+// serial recurrences over more compute units).  All threads stage the right-hand side
+// and pivots with coalesced loads, issued sixteen at a time; MODES threads run the recurrences
+// from LDS; all threads write the result back.  The work-group holding mode 0 removes its
+// segment mean before and after the elimination with all threads.
 constexpr uint32_t TRI_CELLS = 8192;
+
+// Mean over z < L of column 0 of an LDS array [plane][MODES] (L <= 256), by all 256 threads
+// in a fixed order; every thread receives it.
+template <uint32_t MODES>
+__device__ double column0_mean(const double *s, uint32_t L, double *red) {
+    const uint32_t t = threadIdx.x;
+    double v = t < L ? s[t * MODES] : 0.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    const double m = ((red[0] + red[1]) + (red[2] + red[3])) / double(L);
+    __syncthreads();
+    return m;
+}
 
 template <uint32_t MODES>
 __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
                                                    const uint32_t *seg) {
-    __shared__ double sb[TRI_CELLS], sp[TRI_CELLS];   // [plane][MODES]
+    constexpr uint32_t CELLS = MODES * TRI_LDS_MAX < TRI_CELLS ? MODES * TRI_LDS_MAX : TRI_CELLS;
+    __shared__ double sb[CELLS], sp[CELLS];   // [plane][MODES]
+    __shared__ double red[4];
     const uint32_t m0 = blockIdx.x * MODES;
     const uint32_t z0 = seg[blockIdx.y], L = seg[blockIdx.y + 1] - z0;
     const uint32_t t = threadIdx.x, cells = L * MODES;
-    for (uint32_t k0 = 0; k0 < cells; k0 += 256 * 8) {
-        double vb[8], vp[8];
+    for (uint32_t k0 = 0; k0 < cells; k0 += 256 * 16) {
+        double vb[16], vp[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
             const uint32_t k = k0 + u * 256 + t, z = k / MODES, m = k % MODES;
             const bool in = k < cells && m0 + m < nmodes;
             const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
@@ -505,7 +524,7 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
             vp[u] = in ? piv[i] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 16; ++u) {
             const uint32_t k = k0 + u * 256 + t;
             if (k < cells) {
                 sb[k] = vb[u];
@@ -514,16 +533,16 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
         }
     }
     __syncthreads();
+    if (m0 == 0) {   // mode 0: project onto zero segment mean
+        const double bm = column0_mean<MODES>(sb, L, red);
+        if (t < L) sb[t * MODES] -= bm;
+        __syncthreads();
+    }
     if (t < MODES && m0 + t < nmodes) {
-        double bm = 0.0;   // mode 0: project onto zero segment mean
-        if (m0 + t == 0) {
-            for (uint32_t z = 0; z < L; ++z) bm += sb[z * MODES];
-            bm /= double(L);
-        }
         double r = 0.0;
 #pragma unroll 8
         for (uint32_t z = 0; z < L; ++z) {
-            r = (sb[z * MODES + t] - bm - r) * sp[z * MODES + t];
+            r = (sb[z * MODES + t] - r) * sp[z * MODES + t];
             sb[z * MODES + t] = r;
         }
         double x = 0.0;
@@ -532,56 +551,55 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
             x = sb[z * MODES + t] - sp[z * MODES + t] * x;
             sb[z * MODES + t] = x;
         }
-        if (m0 + t == 0) {
-            double sum = 0.0;
-            for (uint32_t z = 0; z < L; ++z) sum += sb[z * MODES];
-            const double mean = sum / double(L);
-            for (uint32_t z = 0; z < L; ++z) sb[z * MODES] -= mean;
-        }
     }
     __syncthreads();
+    if (m0 == 0) {   // and gauge it to zero segment mean
+        const double mean = column0_mean<MODES>(sb, L, red);
+        if (t < L) sb[t * MODES] -= mean;
+        __syncthreads();
+    }
     for (uint32_t k = t; k < cells; k += 256) {
         const uint32_t z = k / MODES, m = k % MODES;
         if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[k];
     }
 }
 
-// C[r][c] = sum_k A(r, k) B(k, c) between LDS arrays (r < R, c < CN, k < K), with
-// A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc], C[r ldc + c]; 4 x 4 outputs per thread
-// (edge indices clamped, their outputs not stored).
-__device__ void lds_product(const double *A, int ar, int ak, const double *B, int bk, int bc, double *C, int ldc,
-                            int R, int CN, int K) {
-    const int nbr = (R + 3) / 4, nbc = (CN + 3) / 4;
-    for (int blk = threadIdx.x; blk < nbr * nbc; blk += blockDim.x) {
-        const int r0 = (blk / nbc) * 4, c0 = (blk % nbc) * 4;
-        int ra[4], cb[4];
+// C(r, c) = sum_k A(r, k) B(k, c) for r, c, k < N (N a multiple of 32) between LDS arrays,
+// with A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c], on the
+// FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
+// operand fragment feeds two products.  v_mfma_f64_16x16x4f64: lane l holds A(i, k) and
+// B(k, j) with i, j = l mod 16 and k = l / 16 of its 16 x 4 and 4 x 16 fragments, and the
+// result rows l / 16 + 4 r, r < 4, of column l mod 16.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <int N>
+__device__ void mfma_product(const double *A, int ar, int ak, const double *B, int bk, int bc, double *C, int ldc) {
+    constexpr int NB = N / 32;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int nwaves = blockDim.x >> 6;
+    for (int blk = threadIdx.x >> 6; blk < NB * NB; blk += nwaves) {
+        const int r0 = (blk / NB) * 32, c0 = (blk % NB) * 32;
+        f64x4 acc[2][2];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            ra[i] = min(r0 + i, R - 1) * ar;
-            cb[i] = min(c0 + i, CN - 1) * bc;
-        }
-        double acc[4][4];
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+            for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int k = 0; k < K; ++k) {
-            double av[4], bv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) av[i] = A[ra[i] + k * ak];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = B[k * bk + cb[j]];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(av[i], bv[j], acc[i][j]);
+        for (int k = 0; k < N; k += 4) {
+            const int kk = k + lk;
+            const double a0 = A[(r0 + li) * ar + kk * ak], a1 = A[(r0 + 16 + li) * ar + kk * ak];
+            const double b0 = B[kk * bk + (c0 + li) * bc], b1 = B[kk * bk + (c0 + 16 + li) * bc];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (r0 + i < R && c0 + j < CN) C[(r0 + i) * ldc + c0 + j] = acc[i][j];
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) C[(r0 + 16 * i + lk + 4 * r) * ldc + c0 + 16 * j + li] = acc[i][j][r];
     }
 }
 
@@ -595,26 +613,41 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
     const int nx = a.nx, ny = a.ny;
     const uint32_t z = blockIdx.x;
     const size_t base = (size_t)z * nx * ny;
-    for (int k = threadIdx.x; k < nx * nx; k += blockDim.x) Tx[(k / nx) * LD + k % nx] = a.tx[k];
-    for (int k = threadIdx.x; k < ny * ny; k += blockDim.x) Ty[(k / ny) * LD + k % ny] = a.ty[k];
-    if (FWD && a.q) {
-        const double lump = a.planes ? a.planes[z].lump : 0.0;
-        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x)
-            P[(k / nx) * LD + k % nx] = -a.K * (a.q[base + k] + lump);
-    } else {
-        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) P[(k / nx) * LD + k % nx] = a.in[base + k];
+    // bases and plane, zero-padded to PM x PM (the padding contributes nothing); all loads of
+    // a thread are issued before its LDS stores, in two batches of eight elements
+    constexpr int NT = PM == 64 ? 256 : 64, PER = PM * PM / NT, BATCH = 8;
+    const bool from_q = FWD && a.q;
+    const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
+    const double *src = from_q ? a.q : a.in;
+#pragma unroll
+    for (int b0 = 0; b0 < PER; b0 += BATCH) {
+        double vx[BATCH], vy[BATCH], vp[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+            vx[u] = (r < nx && c < nx) ? a.tx[r * nx + c] : 0.0;
+            vy[u] = (r < ny && c < ny) ? a.ty[r * ny + c] : 0.0;
+            vp[u] = (r < ny && c < nx) ? src[base + r * nx + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+            Tx[r * LD + c] = vx[u];
+            Ty[r * LD + c] = vy[u];
+            P[r * LD + c] = (from_q && r < ny && c < nx) ? -a.K * (vp[u] + lump) : vp[u];
+        }
     }
     __syncthreads();
     if (FWD) {
         // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
-        lds_product(P, LD, 1, Tx, 1, LD, R, LD, ny, nx, nx);
+        mfma_product<PM>(P, LD, 1, Tx, 1, LD, R, LD);
         __syncthreads();
-        lds_product(Ty, LD, 1, R, LD, 1, P, LD, ny, nx, ny);
+        mfma_product<PM>(Ty, LD, 1, R, LD, 1, P, LD);
     } else {
         // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
-        lds_product(Ty, 1, LD, P, LD, 1, R, LD, ny, nx, ny);
+        mfma_product<PM>(Ty, 1, LD, P, LD, 1, R, LD);
         __syncthreads();
-        lds_product(R, LD, 1, Tx, LD, 1, P, LD, ny, nx, nx);
+        mfma_product<PM>(R, LD, 1, Tx, LD, 1, P, LD);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
@@ -781,12 +814,17 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
 
 hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
                               uint32_t nseg, uint32_t longest, hipStream_t stream) {
-    if (longest * 32 > TRI_CELLS) return hipErrorInvalidValue;
-    if (longest * 64 <= TRI_CELLS)
+    if (longest > TRI_LDS_MAX) return hipErrorInvalidValue;
+    // the widest work-groups that still give every compute unit one
+    const uint32_t wg64 = (nmodes + 63) / 64 * nseg, wg32 = (nmodes + 31) / 32 * nseg;
+    if (longest * 64 <= TRI_CELLS && wg64 >= 256)
         hipLaunchKernelGGL((tridiag_lds<64>), dim3((nmodes + 63) / 64, nseg), dim3(256), 0, stream, b, piv, out,
                            nmodes, seg);
-    else
+    else if (wg32 >= 256)
         hipLaunchKernelGGL((tridiag_lds<32>), dim3((nmodes + 31) / 32, nseg), dim3(256), 0, stream, b, piv, out,
+                           nmodes, seg);
+    else
+        hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, out,
                            nmodes, seg);
     return hipGetLastError();
 }
