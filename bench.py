@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -50,7 +51,7 @@ def traffic_from_profile(storage: str, n: int):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, target_s: float = 12.0):
+def cpu_baseline(w, sc: float, target_s: float = 12.0):
     """The FP64 oracle on the same 256^3 workload, a bounded number of steps."""
     import oracle
 
@@ -69,9 +70,25 @@ def cpu_baseline(w, target_s: float = 12.0):
     elapsed = t1 + t2
     sites = w.nspecies * w.nx * w.ny * w.nz
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": sites * steps / elapsed / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} of the 2000 steps of the {w.nx}^3 binary workload, FP64, "
-                      f"{elapsed:.1f} s on {threads} OpenMP threads"}
+    out = {"value": sites * steps / elapsed / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} of the 2000 steps of the {w.nx}^3 binary workload, FP64, "
+                     f"{elapsed:.1f} s on {threads} OpenMP threads"}
+    # the same oracle on one thread, one step, in a child process (OpenMP reads its thread
+    # count at start-up); the child does not touch the GPU
+    code = ("import sys, time; sys.path.insert(0, %r); import oracle, workloads as WL; "
+            "w = WL.binary_multimode(n=%d, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=%r, seed=2); "
+            "o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag); "
+            "[o.set_state(s, w.n[s], w.u[s]) for s in range(w.nspecies)]; "
+            "t0 = time.perf_counter(); o.step(1); print(time.perf_counter() - t0)") % (ROOT, w.nx, sc)
+    try:
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+        one = float(r.stdout.strip().splitlines()[-1])
+        out["single_thread"] = {"value": sites / one / 1e9, "unit": "GLUPS", "cores": 1,
+                                "sample": f"1 step of the same workload, {one:.1f} s"}
+    except (subprocess.SubprocessError, ValueError, IndexError) as e:
+        out["single_thread"] = {"value": None, "error": str(e)[:200]}
+    return out
 
 
 def time_storage(P, w, storage, steps, warmup, autotune=False):
@@ -292,6 +309,71 @@ def bench_precision_large(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_electrokinetics(args):
+    """The paper's charged-slit experiment (Sec. IV) at full size: 64 x 64 x 130, solvent +
+    cation + anion, lambda_D = 8, sigma = -1e-4 per wall, E_x = 1e-4, Sc = 100, direct
+    Poisson solve, `steps` steps from rest, each storage form.  Prints one JSON line: the
+    electro-osmotic mobility u_centre / E_x against Helmholtz-Smoluchowski, the mass flow
+    I_m and the electro-osmotic current I_eo against twice the paper's half-channel formulas
+    (eqs. theomassflow, theo), the conductivity I / (E_x H) against its conduction part
+    (D / v_T^2) sum (n+ + n-) / H plus I_eo / (E_x H), and the step time."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_1507_04891_amd as P
+    import workloads as WL
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    Ex, sigma, H = w.E[0], w.sigma[0], w.nz - 2
+    nu = (w.tau_visc - 0.5) / 3.0
+    kB = 4 * math.pi * w.bjerrum
+    kd = 1.0 / 8.0
+    out = {"workload": "charged ternary slit 64x64x130 (fluid 64x64x128), lambda_D=8, sigma=-1e-4, E_x=1e-4, "
+                       "Sc=100, direct Poisson solve, from rest", "steps": args.steps}
+    for st in args.storage.split(","):
+        lat = P.from_workload(w, storage=st, stream=stream, poisson=dict(method="direct"))
+        s0 = torch.cuda.Event(enable_timing=True)
+        s1 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        lat.step(args.steps)
+        s1.record(stream)
+        torch.cuda.synchronize()
+        pr = lat.zprofiles()
+        psi = lat.potential().mean(axis=(1, 2))
+        lat.step(1)
+        pr = (0.5 * (pr + lat.zprofiles()))[:, :, 1:-1]
+        psi = (0.5 * (psi + lat.potential().mean(axis=(1, 2))))[1:-1]
+        n = pr[:, 0]
+        rho = n.sum(0)
+        ux = pr[:, 1].sum(0) / rho
+        hs = Ex * (psi - (psi[0] + 0.5 * kB * sigma)) / (kB * nu * rho)
+        c = lambda v: 0.5 * (v[H // 2 - 1] + v[H // 2])
+        Im = float((rho * ux).sum())
+        Im_th = 2 * (Ex * sigma / nu) / kd ** 2 * (1 - (kd * H / 2) / math.tanh(kd * H / 2))
+        Ieo = float(((n[1] - n[2]) * ux).sum())
+        eta = nu * rho.mean()
+        Ieo_th = -2 * (Ex * sigma ** 2 / (eta * kd * math.tanh(kd * H / 2) ** 2)) * (
+            (math.sinh(kd * H) + kd * H) / (4 * math.cosh(kd * H / 2) ** 2)
+            - math.sinh(kd * H / 2) / math.cosh(kd * H / 2))
+        I = float((pr[1, 1] - pr[2, 1]).sum())
+        tau_d = 1.0 / w.omega_drag
+        cond = (tau_d - 0.5) * float((n[1] + n[2]).sum()) * Ex
+        out[st] = {"ms_per_step": round(s0.elapsed_time(s1) / args.steps, 4),
+                   "mobility": c(ux) / Ex, "mobility_hs": c(hs) / Ex, "err_mobility_vs_hs": c(ux) / c(hs) - 1,
+                   "I_m": Im, "I_m_paper": Im_th, "err_I_m": Im / Im_th - 1,
+                   "I_eo": Ieo, "I_eo_paper": Ieo_th, "err_I_eo": Ieo / Ieo_th - 1,
+                   "conductivity": I / (Ex * H), "conduction_plus_convection": (cond + Ieo) / (Ex * H),
+                   "err_conductivity": I / (cond + Ieo) - 1, "ohmic_over_eo": (I - Ieo) / Ieo,
+                   "mass_drift": [float(v) for v in lat.mass_totals() / np.array([a.sum() for a in w.n]) - 1]}
+        del lat
+        print(f"{st} done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
 def bench_precision(args):
     """Transport coefficients with every storage form against FP64 storage: the mutual
     diffusivity D from a decaying concentration wave (Sc 10 and 100; D = v_T^2 (1/omega_drag
@@ -375,7 +457,7 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the library pick the work-group shape of the step (default: its default shape)")
     ap.add_argument("--workload", default="binary",
-                    choices=["binary", "slit", "channels", "precision", "warmstart"],
+                    choices=["binary", "slit", "channels", "precision", "warmstart", "electrokinetics"],
                     help="binary: the 256^3 throughput benchmark (default); slit: the charged slit; "
                          "channels: 64 charged slit channels in one lattice")
     ap.add_argument("--poisson", default="sor", choices=["sor", "multigrid", "direct"])
@@ -408,6 +490,9 @@ def main():
         return
     if args.workload == "warmstart":
         bench_warmstart(args)
+        return
+    if args.workload == "electrokinetics":
+        bench_electrokinetics(args)
         return
 
     import torch
@@ -459,7 +544,7 @@ def main():
         out["copy_probe_bytes"] = nbytes
         del src, dst
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, args.sc)
     print(json.dumps(out), flush=True)
 
 
