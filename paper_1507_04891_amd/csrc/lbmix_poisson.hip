@@ -603,54 +603,69 @@ __device__ void mfma_product(const double *A, int ar, int ak, const double *B, i
     }
 }
 
-// Transform of one plane along x and y in LDS, one work-group per plane: PM = 64 (256
-// threads, 133 KB of LDS) for planes up to 64 x 64, PM = 32 (one wave, 34 KB, four
-// work-groups per compute unit) for planes up to 32 x 32.
+// Transform of planes along x and y in LDS: PM = 64 (256 threads, 133 KB of LDS) for planes
+// up to 64 x 64, PM = 32 (one wave, 34 KB, four work-groups per compute unit) for planes up to
+// 32 x 32.  A work-group stages the two bases once and then transforms the planes z =
+// blockIdx.x, blockIdx.x + gridDim.x, ...
 template <bool FWD, int PM>
 __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
     constexpr int LD = PM + 1;   // row stride of the LDS arrays
     __shared__ double P[PM * LD], R[PM * LD], Tx[PM * LD], Ty[PM * LD];
     const int nx = a.nx, ny = a.ny;
-    const uint32_t z = blockIdx.x;
-    const size_t base = (size_t)z * nx * ny;
-    // bases and plane, zero-padded to PM x PM (the padding contributes nothing); all loads of
-    // a thread are issued before its LDS stores, in two batches of eight elements
+    // bases and planes, zero-padded to PM x PM (the padding contributes nothing); all loads of
+    // a thread are issued before its LDS stores, in batches of eight elements
     constexpr int NT = PM == 64 ? 256 : 64, PER = PM * PM / NT, BATCH = 8;
-    const bool from_q = FWD && a.q;
-    const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
-    const double *src = from_q ? a.q : a.in;
 #pragma unroll
     for (int b0 = 0; b0 < PER; b0 += BATCH) {
-        double vx[BATCH], vy[BATCH], vp[BATCH];
+        double vx[BATCH], vy[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
             vx[u] = (r < nx && c < nx) ? a.tx[r * nx + c] : 0.0;
             vy[u] = (r < ny && c < ny) ? a.ty[r * ny + c] : 0.0;
-            vp[u] = (r < ny && c < nx) ? src[base + r * nx + c] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
             Tx[r * LD + c] = vx[u];
             Ty[r * LD + c] = vy[u];
-            P[r * LD + c] = (from_q && r < ny && c < nx) ? -a.K * (vp[u] + lump) : vp[u];
         }
     }
-    __syncthreads();
-    if (FWD) {
-        // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
-        mfma_product<PM>(P, LD, 1, Tx, 1, LD, R, LD);
+    const bool from_q = FWD && a.q;
+    const double *src = from_q ? a.q : a.in;
+    for (uint32_t z = blockIdx.x; z < a.nplanes; z += gridDim.x) {
+        const size_t base = (size_t)z * nx * ny;
+        const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
+#pragma unroll
+        for (int b0 = 0; b0 < PER; b0 += BATCH) {
+            double vp[BATCH];
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+                vp[u] = (r < ny && c < nx) ? src[base + r * nx + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < BATCH; ++u) {
+                const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+                P[r * LD + c] = (from_q && r < ny && c < nx) ? -a.K * (vp[u] + lump) : vp[u];
+            }
+        }
         __syncthreads();
-        mfma_product<PM>(Ty, LD, 1, R, LD, 1, P, LD);
-    } else {
-        // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
-        mfma_product<PM>(Ty, 1, LD, P, LD, 1, R, LD);
+        if (FWD) {
+            // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
+            mfma_product<PM>(P, LD, 1, Tx, 1, LD, R, LD);
+            __syncthreads();
+            mfma_product<PM>(Ty, LD, 1, R, LD, 1, P, LD);
+        } else {
+            // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
+            mfma_product<PM>(Ty, 1, LD, P, LD, 1, R, LD);
+            __syncthreads();
+            mfma_product<PM>(R, LD, 1, Tx, LD, 1, P, LD);
+        }
         __syncthreads();
-        mfma_product<PM>(R, LD, 1, Tx, LD, 1, P, LD);
+        for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
+        __syncthreads();   // P is restaged for the next plane
     }
-    __syncthreads();
-    for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
 }
 
 // a <- -a / (mu_x + mu_y + mu_z) in the transformed basis of a periodic box (0 for the
@@ -797,8 +812,11 @@ hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const Plan
 
 hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     if (a.nx > 64 || a.ny > 64) return hipErrorInvalidValue;
-    const dim3 g(a.nplanes);
-    if (a.nx <= 32 && a.ny <= 32) {
+    const bool small = a.nx <= 32 && a.ny <= 32;
+    // as many work-groups as fit on the chip at once (LDS-bound: 4 or 1 per compute unit)
+    const uint32_t fit = small ? 4 * 256 : 256;
+    const dim3 g(a.nplanes < fit ? a.nplanes : fit);
+    if (small) {
         if (forward)
             hipLaunchKernelGGL((spec_xy<true, 32>), g, dim3(64), 0, stream, a);
         else
