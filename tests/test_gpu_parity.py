@@ -363,7 +363,10 @@ def test_multigrid_cycles_on_the_charged_slit(P):
 
 
 DIRECT_CASES = [("slit", (16, 8, 34)), ("periodic", (16, 8, 12)), ("slit", (7, 5, 13)), ("periodic", (9, 6, 7)),
-                ("slit", (1, 1, 12)), ("periodic", (70, 3, 5)), ("slit", (130, 66, 8))]
+                ("slit", (1, 1, 12)), ("periodic", (70, 3, 5)), ("slit", (130, 66, 8)),
+                # more planes than transform work-groups (256 of 64 x 64, 1024 of 32 x 32), and
+                # a segment longer than the LDS elimination takes
+                ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100))]
 
 
 def charged_case(geometry, dims):
@@ -378,7 +381,8 @@ def charged_case(geometry, dims):
 def test_direct_poisson_fp64_matches_oracle(P, oracle_mod, geometry, dims):
     """The direct solve (Fourier bases in x, y; tridiagonal or Fourier in z) against the
     oracle's eigenbasis solve: odd and one-node extents, ragged 64-wide transform tiles
-    (70, 130, 66), 30 coupled steps at the full FP64 bar."""
+    (70, 130, 66), planes looped within a transform work-group, 30 coupled steps at the
+    full FP64 bar."""
     w = charged_case(geometry, dims)
     lat = gpu_for(P, w, "f64", poisson=dict(method="direct"))
     o = oracle_for(oracle_mod, w, poisson="direct")
