@@ -91,13 +91,13 @@ def cpu_baseline(w, sc: float, target_s: float = 12.0):
     return out
 
 
-def time_storage(P, w, storage, steps, warmup, autotune=False):
+def time_storage(P, w, storage, steps, warmup, autotune=False, stochastic=None):
     """Time `steps` steps of the workload with one storage form; one fused launch per step
     (work-group shape: the library's default, or its autotuner's pick)."""
     import torch
 
     stream = torch.cuda.current_stream()
-    lat = P.from_workload(w, storage=storage, stream=stream)
+    lat = P.from_workload(w, storage=storage, stream=stream, stochastic=stochastic)
     shape = lat.autotune(reps=5) if autotune else None
     lat.step(warmup)
     start = torch.cuda.Event(enable_timing=True)
@@ -334,8 +334,9 @@ def bench_electrokinetics(args):
     kd = 1.0 / 8.0
     out = {"workload": "charged ternary slit 64x64x130 (fluid 64x64x128), lambda_D=8, sigma=-1e-4, E_x=1e-4, "
                        "Sc=100, direct Poisson solve, from rest", "steps": args.steps}
-    for st in args.storage.split(","):
-        lat = P.from_workload(w, storage=st, stream=stream, poisson=dict(method="direct"))
+    for name in args.storage.split(","):
+        st, sr = (name[:-3], True) if name.endswith(":sr") else (name, None)
+        lat = P.from_workload(w, storage=st, stream=stream, stochastic=sr, poisson=dict(method="direct"))
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
@@ -362,7 +363,7 @@ def bench_electrokinetics(args):
         I = float((pr[1, 1] - pr[2, 1]).sum())
         tau_d = 1.0 / w.omega_drag
         cond = (tau_d - 0.5) * float((n[1] + n[2]).sum()) * Ex
-        out[st] = {"ms_per_step": round(s0.elapsed_time(s1) / args.steps, 4),
+        out[name] = {"ms_per_step": round(s0.elapsed_time(s1) / args.steps, 4),
                    "mobility": c(ux) / Ex, "mobility_hs": c(hs) / Ex, "err_mobility_vs_hs": c(ux) / c(hs) - 1,
                    "I_m": Im, "I_m_paper": Im_th, "err_I_m": Im / Im_th - 1,
                    "I_eo": Ieo, "I_eo_paper": Ieo_th, "err_I_eo": Ieo / Ieo_th - 1,
@@ -370,7 +371,7 @@ def bench_electrokinetics(args):
                    "err_conductivity": I / (cond + Ieo) - 1, "ohmic_over_eo": (I - Ieo) / Ieo,
                    "mass_drift": [float(v) for v in lat.mass_totals() / np.array([a.sum() for a in w.n]) - 1]}
         del lat
-        print(f"{st} done", file=sys.stderr, flush=True)
+        print(f"{name} done", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
 
 
@@ -392,7 +393,8 @@ def bench_precision(args):
     L = 128
     k = 2 * math.pi / L
     basis = np.sin(k * np.arange(L))[None, None, :]
-    forms = [("f64", None), ("f32", None), ("f32s", None), ("f16s", True), ("f16s", False), ("bf16s", True)]
+    forms = [("f64", None), ("f32", None), ("f32s", None), ("f32s", True), ("f16s", True), ("f16s", False),
+             ("bf16s", True)]
     name = lambda st, sr: st + ("" if sr is None else (" SR" if sr else " RNE"))
     out = {"workload": "D: binary sine 128x64x64 (amp 1e-3); nu: shear wave 128x64x64, tau 0.8; "
                        "mobility: charged slit 16x16x34, lambda_D 4, sigma -1e-4, E_x 1e-5, Sc 100"}
@@ -533,6 +535,11 @@ def main():
             var[st] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
                        "hbm_frac": round(r["frac"], 4),
                        "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}
+        # shifted FP32 with FP64 arithmetic and stochastically rounded stores
+        r = time_storage(P, w, "f32s", args.steps, args.warmup, autotune=args.autotune, stochastic=True)
+        var["f32s_stochastic"] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
+                                  "hbm_frac": round(r["frac"], 4),
+                                  "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}
         out["variants"] = var
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 2 ** 30)

@@ -301,15 +301,17 @@ int lbmix_set_warm_start_net(lbmix_ctx *ctx, lbmix_net *net);
  * without charged species, for a bad network or arguments; ESTATE without a state. */
 int lbmix_train_warm_start(lbmix_ctx *ctx, lbmix_net *net, int nsteps, float lr, double *losses);
 
-/* Rounding of the 16-bit storage forms (LBMIX_BF16_SHIFTED, LBMIX_F16_SHIFTED): mode 0
- * rounds to nearest-even (default); mode 1 rounds stochastically, each stored value going
- * up or down with the probabilities that make its expectation exact, the random bits drawn
- * from a counter-based hash of (seed, step, node, direction, species), so runs are
- * reproducible and a restored checkpoint continues bitwise.  Nearest rounding of a 16-bit
- * deviation has fixed points: a slow mode whose change per step is below half a unit in
- * the last place (relative 2.4e-4 for FP16) stops evolving; stochastic rounding removes
- * this bias at the price of noise that averages out over nodes.  Errors: EINVAL for
- * another mode, or mode 1 with a storage form that is not 16-bit. */
+/* Rounding of the stored populations of the FP32 and 16-bit forms: mode 0 rounds to
+ * nearest-even (default); mode 1 rounds stochastically, each stored value going up or down
+ * with the probabilities that make its expectation exact, the random bits drawn from a
+ * counter-based hash of (seed, step, node, direction, species), so runs are reproducible
+ * and a restored checkpoint continues bitwise.  Nearest rounding has fixed points: a slow
+ * mode whose change per step is below half a unit in the last place of the stored value
+ * (relative 2.4e-4 for FP16) stops evolving, and one just above it is biased the same way
+ * every step; stochastic rounding removes this bias at the price of noise that averages out
+ * over nodes.  For the FP32 forms mode 1 also computes the collision in FP64 (the exact
+ * value being rounded must be known beyond FP32).  Errors: EINVAL for another mode, or
+ * mode 1 with FP64 storage; ESTATE for a change of mode after the first step. */
 int lbmix_set_rounding(lbmix_ctx *ctx, int mode, unsigned long long seed);
 
 /* FP16 storage scale of one species: the bound `rel_range` of |f_p - w_p rho0| / (w_p rho0)

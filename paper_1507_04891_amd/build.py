@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbmix.so")
 SOURCES = [os.path.join(HERE, "csrc", name)
-           for name in ("lbmix_step_f64.hip", "lbmix_step_f32.hip", "lbmix_step_bf16.hip", "lbmix_step_f16.hip",
+           for name in ("lbmix_step_f64.hip", "lbmix_step_f32.hip", "lbmix_step_f32x.hip", "lbmix_step_bf16.hip", "lbmix_step_f16.hip",
                         "lbmix_step.hip", "lbmix_poisson.hip", "lbmix_net.hip", "lbmix_net_runtime.hip",
                         "lbmix_runtime.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -74,7 +74,7 @@ struct lbmix_ctx {
     double *psi_prev = nullptr;       // two previous solutions (warm_start 1)
     int have_prev = 0;
     int mg_last = 0;                  // V-cycles of the last multigrid solve
-    int rounding = 0;                 // 16-bit forms: 0 nearest-even, 1 stochastic
+    int rounding = 0;                 // FP32 and 16-bit forms: 0 nearest-even, 1 stochastic
     unsigned long long round_seed = 0;
     int sor_max = 200000, sor_check = 10;
     // device
@@ -1384,8 +1384,10 @@ int lbmix_train_warm_start(lbmix_ctx *c, lbmix_net *net, int nsteps, float lr, d
 int lbmix_set_rounding(lbmix_ctx *c, int mode, unsigned long long seed) {
     if (!c) return LBMIX_EINVAL;
     if (mode != 0 && mode != 1) return c->fail(LBMIX_EINVAL, "rounding mode is 0 or 1");
-    if (mode == 1 && c->storage != LBMIX_BF16_SHIFTED && c->storage != LBMIX_F16_SHIFTED)
-        return c->fail(LBMIX_EINVAL, "stochastic rounding applies to the 16-bit storage forms");
+    if (mode == 1 && c->storage == LBMIX_F64)
+        return c->fail(LBMIX_EINVAL, "stochastic rounding applies to the FP32 and 16-bit storage forms");
+    if (c->started && mode != c->rounding)
+        return c->fail(LBMIX_ESTATE, "the rounding mode is fixed once stepping has started");
     c->rounding = mode;
     c->round_seed = seed;
     return LBMIX_OK;

@@ -56,6 +56,7 @@ __host__ __device__ constexpr C wgt(int p) {
 
 struct BF16 {};
 struct F16 {};
+struct F32X {};   // FP32 storage with FP64 arithmetic, for stochastic rounding of the stores
 
 template <class T> struct Codec;
 template <> struct Codec<double> {
@@ -143,6 +144,39 @@ template <> struct Codec<F16> {
     __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
         if constexpr (SR) return f32_to_f16_sr(v * sc, rnd);
         else return __half_as_ushort(__float2half_rn(v * sc));   // IEEE nearest-even
+    }
+};
+
+// FP32 storage, stochastically rounded from FP64 arithmetic: the nearest FP32 value f of v and
+// its neighbour g on the side of v are chosen with probabilities that make the expected stored
+// value v (to 2^-17 of a unit in the last place: 16 random bits, the high half of rnd).  The
+// residual v - f and the spacing g - f are exact in FP64.
+__device__ inline float f64_to_f32_sr(double v, uint32_t rnd) {
+    const float f = float(v);
+    const double r = v - double(f);
+    if (r == 0.0 || !isfinite(f)) return f;
+    const uint32_t bits = __float_as_uint(f);
+    uint32_t gb;
+    if (f == 0.0f)
+        gb = r > 0.0 ? 1u : 0x80000001u;                       // smallest subnormal, sign of r
+    else
+        gb = ((f > 0.0f) == (r > 0.0)) ? bits + 1u : bits - 1u;   // away from / toward zero
+    const float g = __uint_as_float(gb);
+    const double s = fabs(double(g) - double(f));
+    const double u = (double(rnd >> 16) + 0.5) * (1.0 / 65536.0);
+    return fabs(r) > u * s ? g : f;
+}
+
+template <> struct Codec<F32X> {
+    using C = double;
+    using S = float;
+    static constexpr bool kRounds = true;
+    static constexpr bool kWideSum = true;
+    __device__ static C decode(S v, float inv) { return double(v) * double(inv); }
+    template <bool SR = false>
+    __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
+        if constexpr (SR) return f64_to_f32_sr(v * double(sc), rnd);
+        else return float(v * double(sc));
     }
 };
 
@@ -579,5 +613,6 @@ extern LBMIX_STEP_STORE(double);
 extern LBMIX_STEP_STORE(float);
 extern LBMIX_STEP_STORE(BF16);
 extern LBMIX_STEP_STORE(F16);
+extern LBMIX_STEP_STORE(F32X);
 
 }  // namespace lbmix

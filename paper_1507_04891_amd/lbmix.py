@@ -433,8 +433,8 @@ class Net:
 def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None,
                   forcing="paper"):
     """Build a Lattice from a workloads.Workload or workloads.ChannelStack description
-    (parameters and initial fields).  stochastic: rounding of the 16-bit forms (default:
-    stochastic for them); forcing: "paper" or "guo"."""
+    (parameters and initial fields).  stochastic: rounding of the stored populations (default:
+    stochastic for the 16-bit forms, nearest for the FP32 ones); forcing: "paper" or "guo"."""
     stack = w.geometry == "channels"
     lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream,
                   widths=w.widths if stack else None)
@@ -442,6 +442,8 @@ def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, 
         lat.add_species(w.rho0[s], w.valence[s])
     if storage in ("bf16s", "f16s"):
         lat.set_rounding(True if stochastic is None else stochastic, seed)
+    elif storage in ("f32", "f32s") and stochastic:
+        lat.set_rounding(True, seed)
     lat.set_tau_visc(w.tau_visc)
     if stack:
         for c in range(len(w.widths)):

@@ -76,6 +76,29 @@ def test_paper_mass_flow_and_electroosmotic_current(run):
     assert I / Ieo > 100
 
 
+def test_fp32_stochastic_rounding_mobility():
+    """The same slit with FP32 storage rounded stochastically from FP64 arithmetic: the
+    electro-osmotic mobility stays within 1e-3 of Helmholtz-Smoluchowski, where nearest
+    rounding of the FP32 store is biased by 2e-3 at this flow speed (u ~ 5e-7)."""
+    import paper_1507_04891_amd as P
+    w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    lat = P.from_workload(w, storage="f32s", stochastic=True, seed=1, poisson=dict(method="direct"))
+    lat.step(80000)
+    pr = lat.zprofiles()
+    psi = lat.potential().mean(axis=(1, 2))
+    lat.step(1)
+    pr = (0.5 * (pr + lat.zprofiles()))[:, :, 1:-1]
+    psi = (0.5 * (psi + lat.potential().mean(axis=(1, 2))))[1:-1]
+    rho = pr[:, 0].sum(0)
+    ux = pr[:, 1].sum(0) / rho
+    nu = CS2 * (w.tau_visc - 0.5)
+    k = 4 * math.pi * w.bjerrum
+    hs = w.E[0] * (psi - (psi[0] + 0.5 * k * w.sigma[0])) / (k * nu * rho)
+    H = w.nz - 2
+    c = lambda v: 0.5 * (v[H // 2 - 1] + v[H // 2])
+    assert abs(c(ux) / c(hs) - 1) < 1e-3, c(ux) / c(hs) - 1
+
+
 def test_mass_is_conserved(run):
     """The collision conserves mass exactly; FP32 storage rounds every stored deviation, so over
     80 000 steps the totals may move by the accumulated FP32 rounding (unit roundoff 6e-8 of

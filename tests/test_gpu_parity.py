@@ -725,3 +725,58 @@ def test_degenerate_cases(P, oracle_mod):
     a.step(60)
     o.step(60)
     compare_fp64(a, o, ws)
+
+
+@pytest.mark.parametrize("case", ["slit_charged", "binary_modes"])
+def test_fp32_stochastic_rounding_matches_oracle(P, oracle_mod, case):
+    """Shifted FP32 storage with FP64 collision arithmetic and stochastically rounded stores
+    against the oracle, to the FP32 bar (every store errs by less than one FP32 unit in the
+    last place, with zero mean)."""
+    if case == "slit_charged":
+        w = WL.charged_slit(nx=8, ny=6, nz=18, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+        poisson = dict(method="direct")
+    else:
+        w = WL.binary_multimode(n=16, amp=1e-2, nmodes=3, shear=1e-2, sc=30.0, seed=4)
+        poisson = None
+    lat = P.from_workload(w, storage="f32s", stochastic=True, seed=3, poisson=poisson)
+    o = oracle_for(oracle_mod, w)
+    lat.step(20)
+    o.step(20)
+    m = fluid(w)
+    for s in range(w.nspecies):
+        ng, _ = lat.moments(s)
+        no, _ = o.moments(s)
+        assert rel_max(ng, no, m) <= 1e-5, s
+        assert rel_to_deviation(ng, no, w.rho0[s], m) <= 1e-3, s
+    if w.bjerrum > 0:
+        assert rel_max(lat.potential(), o.potential(), m) <= 1e-5
+
+
+def test_fp32_stochastic_rounding_is_reproducible(P):
+    """The rounding stream is a function of (seed, step, node): captured steps and a restored
+    checkpoint continue it bitwise; another seed rounds differently."""
+    w = WL.charged_slit(nx=16, ny=8, nz=20, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+    pp = dict(method="direct")
+    a = P.from_workload(w, storage="f32s", stochastic=True, seed=5, poisson=pp)
+    g = P.from_workload(w, storage="f32s", stochastic=True, seed=5, poisson=pp)
+    c = P.from_workload(w, storage="f32s", stochastic=True, seed=6, poisson=pp)
+    g.set_step_graph(True)
+    for lat in (a, g, c):
+        lat.step(10)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        a.save(path)
+        a.step(10)
+        b = P.Lattice(w.nx, w.ny, w.nz, geometry="slit", storage="f32s")
+        for s in range(w.nspecies):
+            b.add_species(w.rho0[s], w.valence[s])
+        b.load(path)
+        b.step(10)
+    g.step(10)
+    c.step(10)
+    for s in range(w.nspecies):
+        np.testing.assert_array_equal(a.populations(s), b.populations(s))
+        np.testing.assert_array_equal(a.populations(s), g.populations(s))
+    assert not np.array_equal(a.populations(0), c.populations(0))
+    with pytest.raises(P.LbmixError):
+        a.set_rounding(False)
