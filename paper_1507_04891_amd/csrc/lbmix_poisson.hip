@@ -564,7 +564,7 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
     }
 }
 
-// C(r, c) = sum_k A(r, k) B(k, c) for r, c, k < N (N a multiple of 32) between LDS arrays,
+// C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN between LDS arrays,
 // with A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c], on the
 // FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
 // operand fragment feeds two products.  v_mfma_f64_16x16x4f64: lane l holds A(i, k) and
@@ -572,20 +572,20 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
 // result rows l / 16 + 4 r, r < 4, of column l mod 16.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int N>
+template <int RN, int CN, int KN>
 __device__ void mfma_product(const double *A, int ar, int ak, const double *B, int bk, int bc, double *C, int ldc) {
-    constexpr int NB = N / 32;
+    constexpr int NBR = RN / 32, NBC = CN / 32;
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int nwaves = blockDim.x >> 6;
-    for (int blk = threadIdx.x >> 6; blk < NB * NB; blk += nwaves) {
-        const int r0 = (blk / NB) * 32, c0 = (blk % NB) * 32;
+    for (int blk = threadIdx.x >> 6; blk < NBR * NBC; blk += nwaves) {
+        const int r0 = (blk / NBC) * 32, c0 = (blk % NBC) * 32;
         f64x4 acc[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-        for (int k = 0; k < N; k += 4) {
+        for (int k = 0; k < KN; k += 4) {
             const int kk = k + lk;
             const double a0 = A[(r0 + li) * ar + kk * ak], a1 = A[(r0 + 16 + li) * ar + kk * ak];
             const double b0 = B[kk * bk + (c0 + li) * bc], b1 = B[kk * bk + (c0 + 16 + li) * bc];
@@ -653,18 +653,77 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
         __syncthreads();
         if (FWD) {
             // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
-            mfma_product<PM>(P, LD, 1, Tx, 1, LD, R, LD);
+            mfma_product<PM, PM, PM>(P, LD, 1, Tx, 1, LD, R, LD);
             __syncthreads();
-            mfma_product<PM>(Ty, LD, 1, R, LD, 1, P, LD);
+            mfma_product<PM, PM, PM>(Ty, LD, 1, R, LD, 1, P, LD);
         } else {
             // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
-            mfma_product<PM>(Ty, 1, LD, P, LD, 1, R, LD);
+            mfma_product<PM, PM, PM>(Ty, 1, LD, P, LD, 1, R, LD);
             __syncthreads();
-            mfma_product<PM>(R, LD, 1, Tx, LD, 1, P, LD);
+            mfma_product<PM, PM, PM>(R, LD, 1, Tx, LD, 1, P, LD);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
         __syncthreads();   // P is restaged for the next plane
+    }
+}
+
+// Half of the transform of one plane up to 64 x 64 per work-group, for lattices with fewer
+// planes than compute units: the forward transform splits the output columns kx, the inverse
+// the output rows y, and each half needs the whole plane but only half of one basis.
+template <bool FWD>
+__global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
+    constexpr int PM = 64, LD = PM + 1, HM = 32, NT = 256, BATCH = 8;
+    __shared__ double P[PM * LD], Tx[PM * LD], Ty[PM * LD], R[PM * (HM + 1)];
+    const int nx = a.nx, ny = a.ny;
+    const uint32_t z = blockIdx.x >> 1;
+    const int h = blockIdx.x & 1;
+    const size_t base = (size_t)z * nx * ny;
+    const bool from_q = FWD && a.q;
+    const double *src = from_q ? a.q : a.in;
+    const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
+    // forward: the rows kx of the half of Tx (as Tx[0..32)), all of Ty; inverse: both bases
+    constexpr int TXR = FWD ? HM : PM;
+#pragma unroll
+    for (int b0 = 0; b0 < PM * PM / NT; b0 += BATCH) {
+        double vp[BATCH], vx[BATCH], vy[BATCH];
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+            const int rx = FWD ? HM * h + r : r;
+            vp[u] = (r < ny && c < nx) ? src[base + r * nx + c] : 0.0;
+            vy[u] = (r < ny && c < ny) ? a.ty[r * ny + c] : 0.0;
+            vx[u] = (r < TXR && rx < nx && c < nx) ? a.tx[rx * nx + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < BATCH; ++u) {
+            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
+            P[r * LD + c] = (from_q && r < ny && c < nx) ? -a.K * (vp[u] + lump) : vp[u];
+            Ty[r * LD + c] = vy[u];
+            Tx[r * LD + c] = vx[u];
+        }
+    }
+    __syncthreads();
+    if (FWD) {
+        // R[y][kx'] = sum_x P[y][x] Tx[32 h + kx'][x];  P[ky][kx'] = sum_y Ty[ky][y] R[y][kx']
+        mfma_product<PM, HM, PM>(P, LD, 1, Tx, 1, LD, R, HM + 1);
+        __syncthreads();
+        mfma_product<PM, HM, PM>(Ty, LD, 1, R, HM + 1, 1, P, LD);
+        __syncthreads();
+        for (int k = threadIdx.x; k < PM * HM; k += NT) {
+            const int ky = k / HM, kx = HM * h + k % HM;
+            if (ky < ny && kx < nx) a.out[base + ky * nx + kx] = P[ky * LD + k % HM];
+        }
+    } else {
+        // R[y'][kx] = sum_ky Ty[ky][32 h + y'] P[ky][kx];  P[y'][x] = sum_kx R[y'][kx] Tx[kx][x]
+        mfma_product<HM, PM, PM>(Ty + HM * h, 1, LD, P, LD, 1, R, LD);
+        __syncthreads();
+        mfma_product<HM, PM, PM>(R, LD, 1, Tx, LD, 1, P, LD);
+        __syncthreads();
+        for (int k = threadIdx.x; k < HM * PM; k += NT) {
+            const int y = HM * h + k / PM, x = k % PM;
+            if (y < ny && x < nx) a.out[base + y * nx + x] = P[(k / PM) * LD + x];
+        }
     }
 }
 
@@ -813,6 +872,13 @@ hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const Plan
 hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     if (a.nx > 64 || a.ny > 64) return hipErrorInvalidValue;
     const bool small = a.nx <= 32 && a.ny <= 32;
+    if (!small && a.nplanes <= 256) {   // too few planes to give every compute unit a whole one
+        if (forward)
+            hipLaunchKernelGGL((spec_xy_half<true>), dim3(2 * a.nplanes), dim3(256), 0, stream, a);
+        else
+            hipLaunchKernelGGL((spec_xy_half<false>), dim3(2 * a.nplanes), dim3(256), 0, stream, a);
+        return hipGetLastError();
+    }
     // as many work-groups as fit on the chip at once (LDS-bound: 4 or 1 per compute unit)
     const uint32_t fit = small ? 4 * 256 : 256;
     const dim3 g(a.nplanes < fit ? a.nplanes : fit);

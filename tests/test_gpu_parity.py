@@ -366,7 +366,9 @@ DIRECT_CASES = [("slit", (16, 8, 34)), ("periodic", (16, 8, 12)), ("slit", (7, 5
                 ("slit", (1, 1, 12)), ("periodic", (70, 3, 5)), ("slit", (130, 66, 8)),
                 # more planes than transform work-groups (256 of 64 x 64, 1024 of 32 x 32), and
                 # a segment longer than the LDS elimination takes
-                ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100))]
+                ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100)),
+                # planes between 32 and 64 wide, fewer than 256: split in halves
+                ("slit", (40, 36, 34)), ("periodic", (48, 33, 10))]
 
 
 def charged_case(geometry, dims):
