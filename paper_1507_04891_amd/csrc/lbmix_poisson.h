@@ -106,10 +106,11 @@ hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipS
 // [seg[s], seg[s+1]), s < nseg; piv = inverse pivots [plane][mode].
 hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
                             uint32_t nseg, hipStream_t stream);
-// Per-plane transform along x and y of a plane of at most SPEC_XY_MAX nodes (nx, ny <= 64),
-// in LDS, one work-group per plane.  Forward: out = Ty P Tx^T with P the plane of `in`, or,
-// when `q` is given, of b = -K (q + lump_z) (lumps from planes, which may be null).
-// Inverse: out = Ty^T P Tx.
+// Per-plane transform along x and y of planes of at most SPEC_XY_MAX nodes (nx, ny <= 64),
+// in LDS on the FP64 matrix cores: each work-group takes several planes, or half a plane
+// when there are fewer planes than compute units.  Forward: out = Ty P Tx^T with P the plane
+// of `in`, or, when `q` is given, of b = -K (q + lump_z) (lumps from planes, which may be
+// null).  Inverse: out = Ty^T P Tx.
 constexpr uint32_t SPEC_XY_MAX = 4096;
 struct SpecXY {
     const double *in, *q;
