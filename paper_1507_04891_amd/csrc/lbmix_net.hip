@@ -1,9 +1,10 @@
 // gfx950 kernels of the learned warm start of the Poisson solve: 3 x 3 x 3 convolutions with
 // bias and ReLU (forward, transposed for the input gradient, weight gradient), mean-square
 // loss, Adam, and the glue between the FP64 potential and the FP32 network.  The network
-// works on lattices of a few hundred thousand nodes with at most 16 channels: one thread per
-// node accumulates every output channel, with the weights of the layer in LDS (read by all
-// lanes at once).
+// works on lattices of a few hundred thousand nodes with at most 16 channels.  The 16 -> 16
+// convolutions run on the FP32 matrix cores; the others use one thread per node that
+// accumulates every output channel, with the weights of the layer in LDS (read by all lanes
+// at once).
 #include "lbmix_net.h"
 
 namespace lbmix {
@@ -55,6 +56,55 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
     for (int co = 0; co < a.cout; ++co) {
         const float r = acc[co];
         a.y[(size_t)co * a.N + v] = (a.relu && r < 0.0f) ? 0.0f : r;
+    }
+}
+
+// The same convolution for 16 input and 16 output channels on the FP32 matrix cores: a
+// dense contraction y[co][v] = sum_{k, ci} w[co][ci][k] x[ci][v + offset_k] with K = 27 x 16.
+// Each wave computes tiles of 16 consecutive nodes (one 16 x 16 v_mfma_f32_16x16x4f32 output,
+// rows co, columns the nodes) in 108 steps of 4 (tap k, channels 4c..4c+3): lane l supplies
+// w[co = l mod 16][4c + l/16][k] from LDS and x[4c + l/16][neighbour of node l mod 16].  The
+// output rows 4 (l / 16) + r, r < 4, of column l mod 16 come back in the lane.
+typedef float f32x4m __attribute__((ext_vector_type(4)));
+constexpr int MFMA_C = 16;
+
+__global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
+    __shared__ float sw[MFMA_C * MFMA_C * NET_K];
+    for (int i = threadIdx.x; i < MFMA_C * MFMA_C * NET_K; i += NET_BLOCK) sw[i] = a.w[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const uint32_t ntiles = (a.N + 15) / 16;
+    const uint32_t wave = blockIdx.x * (NET_BLOCK / 64) + (threadIdx.x >> 6);
+    const uint32_t nwaves = gridDim.x * (NET_BLOCK / 64);
+    float bias[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[r] = a.b ? a.b[4 * lk + r] : 0.0f;
+    for (uint32_t t = wave; t < ntiles; t += nwaves) {
+        const uint32_t v = t * 16 + li;           // the node of this lane's column
+        const bool live = v < a.N;
+        const uint32_t vv = live ? v : 0;
+        const uint32_t x = vv % a.nx, y = (vv / a.nx) % a.ny, z = vv / (a.nx * a.ny);
+        f32x4m acc = {bias[0], bias[1], bias[2], bias[3]};
+#pragma unroll 3
+        for (int k = 0; k < NET_K; ++k) {
+            const int64_t nb = live ? tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls) : -1;
+            float bx[4], aw[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int ci = 4 * c + lk;
+                bx[c] = nb >= 0 ? a.x[(size_t)ci * a.N + nb] : 0.0f;
+                aw[c] = sw[(li * MFMA_C + ci) * NET_K + k];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[c], bx[c], acc, 0, 0, 0);
+        }
+        if (live) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float o = acc[r];
+                a.y[(size_t)(4 * lk + r) * a.N + v] = (a.relu && o < 0.0f) ? 0.0f : o;
+            }
+        }
     }
 }
 
@@ -175,7 +225,15 @@ static dim3 grid_of(uint32_t n) { return dim3((n + NET_BLOCK - 1) / NET_BLOCK); 
 
 hipError_t launch_conv3(const ConvArgs &a, hipStream_t stream) {
     if (a.cin < 1 || a.cin > NET_MAXC || a.cout < 1 || a.cout > NET_MAXC) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(conv3, grid_of(a.N), dim3(NET_BLOCK), 0, stream, a);
+    if (a.cin == MFMA_C && a.cout == MFMA_C) {
+        // four 16-node tiles per work-group and pass; about two passes per wave
+        const uint32_t tiles = (a.N + 15) / 16;
+        uint32_t blocks = (tiles + 7) / 8;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(conv3_mfma, dim3(blocks), dim3(NET_BLOCK), 0, stream, a);
+    } else {
+        hipLaunchKernelGGL(conv3, grid_of(a.N), dim3(NET_BLOCK), 0, stream, a);
+    }
     return hipGetLastError();
 }
 
