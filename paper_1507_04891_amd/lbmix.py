@@ -66,8 +66,8 @@ def load_library():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1507_04891_amd/build.py "
-                           "(or __graft_entry__.build()); there is no CPU fallback")
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1507_04891_amd.build; "
+                           "there is no CPU fallback")
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
     fp = ctypes.POINTER(ctypes.c_float)

@@ -2,7 +2,7 @@
 
 The shifted forms store d_p = f_p - w_p rho0; BF16 and FP16 round stochastically (unbiased)
 by default.  The FP64 run of the GPU library is itself pinned to the oracle (test_gpu_parity),
-so it is the reference here.  Measured on MI355X (the design doc lists the numbers):
+so it is the reference here.  Measured on MI355X:
 
 * D from a concentration wave (Sec. IV, D = v_T^2 (1/omega_drag - 1/2)) at Sc = 10 and 100;
 * nu from a shear wave (Sec. IV, nu = v_T^2 (1/omega_visc - 1/2));
