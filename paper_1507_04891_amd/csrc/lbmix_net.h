@@ -34,7 +34,11 @@ hipError_t launch_flip_weights(const float *w, float *wt, int cout, int cin, hip
 hipError_t launch_relu_mask(float *g, const float *y, uint32_t n, hipStream_t stream);
 
 // gw[co][ci][k] = sum_v g[co][v] x[ci][v + offset_k]; gb[co] = sum_v g[co][v] (fixed order).
-hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, hipStream_t stream);
+// 16 -> 16 layers run on the matrix cores with per-wave partial products in `part`
+// (conv3_wgrad_workspace(N) floats; null: the general kernel).
+size_t conv3_wgrad_workspace(uint32_t N);
+hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, float *part,
+                              hipStream_t stream);
 
 // Mean-square loss over n values: g = 2 (y - t) / n, partial sums of (y - t)^2 per block
 // into partials (nblocks written to *nb).

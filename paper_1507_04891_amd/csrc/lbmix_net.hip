@@ -108,6 +108,67 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
     }
 }
 
+// Weight gradients of a 16 -> 16 layer on the FP32 matrix cores: for every tap k the 16 x 16
+// product gw_k[co][ci] = sum_v g[co][v] x[ci][v + offset_k] is a contraction over nodes.  Each
+// wave takes WG_CHUNK consecutive nodes, four per step (lane l: node l / 16 of the step,
+// channel l mod 16 of both operands), and keeps the 27 tap products in its registers, plus a
+// 28th with x = 1 whose column 0 is the bias gradient sum_v g[co][v]; the per-wave partial
+// products go to part[wave][k][co][ci] and are summed in FP64, in a fixed order, by
+// conv3_wgrad_sum.
+constexpr uint32_t WG_CHUNK = 256;
+constexpr int WG_SLOTS = NET_K + 1;   // 27 taps and the bias
+
+__global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_mfma(const ConvArgs a, const float *g, float *part) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const uint32_t wave = blockIdx.x * (NET_BLOCK / 64) + (threadIdx.x >> 6);
+    const uint32_t v_begin = wave * WG_CHUNK;
+    f32x4m acc[WG_SLOTS];
+#pragma unroll
+    for (int k = 0; k < WG_SLOTS; ++k) acc[k] = f32x4m{0.0f, 0.0f, 0.0f, 0.0f};
+    for (uint32_t v0 = v_begin; v0 < v_begin + WG_CHUNK && v0 < a.N; v0 += 4) {
+        const uint32_t v = v0 + lk;
+        const bool live = v < a.N;
+        const uint32_t vv = live ? v : 0;
+        const uint32_t x = vv % a.nx, y = (vv / a.nx) % a.ny, z = vv / (a.nx * a.ny);
+        const float gv = live ? g[(size_t)li * a.N + v] : 0.0f;   // A: g[co = li][node lk]
+#pragma unroll
+        for (int k = 0; k < NET_K; ++k) {
+            const int64_t nb = live ? tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls) : -1;
+            const float xv = nb >= 0 ? a.x[(size_t)li * a.N + nb] : 0.0f;   // B: x[ci = li] at node lk
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, xv, acc[k], 0, 0, 0);
+        }
+        acc[NET_K] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, live ? 1.0f : 0.0f, acc[NET_K], 0, 0, 0);
+    }
+    float *out = part + (size_t)wave * WG_SLOTS * MFMA_C * MFMA_C;
+#pragma unroll
+    for (int k = 0; k < WG_SLOTS; ++k)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(k * MFMA_C + 4 * lk + r) * MFMA_C + li] = acc[k][r];
+}
+
+// gw[co][ci][k] = sum over waves of part[wave][k][co][ci], and gb[co] from the bias slot
+// (column 0): one work-group per weight, FP64, strided per thread and then a fixed tree.
+__global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_sum(const float *part, uint32_t nwaves, float *gw,
+                                                              float *gb) {
+    __shared__ double red[NET_BLOCK];
+    const uint32_t i = blockIdx.x;   // (slot, co, ci)
+    double s = 0.0;
+    for (uint32_t w = threadIdx.x; w < nwaves; w += NET_BLOCK) s += (double)part[(size_t)w * WG_SLOTS * MFMA_C * MFMA_C + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = NET_BLOCK / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t k = i / (MFMA_C * MFMA_C), co = (i / MFMA_C) % MFMA_C, ci = i % MFMA_C;
+        if (k < (uint32_t)NET_K)
+            gw[(co * MFMA_C + ci) * NET_K + k] = (float)red[0];
+        else if (ci == 0)
+            gb[co] = (float)red[0];
+    }
+}
+
 __global__ void flip_weights(const float *w, float *wt, int cout, int cin) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cout * cin * NET_K) return;
@@ -248,7 +309,20 @@ hipError_t launch_relu_mask(float *g, const float *y, uint32_t n, hipStream_t st
     return hipGetLastError();
 }
 
-hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, hipStream_t stream) {
+size_t conv3_wgrad_workspace(uint32_t N) {
+    const size_t waves = (N + WG_CHUNK - 1) / WG_CHUNK;
+    return ((waves + 3) / 4) * 4 * WG_SLOTS * MFMA_C * MFMA_C;
+}
+
+hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, float *part,
+                              hipStream_t stream) {
+    if (a.cin == MFMA_C && a.cout == MFMA_C && part) {
+        const uint32_t blocks = (a.N + WG_CHUNK * 4 - 1) / (WG_CHUNK * 4);   // four waves each
+        hipLaunchKernelGGL(conv3_wgrad_mfma, dim3(blocks), dim3(NET_BLOCK), 0, stream, a, g, part);
+        hipLaunchKernelGGL(conv3_wgrad_sum, dim3(WG_SLOTS * MFMA_C * MFMA_C), dim3(NET_BLOCK), 0, stream, part,
+                           blocks * 4, gw, gb);
+        return hipGetLastError();
+    }
     const uint32_t blocks = (uint32_t)(a.cout * (a.cin * NET_K + 1));
     hipLaunchKernelGGL(conv3_wgrad, dim3(blocks), dim3(NET_BLOCK), 0, stream, a, g, gw, gb);
     return hipGetLastError();

@@ -28,6 +28,7 @@ struct lbmix_net {
     float *gb[2] = {nullptr, nullptr};   // gradients of activations (max channels x N)
     float *wt = nullptr;              // transposed weights of one layer
     double *partials = nullptr, *dloss = nullptr;
+    float *wpart = nullptr;           // per-wave partial weight gradients
     std::string err;
 
     int layers() const { return (int)ch.size() - 1; }
@@ -54,8 +55,10 @@ struct lbmix_net {
         for (float *q : {act, gb[0], gb[1], wt}) if (q) (void)hipFree(q);
         if (partials) (void)hipFree(partials);
         if (dloss) (void)hipFree(dloss);
+        if (wpart) (void)hipFree(wpart);
         act = gb[0] = gb[1] = wt = nullptr;
         partials = dloss = nullptr;
+        wpart = nullptr;
         cap = 0;
         size_t tot = 0;
         int cmax = 0;
@@ -67,7 +70,8 @@ struct lbmix_net {
             (rc = hip(hipMalloc((void **)&gb[1], (size_t)cmax * N * sizeof(float)), "hipMalloc(net)")) ||
             (rc = hip(hipMalloc((void **)&wt, (size_t)NET_MAXC * NET_MAXC * NET_K * sizeof(float)), "hipMalloc(net)")) ||
             (rc = hip(hipMalloc((void **)&partials, ((N + 255) / 256 + 1) * sizeof(double)), "hipMalloc(net)")) ||
-            (rc = hip(hipMalloc((void **)&dloss, sizeof(double)), "hipMalloc(net)")))
+            (rc = hip(hipMalloc((void **)&dloss, sizeof(double)), "hipMalloc(net)")) ||
+            (rc = hip(hipMalloc((void **)&wpart, conv3_wgrad_workspace((uint32_t)N) * sizeof(float)), "hipMalloc(net)")))
             return rc;
         cap = N;
         return LBMIX_OK;
@@ -143,7 +147,8 @@ int net_gradient(lbmix_net *net, const float *x, const float *t, uint32_t nx, ui
         const float *out = net->act + net->act_offset(l, N);
         ConvArgs a = net->conv(l, in, nullptr, nx, ny, nz, zwalls);
         if (a.relu && (rc = net->hip(launch_relu_mask(g, out, (uint32_t)(a.cout * N), stream), "relu_mask"))) return rc;
-        if ((rc = net->hip(launch_conv3_wgrad(a, g, net->g + net->woff[l], net->g + net->boff[l], stream), "wgrad")))
+        if ((rc = net->hip(launch_conv3_wgrad(a, g, net->g + net->woff[l], net->g + net->boff[l], net->wpart, stream),
+                           "wgrad")))
             return rc;
         if (l == 0) break;
         // gradient of the layer's input: the transposed convolution of g
@@ -304,6 +309,7 @@ void lbmix_net_destroy(lbmix_net *net) {
         if (q) (void)hipFree(q);
     if (net->partials) (void)hipFree(net->partials);
     if (net->dloss) (void)hipFree(net->dloss);
+    if (net->wpart) (void)hipFree(net->wpart);
     delete net;
 }
 
