@@ -289,7 +289,7 @@ def bench_precision_large(args):
         a_s = float(((j0[1] + j1[1]) * np.sin(kx * ax)[None, None, :]).sum())
         return a_m, a_s
 
-    for st, sr in [("f64", None), ("f32s", None), ("f16s", True), ("bf16s", True), ("f32", None)]:
+    for st, sr in [("f64", None), ("f32s", None), ("f32s", True), ("f16s", True), ("bf16s", True), ("f32", None)]:
         lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
         lat.step(t1)
         a1 = amps(lat)
