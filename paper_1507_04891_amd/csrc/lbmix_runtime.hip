@@ -1015,7 +1015,9 @@ int validate_start(lbmix_ctx *c) {
         return c->fail(LBMIX_EINVAL, "the pair drag matrix was set for %d species, the lattice has %d", c->pair_ns, c->ns);
     if (c->forcing == 1 && c->pair_ns >= 3)
         return c->fail(LBMIX_EINVAL, "the Guo-type forcing variant has one drag frequency; it excludes a pair drag matrix");
-    if (c->forcing == 1 && c->pair_ns == 0 && c->drag_from_sc && !(c->omega_drag() < 2.0))
+    bool context_drag_used = false;   // by a channel without a drag of its own
+    for (int ch = 0; ch < c->nch; ++ch) context_drag_used = context_drag_used || !(c->ch_tau_d[ch] > 0.0);
+    if (c->forcing == 1 && c->pair_ns == 0 && c->drag_from_sc && context_drag_used && !(c->omega_drag() < 2.0))
         return c->fail(LBMIX_EINVAL, "with the Guo-type variant, Sc = %g needs tau_visc > 1/2 + Sc / 2", c->sc);
     for (int ch = 0; c->pair_ns && ch < c->nch; ++ch)
         if (c->ch_tau_d[ch] > 0.0)

@@ -127,3 +127,19 @@ def test_guo_checkpoint_and_graph(P):
     for s in range(w.nspecies):
         np.testing.assert_array_equal(a.populations(s), b.populations(s))
         np.testing.assert_array_equal(a.populations(s), g.populations(s))
+
+
+def test_guo_channel_stack_matches_each_channel(P, oracle_mod):
+    """A stack of four slit channels (own drag and wall charge, lateral charge waves) under the
+    Guo-type variant: every channel follows its own oracle slit at the FP64 bar."""
+    from test_gpu_parity import SMALL_STACK, ChannelView, check_potential as chk
+    st = WL.channel_stack(**SMALL_STACK)
+    lat = P.from_workload(st, storage="f64", poisson=dict(method="direct"), forcing="guo")
+    lat.step(25)
+    for c in range(len(st.widths)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="direct", forcing="guo")
+        o.step(25)
+        view = ChannelView(lat, st.planes(c), 3)
+        compare_fp64(view, o, wc)
+        chk(view.potential(), o.potential(), wc)

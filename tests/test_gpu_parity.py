@@ -782,3 +782,34 @@ def test_fp32_stochastic_rounding_is_reproducible(P):
     assert not np.array_equal(a.populations(0), c.populations(0))
     with pytest.raises(P.LbmixError):
         a.set_rounding(False)
+
+
+def test_fp32_stochastic_rounding_channels_and_pair_drag(P, oracle_mod):
+    """Stochastically rounded FP32 on a channel stack (each channel against its own oracle
+    slit) and with a pair drag matrix on a ternary under a field, to the FP32 bar."""
+    st = WL.channel_stack(**SMALL_STACK)
+    lat = P.from_workload(st, storage="f32s", stochastic=True, seed=9, poisson=dict(method="direct"))
+    lat.step(20)
+    for c in range(len(st.widths)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="direct")
+        o.step(20)
+        view = ChannelView(lat, st.planes(c), 3)
+        m = fluid(wc)
+        for s in range(3):
+            ng, _ = view.moments(s)
+            no, _ = o.moments(s)
+            assert rel_max(ng, no, m) <= 1e-5, (c, s)
+            assert rel_to_deviation(ng, no, wc.rho0[s], m) <= 1e-3, (c, s)
+    w = WL.random_state(20, 6, 8, 3, seed=21, rho0=[0.6, 0.25, 0.15], valence=[0, 1, -1], bjerrum=0.0,
+                        E=(2e-3, -1e-3, 5e-4), dn=0.05, du=0.02)
+    taus = pair_taus(3, 5)
+    lat = P.from_workload(w, storage="f32s", stochastic=True, seed=9, drag_pairs=taus)
+    o = oracle_for(oracle_mod, w, drag_pairs=taus)
+    lat.step(20)
+    o.step(20)
+    for s in range(3):
+        ng, _ = lat.moments(s)
+        no, _ = o.moments(s)
+        assert rel_max(ng, no) <= 1e-5, s
+        assert rel_to_deviation(ng, no, w.rho0[s]) <= 1e-3, s
