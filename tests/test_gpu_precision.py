@@ -148,3 +148,29 @@ def test_sixteen_bit_parity_with_oracle(P, oracle_mod, storage, eps):
         err = np.abs(lat.populations(s) - fo).max()
         assert err <= 2 * k * eps * dev, (storage, s, err, dev)
         assert err > 0.0
+
+
+@pytest.mark.parametrize("storage,eps", [("f16s", 2.0 ** -11), ("bf16s", 2.0 ** -8)])
+def test_sixteen_bit_guo_and_pair_drag_with_oracle(P, oracle_mod, storage, eps):
+    """The 16-bit forms under the Guo-type forcing (binary) and with a pair drag matrix
+    (ternary under a field), against the oracle with the same bound: after k steps within
+    2 k eps of the largest deviation of any species (the drag couples their rounding)."""
+    from parity_util import W as WQ, oracle_for
+    from test_gpu_parity import pair_taus
+    k = 8
+    w = WL.binary_multimode(n=32, amp=1e-2, shear=1e-2, sc=10.0, seed=5)
+    cases = [(w, dict(forcing="guo"), dict(forcing="guo"))]
+    w3 = WL.random_state(24, 8, 8, 3, seed=21, rho0=[0.6, 0.25, 0.15], valence=[0, 1, -1], bjerrum=0.0,
+                         E=(2e-3, -1e-3, 5e-4), dn=0.05, du=0.02)
+    taus = pair_taus(3, 5)
+    cases.append((w3, dict(drag_pairs=taus), dict(drag_pairs=taus)))
+    for wl, gpu_kw, ora_kw in cases:
+        lat = P.from_workload(wl, storage=storage, seed=3, **gpu_kw)
+        o = oracle_for(oracle_mod, wl, **ora_kw)
+        lat.step(k)
+        o.step(k)
+        dev = max(np.abs(o.populations(s) - (WQ * wl.rho0[s])[:, None, None, None]).max()
+                  for s in range(wl.nspecies))
+        for s in range(wl.nspecies):
+            err = np.abs(lat.populations(s) - o.populations(s)).max()
+            assert err <= 2 * k * eps * dev, (storage, gpu_kw.keys(), s, err, dev)
