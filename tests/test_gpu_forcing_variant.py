@@ -47,10 +47,12 @@ def test_guo_fp64_matches_oracle(P, oracle_mod, name):
         check_potential(lat.potential(), o.potential(), w)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f32s"])
+@pytest.mark.parametrize("storage", ["f32", "f32s", "f32s:sr"])
 def test_guo_fp32_matches_oracle(P, oracle_mod, storage):
     w, poisson = case("slit_charged")
-    lat = P.from_workload(w, storage=storage, poisson=poisson, forcing="guo")
+    sr = storage.endswith(":sr")
+    storage = storage.split(":")[0]
+    lat = P.from_workload(w, storage=storage, poisson=poisson, forcing="guo", stochastic=True if sr else None, seed=2)
     o = oracle_for(oracle_mod, w, forcing="guo")
     lat.step(20)
     o.step(20)

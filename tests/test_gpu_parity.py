@@ -813,3 +813,23 @@ def test_fp32_stochastic_rounding_channels_and_pair_drag(P, oracle_mod):
         no, _ = o.moments(s)
         assert rel_max(ng, no) <= 1e-5, s
         assert rel_to_deviation(ng, no, w.rho0[s]) <= 1e-3, s
+
+
+def test_channel_stack_checkpoint_restart_is_bitwise(P):
+    """A channel stack (per-channel drag and wall charges) saved mid-run and restored into a
+    fresh context continues bitwise, potential included."""
+    st = WL.channel_stack(**SMALL_STACK)
+    a = P.from_workload(st, storage="f32s", poisson=dict(method="direct"))
+    a.step(12)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "ck.bin")
+        a.save(path)
+        a.step(9)
+        b = P.Lattice(st.nx, st.ny, geometry="channels", storage="f32s", widths=st.widths)
+        for s in range(3):
+            b.add_species(st.rho0[s], st.valence[s])
+        b.load(path)
+        b.step(9)
+    for s in range(3):
+        np.testing.assert_array_equal(a.populations(s), b.populations(s))
+    np.testing.assert_array_equal(a.potential(), b.potential())
