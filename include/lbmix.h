@@ -31,9 +31,10 @@
  *     pre-collision populations at time t;
  *   - readings of the paper applied here: the drag acts on the mid-step species velocities
  *     u^alpha + a^alpha / 2, where a^alpha = z^alpha (E_ext - v_T^2 grad psi~) is the field
- *     acceleration; grad psi~ by central differences, ghost value psi~ + 4 pi l_B sigma
- *     across a wall; the collision at step t uses the potential solved from the charge
- *     density of step t-1 (before the first step: of step 0).
+ *     acceleration (lbmix_set_forcing selects a Guo-type alternative); grad psi~ by central
+ *     differences, ghost value psi~ + 4 pi l_B sigma across a wall; the collision at step t
+ *     uses the potential solved from the charge density of step t-1 (before the first step:
+ *     of step 0).
  *
  * Status codes: every call returns LBMIX_OK (0) or a negative code; no C++ exception
  * crosses the ABI.  lbmix_last_error() returns a text for the last failure of a context.
@@ -68,7 +69,8 @@ enum lbmix_forcing { LBMIX_FORCING_PAPER = 0, LBMIX_FORCING_GUO = 1 };
 /* Population storage.  F64 and F32 store f.  The SHIFTED forms store the deviation
  * f_p - w_p rho0 (rho0 = the species' rest density given to lbmix_add_species), in FP32,
  * or in BF16 / FP16 times a power-of-two scale per species and direction; the collision
- * arithmetic is FP64 for F64 and FP32 for all other forms.  Mass totals and the Poisson
+ * arithmetic is FP64 for F64 and FP32 for all other forms, except that the FP32 forms with
+ * stochastic rounding (lbmix_set_rounding) collide in FP64.  Mass totals and the Poisson
  * solve are FP64 in every form. */
 enum lbmix_storage {
     LBMIX_F64 = 0,
