@@ -1,10 +1,10 @@
 // gfx950 kernels of the learned warm start of the Poisson solve: 3 x 3 x 3 convolutions with
 // bias and ReLU (forward, transposed for the input gradient, weight gradient), mean-square
 // loss, Adam, and the glue between the FP64 potential and the FP32 network.  The network
-// works on lattices of a few hundred thousand nodes with at most 16 channels.  The 16 -> 16
-// convolutions run on the FP32 matrix cores; the others use one thread per node that
-// accumulates every output channel, with the weights of the layer in LDS (read by all lanes
-// at once).
+// works on lattices of a few hundred thousand nodes with at most 16 channels.  Convolutions
+// with at least 16 channel pairs run on the FP32 matrix cores (channels zero-padded to 16);
+// smaller ones use one thread per node that accumulates every output channel, with the
+// weights of the layer in LDS (read by all lanes at once).
 #include "lbmix_net.h"
 
 namespace lbmix {
@@ -59,8 +59,8 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
     }
 }
 
-// The same convolution for 16 input and 16 output channels on the FP32 matrix cores: a
-// dense contraction y[co][v] = sum_{k, ci} w[co][ci][k] x[ci][v + offset_k] with K = 27 x 16.
+// The same convolution on the FP32 matrix cores, channels zero-padded to 16: a dense
+// contraction y[co][v] = sum_{k, ci} w[co][ci][k] x[ci][v + offset_k] with K = 27 x 16.
 // Each wave computes tiles of 16 consecutive nodes (one 16 x 16 v_mfma_f32_16x16x4f32 output,
 // rows co, columns the nodes) in 108 steps of 4 (tap k, channels 4c..4c+3): lane l supplies
 // w[co = l mod 16][4c + l/16][k] from LDS and x[4c + l/16][neighbour of node l mod 16].  The
@@ -69,8 +69,11 @@ typedef float f32x4m __attribute__((ext_vector_type(4)));
 constexpr int MFMA_C = 16;
 
 __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
-    __shared__ float sw[MFMA_C * MFMA_C * NET_K];
-    for (int i = threadIdx.x; i < MFMA_C * MFMA_C * NET_K; i += NET_BLOCK) sw[i] = a.w[i];
+    __shared__ float sw[MFMA_C * MFMA_C * NET_K];   // [co][ci][k], zero beyond cout, cin
+    for (int i = threadIdx.x; i < MFMA_C * MFMA_C * NET_K; i += NET_BLOCK) {
+        const int co = i / (MFMA_C * NET_K), ci = (i / NET_K) % MFMA_C, k = i % NET_K;
+        sw[i] = (co < a.cout && ci < a.cin) ? a.w[(co * a.cin + ci) * NET_K + k] : 0.0f;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const uint32_t ntiles = (a.N + 15) / 16;
@@ -78,7 +81,7 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
     const uint32_t nwaves = gridDim.x * (NET_BLOCK / 64);
     float bias[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) bias[r] = a.b ? a.b[4 * lk + r] : 0.0f;
+    for (int r = 0; r < 4; ++r) bias[r] = (a.b && 4 * lk + r < a.cout) ? a.b[4 * lk + r] : 0.0f;
     for (uint32_t t = wave; t < ntiles; t += nwaves) {
         const uint32_t v = t * 16 + li;           // the node of this lane's column
         const bool live = v < a.N;
@@ -92,7 +95,7 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int ci = 4 * c + lk;
-                bx[c] = nb >= 0 ? a.x[(size_t)ci * a.N + nb] : 0.0f;
+                bx[c] = (nb >= 0 && ci < a.cin) ? a.x[(size_t)ci * a.N + nb] : 0.0f;
                 aw[c] = sw[(li * MFMA_C + ci) * NET_K + k];
             }
 #pragma unroll
@@ -102,13 +105,13 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float o = acc[r];
-                a.y[(size_t)(4 * lk + r) * a.N + v] = (a.relu && o < 0.0f) ? 0.0f : o;
+                if (4 * lk + r < a.cout) a.y[(size_t)(4 * lk + r) * a.N + v] = (a.relu && o < 0.0f) ? 0.0f : o;
             }
         }
     }
 }
 
-// Weight gradients of a 16 -> 16 layer on the FP32 matrix cores: for every tap k the 16 x 16
+// Weight gradients on the FP32 matrix cores, channels zero-padded to 16: for every tap k the 16 x 16
 // product gw_k[co][ci] = sum_v g[co][v] x[ci][v + offset_k] is a contraction over nodes.  Each
 // wave takes WG_CHUNK consecutive nodes, four per step (lane l: node l / 16 of the step,
 // channel l mod 16 of both operands), and keeps the 27 tap products in its registers, plus a
@@ -130,11 +133,11 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_mfma(const ConvArgs a, 
         const bool live = v < a.N;
         const uint32_t vv = live ? v : 0;
         const uint32_t x = vv % a.nx, y = (vv / a.nx) % a.ny, z = vv / (a.nx * a.ny);
-        const float gv = live ? g[(size_t)li * a.N + v] : 0.0f;   // A: g[co = li][node lk]
+        const float gv = (live && li < a.cout) ? g[(size_t)li * a.N + v] : 0.0f;   // A: g[co = li][node lk]
 #pragma unroll
         for (int k = 0; k < NET_K; ++k) {
             const int64_t nb = live ? tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls) : -1;
-            const float xv = nb >= 0 ? a.x[(size_t)li * a.N + nb] : 0.0f;   // B: x[ci = li] at node lk
+            const float xv = (nb >= 0 && li < a.cin) ? a.x[(size_t)li * a.N + nb] : 0.0f;   // B: x[ci = li] at node lk
             acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, xv, acc[k], 0, 0, 0);
         }
         acc[NET_K] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, live ? 1.0f : 0.0f, acc[NET_K], 0, 0, 0);
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_mfma(const ConvArgs a, 
 
 // gw[co][ci][k] = sum over waves of part[wave][k][co][ci], and gb[co] from the bias slot
 // (column 0): one work-group per weight, FP64, strided per thread and then a fixed tree.
-__global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_sum(const float *part, uint32_t nwaves, float *gw,
-                                                              float *gb) {
+__global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_sum(const float *part, uint32_t nwaves, int cout, int cin,
+                                                              float *gw, float *gb) {
     __shared__ double red[NET_BLOCK];
     const uint32_t i = blockIdx.x;   // (slot, co, ci)
     double s = 0.0;
@@ -161,10 +164,10 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_sum(const float *part, 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const uint32_t k = i / (MFMA_C * MFMA_C), co = (i / MFMA_C) % MFMA_C, ci = i % MFMA_C;
-        if (k < (uint32_t)NET_K)
-            gw[(co * MFMA_C + ci) * NET_K + k] = (float)red[0];
-        else if (ci == 0)
+        const int k = (int)(i / (MFMA_C * MFMA_C)), co = (int)(i / MFMA_C) % MFMA_C, ci = (int)(i % MFMA_C);
+        if (k < NET_K && co < cout && ci < cin)
+            gw[(co * cin + ci) * NET_K + k] = (float)red[0];
+        else if (k == NET_K && ci == 0 && co < cout)
             gb[co] = (float)red[0];
     }
 }
@@ -286,7 +289,7 @@ static dim3 grid_of(uint32_t n) { return dim3((n + NET_BLOCK - 1) / NET_BLOCK); 
 
 hipError_t launch_conv3(const ConvArgs &a, hipStream_t stream) {
     if (a.cin < 1 || a.cin > NET_MAXC || a.cout < 1 || a.cout > NET_MAXC) return hipErrorInvalidValue;
-    if (a.cin == MFMA_C && a.cout == MFMA_C) {
+    if (a.cin * a.cout >= 16) {   // the 4 -> 16, 16 -> 16 and 16 -> 1 layers
         // four 16-node tiles per work-group and pass; about two passes per wave
         const uint32_t tiles = (a.N + 15) / 16;
         uint32_t blocks = (tiles + 7) / 8;
@@ -316,11 +319,11 @@ size_t conv3_wgrad_workspace(uint32_t N) {
 
 hipError_t launch_conv3_wgrad(const ConvArgs &a, const float *g, float *gw, float *gb, float *part,
                               hipStream_t stream) {
-    if (a.cin == MFMA_C && a.cout == MFMA_C && part) {
+    if (a.cin * a.cout >= 16 && part) {
         const uint32_t blocks = (a.N + WG_CHUNK * 4 - 1) / (WG_CHUNK * 4);   // four waves each
         hipLaunchKernelGGL(conv3_wgrad_mfma, dim3(blocks), dim3(NET_BLOCK), 0, stream, a, g, part);
         hipLaunchKernelGGL(conv3_wgrad_sum, dim3(WG_SLOTS * MFMA_C * MFMA_C), dim3(NET_BLOCK), 0, stream, part,
-                           blocks * 4, gw, gb);
+                           blocks * 4, a.cout, a.cin, gw, gb);
         return hipGetLastError();
     }
     const uint32_t blocks = (uint32_t)(a.cout * (a.cin * NET_K + 1));
