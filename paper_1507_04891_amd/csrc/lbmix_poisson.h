@@ -112,10 +112,12 @@ hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uin
 // of `in`, or, when `q` is given, of b = -K (q + lump_z) (lumps from planes, which may be
 // null).  Inverse: out = Ty^T P Tx.
 constexpr uint32_t SPEC_XY_MAX = 4096;
+constexpr uint32_t SPEC_PAD = 64;    // padded extent of the bases below (row stride SPEC_PAD + 1)
 struct SpecXY {
     const double *in, *q;
     double *out;
     const double *tx, *ty;           // nx x nx and ny x ny bases (row k = basis vector k)
+    const double *txp, *typ;         // the same zero-padded to 64 x 65 (required for planes over 32 wide)
     const PlaneInfo *planes;
     double K;
     uint32_t nx, ny, nplanes;

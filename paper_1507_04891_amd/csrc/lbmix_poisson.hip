@@ -670,11 +670,15 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
 
 // Half of the transform of one plane up to 64 x 64 per work-group, for lattices with fewer
 // planes than compute units: the forward transform splits the output columns kx, the inverse
-// the output rows y, and each half needs the whole plane but only half of one basis.
+// the output rows y, and each half needs the whole plane.  The bases are read by the
+// matrix-core steps straight from their zero-padded copies in device memory (they stay in
+// the caches), so only the plane is staged in LDS.
 template <bool FWD>
 __global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
     constexpr int PM = 64, LD = PM + 1, HM = 32, NT = 256, BATCH = 8;
-    __shared__ double P[PM * LD], Tx[PM * LD], Ty[PM * LD], R[PM * (HM + 1)];
+    static_assert(PM == (int)SPEC_PAD, "padded bases");
+    __shared__ double P[PM * LD], R[PM * (HM + 1)];
+    const double *Tx = a.txp, *Ty = a.typ;
     const int nx = a.nx, ny = a.ny;
     const uint32_t z = blockIdx.x >> 1;
     const int h = blockIdx.x & 1;
@@ -682,31 +686,24 @@ __global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
     const bool from_q = FWD && a.q;
     const double *src = from_q ? a.q : a.in;
     const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
-    // forward: the rows kx of the half of Tx (as Tx[0..32)), all of Ty; inverse: both bases
-    constexpr int TXR = FWD ? HM : PM;
 #pragma unroll
     for (int b0 = 0; b0 < PM * PM / NT; b0 += BATCH) {
-        double vp[BATCH], vx[BATCH], vy[BATCH];
+        double vp[BATCH];
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
-            const int rx = FWD ? HM * h + r : r;
             vp[u] = (r < ny && c < nx) ? src[base + r * nx + c] : 0.0;
-            vy[u] = (r < ny && c < ny) ? a.ty[r * ny + c] : 0.0;
-            vx[u] = (r < TXR && rx < nx && c < nx) ? a.tx[rx * nx + c] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < BATCH; ++u) {
             const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
             P[r * LD + c] = (from_q && r < ny && c < nx) ? -a.K * (vp[u] + lump) : vp[u];
-            Ty[r * LD + c] = vy[u];
-            Tx[r * LD + c] = vx[u];
         }
     }
     __syncthreads();
     if (FWD) {
         // R[y][kx'] = sum_x P[y][x] Tx[32 h + kx'][x];  P[ky][kx'] = sum_y Ty[ky][y] R[y][kx']
-        mfma_product<PM, HM, PM>(P, LD, 1, Tx, 1, LD, R, HM + 1);
+        mfma_product<PM, HM, PM>(P, LD, 1, Tx + HM * h * LD, 1, LD, R, HM + 1);
         __syncthreads();
         mfma_product<PM, HM, PM>(Ty, LD, 1, R, HM + 1, 1, P, LD);
         __syncthreads();
@@ -872,7 +869,7 @@ hipError_t launch_shift_planes(double *psi, uint32_t nxy, uint32_t N, const Plan
 hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     if (a.nx > 64 || a.ny > 64) return hipErrorInvalidValue;
     const bool small = a.nx <= 32 && a.ny <= 32;
-    if (!small && a.nplanes <= 256) {   // too few planes to give every compute unit a whole one
+    if (!small && a.nplanes <= 256 && a.txp && a.typ) {   // too few planes to give every compute unit a whole one
         if (forward)
             hipLaunchKernelGGL((spec_xy_half<true>), dim3(2 * a.nplanes), dim3(256), 0, stream, a);
         else

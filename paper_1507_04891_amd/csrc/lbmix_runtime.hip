@@ -108,6 +108,7 @@ struct lbmix_ctx {
     // direct solve: orthonormal bases of the periodic axes, their eigenvalues, the inverse
     // pivots of the z systems (slit), segment bounds, two work arrays
     double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
+    double *sp_txp = nullptr, *sp_typ = nullptr;   // x and y bases zero-padded to 64 x 65 (planes up to 64)
     double *sp_piv = nullptr, *sp_a = nullptr, *sp_b = nullptr;
     uint32_t *sp_seg = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
@@ -639,6 +640,15 @@ int spec_build(lbmix_ctx *c) {
     periodic_basis(c->ny, ty, muy);
     int rc;
     if ((rc = upload(c, &c->sp_tx, tx)) || (rc = upload(c, &c->sp_ty, ty))) return rc;
+    if (c->nx <= (int)SPEC_PAD && c->ny <= (int)SPEC_PAD) {
+        auto pad = [](const std::vector<double> &b, int n) {
+            std::vector<double> p((size_t)SPEC_PAD * (SPEC_PAD + 1), 0.0);
+            for (int r = 0; r < n; ++r)
+                for (int k = 0; k < n; ++k) p[(size_t)r * (SPEC_PAD + 1) + k] = b[(size_t)r * n + k];
+            return p;
+        };
+        if ((rc = upload(c, &c->sp_txp, pad(tx, c->nx))) || (rc = upload(c, &c->sp_typ, pad(ty, c->ny)))) return rc;
+    }
     std::vector<double> mu(mux);
     mu.insert(mu.end(), muy.begin(), muy.end());
     if (c->slit) {
@@ -713,7 +723,8 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     double *a = c->sp_a, *b = c->sp_b;
     const bool in_lds = c->nx <= 64 && c->ny <= 64;
     SpecXY xy{};
-    xy.tx = c->sp_tx; xy.ty = c->sp_ty; xy.planes = c->slit ? c->d_planes : nullptr;
+    xy.tx = c->sp_tx; xy.ty = c->sp_ty; xy.txp = c->sp_txp; xy.typ = c->sp_typ;
+    xy.planes = c->slit ? c->d_planes : nullptr;
     xy.K = 4.0 * kPi * c->lB; xy.nx = c->nx; xy.ny = c->ny; xy.nplanes = c->nzf;
     if (in_lds) {
         xy.q = c->q; xy.in = nullptr; xy.out = a;
@@ -1888,7 +1899,7 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (void *p : {(void *)c->ws_r, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
                         (void *)c->ws_t, (void *)c->ws_mask})
             if (p) (void)hipFree(p);
-        for (double *p : {c->sp_tx, c->sp_ty, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
+        for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
         if (c->step_dev) (void)hipFree(c->step_dev);
