@@ -603,34 +603,21 @@ __device__ void mfma_product(const double *A, int ar, int ak, const double *B, i
     }
 }
 
-// Transform of planes along x and y in LDS: PM = 64 (256 threads, 133 KB of LDS) for planes
-// up to 64 x 64, PM = 32 (one wave, 34 KB, four work-groups per compute unit) for planes up to
-// 32 x 32.  A work-group stages the two bases once and then transforms the planes z =
-// blockIdx.x, blockIdx.x + gridDim.x, ...
+// Transform of planes along x and y: PM = 64 (256 threads, 67 KB of LDS) for planes up to
+// 64 x 64, PM = 32 (one wave, 17 KB) for planes up to 32 x 32.  A work-group transforms the
+// planes z = blockIdx.x, blockIdx.x + gridDim.x, ..., each staged in LDS; the matrix-core
+// steps read the bases from their zero-padded copies in device memory, which stay in the
+// caches.
 template <bool FWD, int PM>
 __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
-    constexpr int LD = PM + 1;   // row stride of the LDS arrays
-    __shared__ double P[PM * LD], R[PM * LD], Tx[PM * LD], Ty[PM * LD];
+    constexpr int LD = PM + 1;              // row stride of the LDS arrays
+    constexpr int BLD = SPEC_PAD + 1;       // row stride of the padded bases
+    __shared__ double P[PM * LD], R[PM * LD];
+    const double *Tx = a.txp, *Ty = a.typ;   // read by the matrix-core steps from the caches
     const int nx = a.nx, ny = a.ny;
-    // bases and planes, zero-padded to PM x PM (the padding contributes nothing); all loads of
-    // a thread are issued before its LDS stores, in batches of eight elements
+    // planes zero-padded to PM x PM (the padding contributes nothing); all loads of a thread
+    // are issued before its LDS stores, in batches of eight elements
     constexpr int NT = PM == 64 ? 256 : 64, PER = PM * PM / NT, BATCH = 8;
-#pragma unroll
-    for (int b0 = 0; b0 < PER; b0 += BATCH) {
-        double vx[BATCH], vy[BATCH];
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
-            vx[u] = (r < nx && c < nx) ? a.tx[r * nx + c] : 0.0;
-            vy[u] = (r < ny && c < ny) ? a.ty[r * ny + c] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < BATCH; ++u) {
-            const int k = threadIdx.x + (b0 + u) * NT, r = k / PM, c = k % PM;
-            Tx[r * LD + c] = vx[u];
-            Ty[r * LD + c] = vy[u];
-        }
-    }
     const bool from_q = FWD && a.q;
     const double *src = from_q ? a.q : a.in;
     for (uint32_t z = blockIdx.x; z < a.nplanes; z += gridDim.x) {
@@ -653,14 +640,14 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
         __syncthreads();
         if (FWD) {
             // R[y][kx] = sum_x P[y][x] Tx[kx][x];  P[ky][kx] = sum_y Ty[ky][y] R[y][kx]
-            mfma_product<PM, PM, PM>(P, LD, 1, Tx, 1, LD, R, LD);
+            mfma_product<PM, PM, PM>(P, LD, 1, Tx, 1, BLD, R, LD);
             __syncthreads();
-            mfma_product<PM, PM, PM>(Ty, LD, 1, R, LD, 1, P, LD);
+            mfma_product<PM, PM, PM>(Ty, BLD, 1, R, LD, 1, P, LD);
         } else {
             // R[y][kx] = sum_ky Ty[ky][y] P[ky][kx];  P[y][x] = sum_kx R[y][kx] Tx[kx][x]
-            mfma_product<PM, PM, PM>(Ty, 1, LD, P, LD, 1, R, LD);
+            mfma_product<PM, PM, PM>(Ty, 1, BLD, P, LD, 1, R, LD);
             __syncthreads();
-            mfma_product<PM, PM, PM>(R, LD, 1, Tx, LD, 1, P, LD);
+            mfma_product<PM, PM, PM>(R, LD, 1, Tx, BLD, 1, P, LD);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
@@ -876,8 +863,9 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
             hipLaunchKernelGGL((spec_xy_half<false>), dim3(2 * a.nplanes), dim3(256), 0, stream, a);
         return hipGetLastError();
     }
-    // as many work-groups as fit on the chip at once (LDS-bound: 4 or 1 per compute unit)
-    const uint32_t fit = small ? 4 * 256 : 256;
+    if (!a.txp || !a.typ) return hipErrorInvalidValue;
+    // as many work-groups as fit on the chip at once (LDS-bound: 9 or 2 per compute unit)
+    const uint32_t fit = small ? 8 * 256 : 2 * 256;
     const dim3 g(a.nplanes < fit ? a.nplanes : fit);
     if (small) {
         if (forward)
