@@ -103,9 +103,11 @@ struct SpecGemm {
 // coalesced load pattern only.
 hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipStream_t stream);
 // Tridiagonal solves along z for every mode (nmodes per plane) and every segment of planes
-// [seg[s], seg[s+1]), s < nseg; piv = inverse pivots [plane][mode].
-hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
-                            uint32_t nseg, hipStream_t stream);
+// [seg[s], seg[s+1]), s < nseg.  Inverse pivots: piv[k][mode] for plane k of a segment
+// before its last plane (the same for every segment; as many rows as the longest segment
+// less one), piv_end[s][mode] for the last plane of segment s.
+hipError_t launch_tridiag_z(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
+                            const uint32_t *seg, uint32_t nseg, hipStream_t stream);
 // Per-plane transform along x and y of planes of at most SPEC_XY_MAX nodes (nx, ny <= 64),
 // in LDS on the FP64 matrix cores: each work-group takes several planes, or half a plane
 // when there are fewer planes than compute units.  Forward: out = Ty P Tx^T with P the plane
@@ -127,7 +129,7 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream);
 // the longest segment, at most TRI_LDS_MAX.  Both forms also remove the segment mean of
 // mode 0 from the right-hand side first (the projection onto consistent data of each channel).
 constexpr uint32_t TRI_LDS_MAX = 256;
-hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
+hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream);
 // a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
 hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,

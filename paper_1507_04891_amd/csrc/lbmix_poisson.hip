@@ -446,11 +446,17 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
 
 // One thread per (mode, segment): rows psi_{z-1} - (2 + mu) psi_z + psi_{z+1} = b_z of a
 // segment of planes with zero-flux ends, by elimination with the precomputed inverse
-// pivots piv ([plane][mode]; piv_z = 1 / (d_z - piv_{z-1})).  The singular mode (mu = 0,
-// index 0) has its last pivot stored as 0, which fixes psi = 0 on the segment's last plane;
-// its segment mean is removed afterwards.
-__global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes,
-                                                const uint32_t *seg) {
+// pivots p_k = 1 / (d_k - p_{k-1}) of plane k of the segment.  Every segment shares the
+// pivots before its last plane (piv, [k][mode]); only the last differs (piv_end,
+// [segment][mode]).  The singular mode (mu = 0, index 0) has its last pivot stored as 0,
+// which fixes psi = 0 on the segment's last plane; its segment mean is removed afterwards.
+__device__ __forceinline__ double seg_pivot(const double *piv, const double *piv_end, uint32_t k, uint32_t L,
+                                            uint32_t s, uint32_t mode, uint32_t nmodes) {
+    return k + 1 == L ? piv_end[(size_t)s * nmodes + mode] : piv[(size_t)k * nmodes + mode];
+}
+
+__global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *piv, const double *piv_end,
+                                                double *out, uint32_t nmodes, const uint32_t *seg) {
     const uint32_t mode = blockIdx.x * 64 + threadIdx.x;
     if (mode >= nmodes) return;
     const uint32_t z0 = seg[blockIdx.y], z1 = seg[blockIdx.y + 1];
@@ -463,14 +469,14 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 #pragma unroll 8
     for (uint32_t z = z0; z < z1; ++z) {
         const size_t i = (size_t)z * nmodes + mode;
-        r = (b[i] - bm - r) * piv[i];
+        r = (b[i] - bm - r) * seg_pivot(piv, piv_end, z - z0, z1 - z0, blockIdx.y, mode, nmodes);
         out[i] = r;
     }
     double x = 0.0;
 #pragma unroll 8
     for (uint32_t z = z1; z-- > z0;) {
         const size_t i = (size_t)z * nmodes + mode;
-        x = out[i] - piv[i] * x;
+        x = out[i] - seg_pivot(piv, piv_end, z - z0, z1 - z0, blockIdx.y, mode, nmodes) * x;
         out[i] = x;
     }
     if (mode == 0) {
@@ -505,8 +511,8 @@ __device__ double column0_mean(const double *s, uint32_t L, double *red) {
 }
 
 template <uint32_t MODES>
-__global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes,
-                                                   const uint32_t *seg) {
+__global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, const double *piv_end,
+                                                   double *out, uint32_t nmodes, const uint32_t *seg) {
     constexpr uint32_t CELLS = MODES * TRI_LDS_MAX < TRI_CELLS ? MODES * TRI_LDS_MAX : TRI_CELLS;
     __shared__ double sb[CELLS], sp[CELLS];   // [plane][MODES]
     __shared__ double red[4];
@@ -521,7 +527,7 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
             const bool in = k < cells && m0 + m < nmodes;
             const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
             vb[u] = in ? b[i] : 0.0;
-            vp[u] = in ? piv[i] : 0.0;
+            vp[u] = in ? seg_pivot(piv, piv_end, z, L, blockIdx.y, m0 + m, nmodes) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -881,26 +887,27 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag_lds(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
-                              uint32_t nseg, uint32_t longest, hipStream_t stream) {
+hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
+                              const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream) {
     if (longest > TRI_LDS_MAX) return hipErrorInvalidValue;
     // the widest work-groups that still give every compute unit one
     const uint32_t wg64 = (nmodes + 63) / 64 * nseg, wg32 = (nmodes + 31) / 32 * nseg;
     if (longest * 64 <= TRI_CELLS && wg64 >= 256)
-        hipLaunchKernelGGL((tridiag_lds<64>), dim3((nmodes + 63) / 64, nseg), dim3(256), 0, stream, b, piv, out,
-                           nmodes, seg);
+        hipLaunchKernelGGL((tridiag_lds<64>), dim3((nmodes + 63) / 64, nseg), dim3(256), 0, stream, b, piv, piv_end,
+                           out, nmodes, seg);
     else if (wg32 >= 256)
-        hipLaunchKernelGGL((tridiag_lds<32>), dim3((nmodes + 31) / 32, nseg), dim3(256), 0, stream, b, piv, out,
-                           nmodes, seg);
+        hipLaunchKernelGGL((tridiag_lds<32>), dim3((nmodes + 31) / 32, nseg), dim3(256), 0, stream, b, piv, piv_end,
+                           out, nmodes, seg);
     else
-        hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, out,
-                           nmodes, seg);
+        hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, piv_end,
+                           out, nmodes, seg);
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag_z(const double *b, const double *piv, double *out, uint32_t nmodes, const uint32_t *seg,
-                            uint32_t nseg, hipStream_t stream) {
-    hipLaunchKernelGGL(tridiag_z, dim3((nmodes + 63) / 64, nseg), dim3(64), 0, stream, b, piv, out, nmodes, seg);
+hipError_t launch_tridiag_z(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
+                            const uint32_t *seg, uint32_t nseg, hipStream_t stream) {
+    hipLaunchKernelGGL(tridiag_z, dim3((nmodes + 63) / 64, nseg), dim3(64), 0, stream, b, piv, piv_end, out, nmodes,
+                       seg);
     return hipGetLastError();
 }
 

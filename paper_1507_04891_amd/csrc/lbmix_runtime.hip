@@ -109,7 +109,7 @@ struct lbmix_ctx {
     // pivots of the z systems (slit), segment bounds, two work arrays
     double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
     double *sp_txp = nullptr, *sp_typ = nullptr;   // x and y bases zero-padded to 64 x 65 (planes up to 64)
-    double *sp_piv = nullptr, *sp_a = nullptr, *sp_b = nullptr;
+    double *sp_piv = nullptr, *sp_piv_end = nullptr, *sp_a = nullptr, *sp_b = nullptr;
     uint32_t *sp_seg = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
     // state
@@ -653,25 +653,30 @@ int spec_build(lbmix_ctx *c) {
     mu.insert(mu.end(), muy.begin(), muy.end());
     if (c->slit) {
         // zero-flux z in every channel: rows of the z system carry diagonal -(2 + mu),
-        // -(1 + mu) on the two end planes of the channel (-mu for a single plane)
+        // -(1 + mu) on the two end planes of the channel (-mu for a single plane).  The
+        // inverse pivots before the last plane are those of one recurrence from the first
+        // plane, shared by every channel; each channel has its own last pivot.
         const size_t nm = (size_t)c->nx * c->ny;
-        std::vector<double> piv(nm * c->nzf);
-        for (int ch = 0; ch < c->nch; ++ch) {
-            const int z0 = c->ch_first[ch], W = c->ch_width[ch];
-            for (int my = 0; my < c->ny; ++my)
-                for (int mx = 0; mx < c->nx; ++mx) {
-                    const size_t m = (size_t)my * c->nx + mx;
-                    const double mxy = mux[mx] + muy[my];
-                    double prev = 0.0;
-                    for (int k = 0; k < W; ++k) {
-                        const double d = -(2.0 + mxy) + (k == 0 ? 1.0 : 0.0) + (k == W - 1 ? 1.0 : 0.0);
-                        const bool pin = (m == 0 && k == W - 1);
-                        prev = pin ? 0.0 : 1.0 / (d - prev);
-                        piv[(size_t)(z0 + k) * nm + m] = prev;
-                    }
+        int longest = 1;
+        for (int w : c->ch_width) longest = std::max(longest, w);
+        std::vector<double> piv(nm * (size_t)std::max(longest - 1, 1), 0.0), piv_end(nm * c->nch);
+        for (int my = 0; my < c->ny; ++my)
+            for (int mx = 0; mx < c->nx; ++mx) {
+                const size_t m = (size_t)my * c->nx + mx;
+                const double mxy = mux[mx] + muy[my];
+                double prev = 0.0;
+                for (int k = 0; k + 1 < longest; ++k) {
+                    prev = 1.0 / (-(2.0 + mxy) + (k == 0 ? 1.0 : 0.0) - prev);
+                    piv[(size_t)k * nm + m] = prev;
                 }
-        }
-        if ((rc = upload(c, &c->sp_piv, piv))) return rc;
+                for (int ch = 0; ch < c->nch; ++ch) {
+                    const int W = c->ch_width[ch];
+                    const double before = W > 1 ? piv[(size_t)(W - 2) * nm + m] : 0.0;
+                    const double d = -(2.0 + mxy) + 1.0 + (W == 1 ? 1.0 : 0.0);
+                    piv_end[(size_t)ch * nm + m] = m == 0 ? 0.0 : 1.0 / (d - before);
+                }
+            }
+        if ((rc = upload(c, &c->sp_piv, piv)) || (rc = upload(c, &c->sp_piv_end, piv_end))) return rc;
         std::vector<uint32_t> seg(c->nch + 1);
         for (int ch = 0; ch <= c->nch; ++ch) seg[ch] = ch < c->nch ? (uint32_t)c->ch_first[ch] : (uint32_t)c->nzf;
         if ((rc = c->hip(hipMalloc((void **)&c->sp_seg, seg.size() * sizeof(uint32_t)), "hipMalloc(direct solve)")))
@@ -739,10 +744,11 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
         int longest = 0;
         for (int w : c->ch_width) longest = std::max(longest, w);
         if (longest <= (int)TRI_LDS_MAX)
-            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, (uint32_t)longest, c->stream),
+            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, c->sp_piv_end, b, nxy, c->sp_seg, c->nch, (uint32_t)longest,
+                                           c->stream),
                         "tridiag_lds");
         else
-            rc = c->hip(launch_tridiag_z(a, c->sp_piv, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_z");
+            rc = c->hip(launch_tridiag_z(a, c->sp_piv, c->sp_piv_end, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_z");
         if (rc) return rc;
     } else {
         if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, a, b, false, "gemm(z)"))) return rc;
@@ -1899,7 +1905,8 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (void *p : {(void *)c->ws_r, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
                         (void *)c->ws_t, (void *)c->ws_mask})
             if (p) (void)hipFree(p);
-        for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_a, c->sp_b})
+        for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_piv_end, c->sp_a,
+                          c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
         if (c->step_dev) (void)hipFree(c->step_dev);
