@@ -488,8 +488,7 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 }
 
 // The same eliminations with the columns staged in LDS: one work-group of 256 threads per
-// MODES modes of one segment (MODES * planes <= 8192; fewer modes per work-group spread the
-// serial recurrences over more compute units).  All threads stage the right-hand side
+// MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
 // and pivots with coalesced loads, issued sixteen at a time; MODES threads run the recurrences
 // from LDS; all threads write the result back.  The work-group holding mode 0 removes its
 // segment mean before and after the elimination with all threads.
@@ -890,17 +889,12 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
 hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream) {
     if (longest > TRI_LDS_MAX) return hipErrorInvalidValue;
-    // the widest work-groups that still give every compute unit one
-    const uint32_t wg64 = (nmodes + 63) / 64 * nseg, wg32 = (nmodes + 31) / 32 * nseg;
-    if (longest * 64 <= TRI_CELLS && wg64 >= 256)
-        hipLaunchKernelGGL((tridiag_lds<64>), dim3((nmodes + 63) / 64, nseg), dim3(256), 0, stream, b, piv, piv_end,
-                           out, nmodes, seg);
-    else if (wg32 >= 256)
-        hipLaunchKernelGGL((tridiag_lds<32>), dim3((nmodes + 31) / 32, nseg), dim3(256), 0, stream, b, piv, piv_end,
-                           out, nmodes, seg);
-    else
-        hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, piv_end,
-                           out, nmodes, seg);
+    // 16 modes per work-group: 64 KB of LDS, so two work-groups share a compute unit and one
+    // stages its columns while the other runs its recurrences.  On 64 stacked channels of
+    // 32 x 32 planes this took 85 us against 91 (8 modes), 102 (32) and 98 (64, pivots
+    // read from the caches).
+    hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, piv_end, out,
+                       nmodes, seg);
     return hipGetLastError();
 }
 
