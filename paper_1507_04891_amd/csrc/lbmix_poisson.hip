@@ -608,11 +608,11 @@ __device__ void mfma_product(const double *A, int ar, int ak, const double *B, i
     }
 }
 
-// Transform of planes along x and y: PM = 64 (256 threads, 67 KB of LDS) for planes up to
-// 64 x 64, PM = 32 (one wave, 17 KB) for planes up to 32 x 32.  A work-group transforms the
-// planes z = blockIdx.x, blockIdx.x + gridDim.x, ..., each staged in LDS; the matrix-core
-// steps read the bases from their zero-padded copies in device memory, which stay in the
-// caches.
+// Transform of planes along x and y staged in LDS, zero-padded to PM x PM (PM = 64: 256
+// threads, 67 KB of LDS; planes up to 32 x 32 take the register form spec_xy32 instead).  A
+// work-group transforms the planes z = blockIdx.x, blockIdx.x + gridDim.x, ...; the
+// matrix-core steps read the bases from their zero-padded copies in device memory, which
+// stay in the caches.
 template <bool FWD, int PM>
 __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
     constexpr int LD = PM + 1;              // row stride of the LDS arrays
@@ -657,6 +657,91 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
         __syncthreads();
         for (int k = threadIdx.x; k < nx * ny; k += blockDim.x) a.out[base + k] = P[(k / nx) * LD + k % nx];
         __syncthreads();   // P is restaged for the next plane
+    }
+}
+
+// Transform of planes up to 32 x 32 by one wave each, held in registers: no LDS and no
+// barrier.  Both directions take x first and then y, so that the result of the first
+// product, in the accumulator layout of v_mfma_f64_16x16x4f64 (register r of lane l holds
+// row 4 r + l / 16 of column l mod 16 of its 16 x 16 tile), is already the second product's
+// B operand of k-step r (rows 4 r + l / 16 at lane l).
+//   forward: R = P Tx^T, out = Ty R;   inverse: R = P Tx, out = Ty^T R.
+// The two basis operands (16 values per lane each) are loaded once per wave from the
+// zero-padded copies; the next plane's loads are issued before the current plane's products.
+template <bool FWD>
+__global__ __launch_bounds__(64, 2) void spec_xy32(const SpecXY a) {   // at most 256 registers: two waves per SIMD
+    constexpr int BLD = SPEC_PAD + 1;
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int nx = a.nx, ny = a.ny;
+    double b1[2][8], a2[2][8];   // [tile][k-step]
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            // B1(k, j): forward Tx[j][k], inverse Tx[k][j];  A2(i, k): forward Ty[i][k], inverse Ty[k][i]
+            const int j = 16 * t + li, k = 4 * s + lk;
+            b1[t][s] = FWD ? a.txp[j * BLD + k] : a.txp[k * BLD + j];
+            a2[t][s] = FWD ? a.typ[j * BLD + k] : a.typ[k * BLD + j];
+        }
+    const bool from_q = FWD && a.q;
+    const double *src = from_q ? a.q : a.in;
+    // A1(i, k) = plane[16 t + i][4 s + k], zero outside the plane
+    auto load = [&](uint32_t z, double (&p)[2][8]) {
+        const size_t base = (size_t)z * nx * ny;
+        const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int r = 16 * t + li, c = 4 * s + lk;
+                const bool in = r < ny && c < nx;
+                const double v = in ? src[base + r * nx + c] : 0.0;
+                p[t][s] = (from_q && in) ? -a.K * (v + lump) : v;
+            }
+    };
+    uint32_t z = blockIdx.x;
+    if (z >= a.nplanes) return;
+    double p[2][8];
+    load(z, p);
+    for (; z < a.nplanes; z += gridDim.x) {
+        double pn[2][8];
+        const uint32_t zn = z + gridDim.x;
+        if (zn < a.nplanes) load(zn, pn);
+        f64x4 c1[2][2], c2[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) c1[i][j] = c2[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    c1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[i][s], b1[j][s], c1[i][j], 0, 0, 0);
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    c2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[i][s], c1[s / 4][j][s % 4], c2[i][j], 0, 0, 0);
+        const size_t base = (size_t)z * nx * ny;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * i + 4 * r + lk, col = 16 * j + li;
+                    if (row < ny && col < nx) a.out[base + row * nx + col] = c2[i][j][r];
+                }
+        if (zn < a.nplanes) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int s = 0; s < 8; ++s) p[i][s] = pn[i][s];
+        }
     }
 }
 
@@ -869,14 +954,15 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
         return hipGetLastError();
     }
     if (!a.txp || !a.typ) return hipErrorInvalidValue;
-    // as many work-groups as fit on the chip at once (LDS-bound: 9 or 2 per compute unit)
+    // as many work-groups as fit on the chip at once: eight one-wave work-groups per compute
+    // unit for the register transform (two per SIMD), two for the 64-wide one (LDS-bound)
     const uint32_t fit = small ? 8 * 256 : 2 * 256;
     const dim3 g(a.nplanes < fit ? a.nplanes : fit);
     if (small) {
         if (forward)
-            hipLaunchKernelGGL((spec_xy<true, 32>), g, dim3(64), 0, stream, a);
+            hipLaunchKernelGGL((spec_xy32<true>), g, dim3(64), 0, stream, a);
         else
-            hipLaunchKernelGGL((spec_xy<false, 32>), g, dim3(64), 0, stream, a);
+            hipLaunchKernelGGL((spec_xy32<false>), g, dim3(64), 0, stream, a);
     } else {
         if (forward)
             hipLaunchKernelGGL((spec_xy<true, 64>), g, dim3(256), 0, stream, a);
