@@ -718,9 +718,10 @@ int spec_left(lbmix_ctx *c, const double *T, uint32_t n, uint32_t inner, uint32_
     return c->hip(launch_gemm_f64(g, !inverse, true, c->stream), what);
 }
 
-// The direct solve.  Planes of at most 64 x 64 nodes are transformed in LDS, straight from
-// q (b = -K (q + lump); the projection onto zero channel mean acts on the constant mode
-// only and is applied there); larger planes go through the batched products.
+// The direct solve.  Planes of at most 64 x 64 nodes are transformed per plane (in
+// registers up to 32 x 32, in LDS above), straight from q (b = -K (q + lump); the
+// projection onto zero channel mean acts on the constant mode only and is applied there);
+// larger planes go through the batched products.
 int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     int rc;
     if ((rc = spec_build(c))) return rc;
