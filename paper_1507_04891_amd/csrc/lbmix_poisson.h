@@ -108,9 +108,10 @@ hipError_t launch_gemm_f64(const SpecGemm &g, bool a_k_unit, bool b_n_unit, hipS
 // less one), piv_end[s][mode] for the last plane of segment s.
 hipError_t launch_tridiag_z(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
                             const uint32_t *seg, uint32_t nseg, hipStream_t stream);
-// Per-plane transform along x and y of planes of at most SPEC_XY_MAX nodes (nx, ny <= 64),
-// in LDS on the FP64 matrix cores: each work-group takes several planes, or half a plane
-// when there are fewer planes than compute units.  Forward: out = Ty P Tx^T with P the plane
+// Per-plane transform along x and y of planes of at most SPEC_XY_MAX nodes (nx, ny <= 64)
+// on the FP64 matrix cores: planes up to 32 x 32 in the registers of one wave each, larger
+// ones in LDS (each work-group takes several planes, or half a plane when there are fewer
+// planes than compute units).  Forward: out = Ty P Tx^T with P the plane
 // of `in`, or, when `q` is given, of b = -K (q + lump_z) (lumps from planes, which may be
 // null).  Inverse: out = Ty^T P Tx.
 constexpr uint32_t SPEC_XY_MAX = 4096;
@@ -119,7 +120,7 @@ struct SpecXY {
     const double *in, *q;
     double *out;
     const double *tx, *ty;           // nx x nx and ny x ny bases (row k = basis vector k)
-    const double *txp, *typ;         // the same zero-padded to 64 x 65 (required for planes over 32 wide)
+    const double *txp, *typ;         // the same zero-padded to 64 x 65 rows (required)
     const PlaneInfo *planes;
     double K;
     uint32_t nx, ny, nplanes;
