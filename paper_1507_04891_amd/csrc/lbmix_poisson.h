@@ -120,7 +120,7 @@ struct SpecXY {
     const double *in, *q;
     double *out;
     const double *tx, *ty;           // nx x nx and ny x ny bases (row k = basis vector k)
-    const double *txp, *typ;         // the same zero-padded to 64 x 65 rows (required)
+    const double *txp, *typ;         // the same zero-padded to 64 rows of stride 65 (required)
     const PlaneInfo *planes;
     double K;
     uint32_t nx, ny, nplanes;
