@@ -130,7 +130,9 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream);
 // the longest segment, at most TRI_LDS_MAX.  Both forms also remove the segment mean of
 // mode 0 from the right-hand side first (the projection onto consistent data of each channel).
 constexpr uint32_t TRI_LDS_MAX = 256;
-hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
+// They eliminate from both ends of a segment towards its middle plane L / 2, which takes the
+// inverse of its condensed diagonal from pmid[s][mode] (0 for the singular mode).
+hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *pmid, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream);
 // a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
 hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,

@@ -455,6 +455,17 @@ __device__ __forceinline__ double seg_pivot(const double *piv, const double *piv
     return k + 1 == L ? piv_end[(size_t)s * nmodes + mode] : piv[(size_t)k * nmodes + mode];
 }
 
+// Pivots of the elimination from both ends of a segment towards its middle plane m = L / 2:
+// plane k < m takes the pivot of plane k from the top, plane k > m that of plane L - 1 - k
+// (the same recurrence from the bottom, since the rows are symmetric), and the middle plane
+// the inverse of its condensed diagonal, pmid[segment][mode] (0 for the singular mode, which
+// fixes psi = 0 on the middle plane).
+__device__ __forceinline__ double twoway_pivot(const double *piv, const double *pmid, uint32_t k, uint32_t L,
+                                               uint32_t s, uint32_t mode, uint32_t nmodes) {
+    const uint32_t m = L / 2;
+    return k == m ? pmid[(size_t)s * nmodes + mode] : piv[(size_t)(k < m ? k : L - 1 - k) * nmodes + mode];
+}
+
 __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *piv, const double *piv_end,
                                                 double *out, uint32_t nmodes, const uint32_t *seg) {
     const uint32_t mode = blockIdx.x * 64 + threadIdx.x;
@@ -489,17 +500,27 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 
 // The same eliminations with the columns staged in LDS: one work-group of 256 threads per
 // MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
-// and pivots with coalesced loads, issued sixteen at a time; MODES threads run the recurrences
-// from LDS; all threads write the result back.  The work-group holding mode 0 removes its
+// and pivots with coalesced loads, issued sixteen at a time; 2 MODES threads run the
+// recurrences from LDS, from both ends of the segment; all threads write the result back.  The work-group holding mode 0 removes its
 // segment mean before and after the elimination with all threads.
 constexpr uint32_t TRI_CELLS = 8192;
 
-// Mean over z < L of column 0 of an LDS array [plane][MODES] (L <= 256), by all 256 threads
-// in a fixed order; every thread receives it.
+// LDS layout of the columns of one segment folded at its middle plane mid = L / 2: row j
+// holds plane j in columns 0 .. MODES - 1 (j < mid) and plane L - 1 - j in columns MODES ..
+// 2 MODES - 1 (j < L - 1 - mid); the middle plane sits after the rows, at offset `cells`.
+// The elimination from the top and the one from the bottom then walk the same rows.
 template <uint32_t MODES>
+__device__ __forceinline__ uint32_t folded(uint32_t z, uint32_t m, uint32_t L, uint32_t cells) {
+    const uint32_t mid = L / 2;
+    return z < mid ? z * 2 * MODES + m : z > mid ? (L - 1 - z) * 2 * MODES + MODES + m : cells + m;
+}
+
+// Mean over planes z < L (L <= 256) of mode 0 in the folded layout, by all 256 threads in a
+// fixed order; every thread receives it.
+template <uint32_t MODES, uint32_t CELLS>
 __device__ double column0_mean(const double *s, uint32_t L, double *red) {
     const uint32_t t = threadIdx.x;
-    double v = t < L ? s[t * MODES] : 0.0;
+    double v = t < L ? s[folded<MODES>(t, 0, L, CELLS)] : 0.0;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((t & 63) == 0) red[t >> 6] = v;
@@ -510,10 +531,11 @@ __device__ double column0_mean(const double *s, uint32_t L, double *red) {
 }
 
 template <uint32_t MODES>
-__global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, const double *piv_end,
+__global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, const double *pmid,
                                                    double *out, uint32_t nmodes, const uint32_t *seg) {
     constexpr uint32_t CELLS = MODES * TRI_LDS_MAX < TRI_CELLS ? MODES * TRI_LDS_MAX : TRI_CELLS;
-    __shared__ double sb[CELLS], sp[CELLS];   // [plane][MODES]
+    constexpr uint32_t RS = 2 * MODES;   // row stride of the folded layout
+    __shared__ double sb[CELLS + MODES], sp[CELLS + MODES];
     __shared__ double red[4];
     const uint32_t m0 = blockIdx.x * MODES;
     const uint32_t z0 = seg[blockIdx.y], L = seg[blockIdx.y + 1] - z0;
@@ -526,46 +548,64 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
             const bool in = k < cells && m0 + m < nmodes;
             const size_t i = (size_t)(z0 + z) * nmodes + m0 + m;
             vb[u] = in ? b[i] : 0.0;
-            vp[u] = in ? seg_pivot(piv, piv_end, z, L, blockIdx.y, m0 + m, nmodes) : 0.0;
+            vp[u] = in ? twoway_pivot(piv, pmid, z, L, blockIdx.y, m0 + m, nmodes) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const uint32_t k = k0 + u * 256 + t;
             if (k < cells) {
-                sb[k] = vb[u];
-                sp[k] = vp[u];
+                const uint32_t f = folded<MODES>(k / MODES, k % MODES, L, CELLS);
+                sb[f] = vb[u];
+                sp[f] = vp[u];
             }
         }
     }
     __syncthreads();
     if (m0 == 0) {   // mode 0: project onto zero segment mean
-        const double bm = column0_mean<MODES>(sb, L, red);
-        if (t < L) sb[t * MODES] -= bm;
+        const double bm = column0_mean<MODES, CELLS>(sb, L, red);
+        if (t < L) sb[folded<MODES>(t, 0, L, CELLS)] -= bm;
         __syncthreads();
     }
-    if (t < MODES && m0 + t < nmodes) {
+    // Elimination from both ends towards the middle plane mid: thread c < MODES sweeps down
+    // over planes 0 .. mid - 1 of mode c, thread MODES + c up over planes L - 1 .. mid + 1,
+    // both along the rows of the folded layout with r_k = (b_k - r_prev) p_k; then the middle
+    // plane is solved from its two neighbours, and both threads substitute back outwards,
+    // x_k = r_k - p_k x_(next).
+    const uint32_t mid = L / 2, c = t % MODES;
+    const bool top = t < MODES, act = t < RS && m0 + c < nmodes;
+    const uint32_t steps = top ? mid : L - 1 - mid;
+    if (act) {
         double r = 0.0;
 #pragma unroll 8
-        for (uint32_t z = 0; z < L; ++z) {
-            r = (sb[z * MODES + t] - r) * sp[z * MODES + t];
-            sb[z * MODES + t] = r;
+        for (uint32_t j = 0; j < steps; ++j) {
+            r = (sb[j * RS + t] - r) * sp[j * RS + t];
+            sb[j * RS + t] = r;
         }
-        double x = 0.0;
+    }
+    __syncthreads();
+    if (top && act) {
+        const double up = mid >= 1 ? sb[(mid - 1) * RS + t] : 0.0;
+        const double down = mid + 1 < L ? sb[(L - 2 - mid) * RS + MODES + t] : 0.0;
+        sb[CELLS + t] = (sb[CELLS + t] - up - down) * sp[CELLS + t];
+    }
+    __syncthreads();
+    if (act) {
+        double x = sb[CELLS + c];
 #pragma unroll 8
-        for (uint32_t z = L; z-- > 0;) {
-            x = sb[z * MODES + t] - sp[z * MODES + t] * x;
-            sb[z * MODES + t] = x;
+        for (uint32_t j = steps; j-- > 0;) {
+            x = sb[j * RS + t] - sp[j * RS + t] * x;
+            sb[j * RS + t] = x;
         }
     }
     __syncthreads();
     if (m0 == 0) {   // and gauge it to zero segment mean
-        const double mean = column0_mean<MODES>(sb, L, red);
-        if (t < L) sb[t * MODES] -= mean;
+        const double mean = column0_mean<MODES, CELLS>(sb, L, red);
+        if (t < L) sb[folded<MODES>(t, 0, L, CELLS)] -= mean;
         __syncthreads();
     }
     for (uint32_t k = t; k < cells; k += 256) {
         const uint32_t z = k / MODES, m = k % MODES;
-        if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[k];
+        if (m0 + m < nmodes) out[(size_t)(z0 + z) * nmodes + m0 + m] = sb[folded<MODES>(z, m, L, CELLS)];
     }
 }
 
@@ -972,14 +1012,14 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *piv_end, double *out, uint32_t nmodes,
+hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *pmid, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream) {
     if (longest > TRI_LDS_MAX) return hipErrorInvalidValue;
     // 16 modes per work-group: 64 KB of LDS, so two work-groups share a compute unit and one
     // stages its columns while the other runs its recurrences.  On 64 stacked channels of
     // 32 x 32 planes this took 85 us against 91 (8 modes), 102 (32) and 98 (64, pivots
     // read from the caches).
-    hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, piv_end, out,
+    hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, pmid, out,
                        nmodes, seg);
     return hipGetLastError();
 }

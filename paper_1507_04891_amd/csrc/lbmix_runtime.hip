@@ -109,7 +109,7 @@ struct lbmix_ctx {
     // pivots of the z systems (slit), segment bounds, two work arrays
     double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
     double *sp_txp = nullptr, *sp_typ = nullptr;   // x and y bases zero-padded to 64 x 65 (planes up to 64)
-    double *sp_piv = nullptr, *sp_piv_end = nullptr, *sp_a = nullptr, *sp_b = nullptr;
+    double *sp_piv = nullptr, *sp_piv_end = nullptr, *sp_pmid = nullptr, *sp_a = nullptr, *sp_b = nullptr;
     uint32_t *sp_seg = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
     // state
@@ -659,7 +659,7 @@ int spec_build(lbmix_ctx *c) {
         const size_t nm = (size_t)c->nx * c->ny;
         int longest = 1;
         for (int w : c->ch_width) longest = std::max(longest, w);
-        std::vector<double> piv(nm * (size_t)std::max(longest - 1, 1), 0.0), piv_end(nm * c->nch);
+        std::vector<double> piv(nm * (size_t)std::max(longest - 1, 1), 0.0), piv_end(nm * c->nch), pmid(nm * c->nch);
         for (int my = 0; my < c->ny; ++my)
             for (int mx = 0; mx < c->nx; ++mx) {
                 const size_t m = (size_t)my * c->nx + mx;
@@ -674,9 +674,18 @@ int spec_build(lbmix_ctx *c) {
                     const double before = W > 1 ? piv[(size_t)(W - 2) * nm + m] : 0.0;
                     const double d = -(2.0 + mxy) + 1.0 + (W == 1 ? 1.0 : 0.0);
                     piv_end[(size_t)ch * nm + m] = m == 0 ? 0.0 : 1.0 / (d - before);
+                    // middle plane h = W / 2 of the elimination from both ends: its diagonal
+                    // less the pivots of its two neighbours (pivot W - 2 - h from the bottom)
+                    const int h = W / 2;
+                    const double dh = -(2.0 + mxy) + (h == 0 ? 1.0 : 0.0) + (h == W - 1 ? 1.0 : 0.0);
+                    const double above = h >= 1 ? piv[(size_t)(h - 1) * nm + m] : 0.0;
+                    const double below = h + 1 < W ? piv[(size_t)(W - 2 - h) * nm + m] : 0.0;
+                    pmid[(size_t)ch * nm + m] = m == 0 ? 0.0 : 1.0 / (dh - above - below);
                 }
             }
-        if ((rc = upload(c, &c->sp_piv, piv)) || (rc = upload(c, &c->sp_piv_end, piv_end))) return rc;
+        if ((rc = upload(c, &c->sp_piv, piv)) || (rc = upload(c, &c->sp_piv_end, piv_end)) ||
+            (rc = upload(c, &c->sp_pmid, pmid)))
+            return rc;
         std::vector<uint32_t> seg(c->nch + 1);
         for (int ch = 0; ch <= c->nch; ++ch) seg[ch] = ch < c->nch ? (uint32_t)c->ch_first[ch] : (uint32_t)c->nzf;
         if ((rc = c->hip(hipMalloc((void **)&c->sp_seg, seg.size() * sizeof(uint32_t)), "hipMalloc(direct solve)")))
@@ -745,7 +754,7 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
         int longest = 0;
         for (int w : c->ch_width) longest = std::max(longest, w);
         if (longest <= (int)TRI_LDS_MAX)
-            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, c->sp_piv_end, b, nxy, c->sp_seg, c->nch, (uint32_t)longest,
+            rc = c->hip(launch_tridiag_lds(a, c->sp_piv, c->sp_pmid, b, nxy, c->sp_seg, c->nch, (uint32_t)longest,
                                            c->stream),
                         "tridiag_lds");
         else
@@ -1906,8 +1915,8 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (void *p : {(void *)c->ws_r, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
                         (void *)c->ws_t, (void *)c->ws_mask})
             if (p) (void)hipFree(p);
-        for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_piv_end, c->sp_a,
-                          c->sp_b})
+        for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_piv_end, c->sp_pmid,
+                          c->sp_a, c->sp_b})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
         if (c->step_dev) (void)hipFree(c->step_dev);
