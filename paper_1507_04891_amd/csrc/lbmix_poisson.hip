@@ -785,21 +785,66 @@ __global__ __launch_bounds__(64, 2) void spec_xy32(const SpecXY a) {   // at mos
     }
 }
 
+// One block of 16 TI x 16 TJ of a product on the FP64 matrix cores, C(r0 + r, c0 + c) =
+// sum_k A(r, k) B(k, c) over KN, with the operand fragments of k-step ks supplied by
+// fa(ks, i) (row 16 i + lane mod 16, column 4 ks + lane / 16) and fb(ks, j) (row 4 ks +
+// lane / 16, column 16 j + lane mod 16).
+template <int KN, int TI, int TJ, class FA, class FB>
+__device__ __forceinline__ void mfma_block(FA fa, FB fb, double *C, int ldc, int r0, int c0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    f64x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KN / 4; ++ks) {
+        double av[TI], bv[TJ];
+#pragma unroll
+        for (int i = 0; i < TI; ++i) av[i] = fa(ks, i);
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) bv[j] = fb(ks, j);
+#pragma unroll
+        for (int i = 0; i < TI; ++i)
+#pragma unroll
+            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) C[(r0 + 16 * i + lk + 4 * r) * ldc + c0 + 16 * j + li] = acc[i][j][r];
+}
+
 // Half of the transform of one plane up to 64 x 64 per work-group, for lattices with fewer
 // planes than compute units: the forward transform splits the output columns kx, the inverse
-// the output rows y, and each half needs the whole plane.  The bases are read by the
-// matrix-core steps straight from their zero-padded copies in device memory (they stay in
-// the caches), so only the plane is staged in LDS.
+// the output rows y, and each half needs the whole plane, staged in LDS.  Each product of a
+// half (64 x 32 or 32 x 64) is split over the four waves in blocks of 16 x 32 or 32 x 16;
+// their basis fragments are read from the zero-padded copies into registers at the start,
+// together with the plane, so the matrix-core steps wait on LDS only.
 template <bool FWD>
 __global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
-    constexpr int PM = 64, LD = PM + 1, HM = 32, NT = 256, BATCH = 8;
+    constexpr int PM = 64, LD = PM + 1, HM = 32, NT = 256, BATCH = 8, KS = PM / 4;
     static_assert(PM == (int)SPEC_PAD, "padded bases");
     __shared__ double P[PM * LD], R[PM * (HM + 1)];
-    const double *Tx = a.txp, *Ty = a.typ;
     const int nx = a.nx, ny = a.ny;
     const uint32_t z = blockIdx.x >> 1;
     const int h = blockIdx.x & 1;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const size_t base = (size_t)z * nx * ny;
+    // basis fragments of this wave's blocks: f1 for the first product, f2 for the second
+    //   forward: f1[ks][j] = Tx[32 h + 16 j + li][4 ks + lk], f2[ks] = Ty[16 w + li][4 ks + lk]
+    //   inverse: f1[ks][i] = Ty[4 ks + lk][32 h + 16 i + li], f2[ks] = Tx[4 ks + lk][16 w + li]
+    double f1[KS][2], f2[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lk;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+            f1[ks][u] = FWD ? a.txp[(HM * h + 16 * u + li) * LD + k] : a.typ[k * LD + HM * h + 16 * u + li];
+        f2[ks] = FWD ? a.typ[(16 * w + li) * LD + k] : a.txp[k * LD + 16 * w + li];
+    }
     const bool from_q = FWD && a.q;
     const double *src = from_q ? a.q : a.in;
     const double lump = (from_q && a.planes) ? a.planes[z].lump : 0.0;
@@ -819,20 +864,27 @@ __global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
     }
     __syncthreads();
     if (FWD) {
-        // R[y][kx'] = sum_x P[y][x] Tx[32 h + kx'][x];  P[ky][kx'] = sum_y Ty[ky][y] R[y][kx']
-        mfma_product<PM, HM, PM>(P, LD, 1, Tx + HM * h * LD, 1, LD, R, HM + 1);
+        // R[y][kx'] = sum_x P[y][x] Tx[32 h + kx'][x]  (rows 16 w of R by wave w)
+        mfma_block<PM, 1, 2>([&](int ks, int) { return P[(16 * w + li) * LD + 4 * ks + lk]; },
+                             [&](int ks, int j) { return f1[ks][j]; }, R, HM + 1, 16 * w, 0);
         __syncthreads();
-        mfma_product<PM, HM, PM>(Ty, LD, 1, R, HM + 1, 1, P, LD);
+        // P[ky][kx'] = sum_y Ty[ky][y] R[y][kx']  (rows 16 w)
+        mfma_block<PM, 1, 2>([&](int ks, int) { return f2[ks]; },
+                             [&](int ks, int j) { return R[(4 * ks + lk) * (HM + 1) + 16 * j + li]; }, P, LD, 16 * w,
+                             0);
         __syncthreads();
         for (int k = threadIdx.x; k < PM * HM; k += NT) {
             const int ky = k / HM, kx = HM * h + k % HM;
             if (ky < ny && kx < nx) a.out[base + ky * nx + kx] = P[ky * LD + k % HM];
         }
     } else {
-        // R[y'][kx] = sum_ky Ty[ky][32 h + y'] P[ky][kx];  P[y'][x] = sum_kx R[y'][kx] Tx[kx][x]
-        mfma_product<HM, PM, PM>(Ty + HM * h, 1, LD, P, LD, 1, R, LD);
+        // R[y'][kx] = sum_ky Ty[ky][32 h + y'] P[ky][kx]  (columns 16 w of R by wave w)
+        mfma_block<PM, 2, 1>([&](int ks, int i) { return f1[ks][i]; },
+                             [&](int ks, int) { return P[(4 * ks + lk) * LD + 16 * w + li]; }, R, LD, 0, 16 * w);
         __syncthreads();
-        mfma_product<HM, PM, PM>(R, LD, 1, Tx, LD, 1, P, LD);
+        // P[y'][x] = sum_kx R[y'][kx] Tx[kx][x]  (columns 16 w)
+        mfma_block<PM, 2, 1>([&](int ks, int i) { return R[(16 * i + li) * LD + 4 * ks + lk]; },
+                             [&](int ks, int) { return f2[ks]; }, P, LD, 0, 16 * w);
         __syncthreads();
         for (int k = threadIdx.x; k < HM * PM; k += NT) {
             const int y = HM * h + k / PM, x = k % PM;
