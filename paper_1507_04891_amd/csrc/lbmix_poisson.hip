@@ -707,9 +707,10 @@ __global__ __launch_bounds__(PM == 64 ? 256 : 64) void spec_xy(const SpecXY a) {
 // B operand of k-step r (rows 4 r + l / 16 at lane l).
 //   forward: R = P Tx^T, out = Ty R;   inverse: R = P Tx, out = Ty^T R.
 // The two basis operands (16 values per lane each) are loaded once per wave from the
-// zero-padded copies; the next plane's loads are issued before the current plane's products.
+// zero-padded copies.  Loading the next plane ahead of the current plane's products, at two
+// waves per SIMD, was no faster than three waves per SIMD without it.
 template <bool FWD>
-__global__ __launch_bounds__(64, 2) void spec_xy32(const SpecXY a) {   // at most 256 registers: two waves per SIMD
+__global__ __launch_bounds__(64, 3) void spec_xy32(const SpecXY a) {   // three waves per SIMD
     constexpr int BLD = SPEC_PAD + 1;
     const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
     const int nx = a.nx, ny = a.ny;
@@ -744,9 +745,7 @@ __global__ __launch_bounds__(64, 2) void spec_xy32(const SpecXY a) {   // at mos
     double p[2][8];
     load(z, p);
     for (; z < a.nplanes; z += gridDim.x) {
-        double pn[2][8];
         const uint32_t zn = z + gridDim.x;
-        if (zn < a.nplanes) load(zn, pn);
         f64x4 c1[2][2], c2[2][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -776,12 +775,7 @@ __global__ __launch_bounds__(64, 2) void spec_xy32(const SpecXY a) {   // at mos
                     const int row = 16 * i + 4 * r + lk, col = 16 * j + li;
                     if (row < ny && col < nx) a.out[base + row * nx + col] = c2[i][j][r];
                 }
-        if (zn < a.nplanes) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int s = 0; s < 8; ++s) p[i][s] = pn[i][s];
-        }
+        if (zn < a.nplanes) load(zn, p);
     }
 }
 
@@ -1046,9 +1040,9 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
         return hipGetLastError();
     }
     if (!a.txp || !a.typ) return hipErrorInvalidValue;
-    // as many work-groups as fit on the chip at once: eight one-wave work-groups per compute
-    // unit for the register transform (two per SIMD), two for the 64-wide one (LDS-bound)
-    const uint32_t fit = small ? 8 * 256 : 2 * 256;
+    // as many work-groups as fit on the chip at once: twelve one-wave work-groups per compute
+    // unit for the register transform (three per SIMD), two for the 64-wide one (LDS-bound)
+    const uint32_t fit = small ? 12 * 256 : 2 * 256;
     const dim3 g(a.nplanes < fit ? a.nplanes : fit);
     if (small) {
         if (forward)
