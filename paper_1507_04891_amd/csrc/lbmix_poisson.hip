@@ -501,8 +501,9 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 // The same eliminations with the columns staged in LDS: one work-group of 256 threads per
 // MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
 // and pivots with coalesced loads, issued sixteen at a time; 2 MODES threads run the
-// recurrences from LDS, from both ends of the segment; all threads write the result back.  The work-group holding mode 0 removes its
-// segment mean before and after the elimination with all threads.
+// recurrences from LDS, from both ends of the segment; all threads write the result back.
+// The work-group holding mode 0 removes its segment mean before and after the elimination
+// with all threads.
 constexpr uint32_t TRI_CELLS = 8192;
 
 // LDS layout of the columns of one segment folded at its middle plane mid = L / 2: row j
@@ -609,7 +610,8 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
     }
 }
 
-// C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN between LDS arrays,
+// C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN, operands in LDS
+// or device memory,
 // with A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c], on the
 // FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
 // operand fragment feeds two products.  v_mfma_f64_16x16x4f64: lane l holds A(i, k) and
