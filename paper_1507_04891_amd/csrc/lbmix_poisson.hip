@@ -610,10 +610,9 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
     }
 }
 
-// C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN, operands in LDS
-// or device memory,
-// with A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c], on the
-// FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
+// C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN, with
+// A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c] (operands in
+// LDS or device memory), on the FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
 // operand fragment feeds two products.  v_mfma_f64_16x16x4f64: lane l holds A(i, k) and
 // B(k, j) with i, j = l mod 16 and k = l / 16 of its 16 x 4 and 4 x 16 fragments, and the
 // result rows l / 16 + 4 r, r < 4, of column l mod 16.
