@@ -129,7 +129,7 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream);
 // Tridiagonal solves as launch_tridiag_z, the columns staged in LDS; `longest` = planes of
 // the longest segment, at most TRI_LDS_MAX.  Both forms also remove the segment mean of
 // mode 0 from the right-hand side first (the projection onto consistent data of each channel).
-constexpr uint32_t TRI_LDS_MAX = 256;
+constexpr uint32_t TRI_LDS_MAX = 2048;
 // They eliminate from both ends of a segment towards its middle plane L / 2, which takes the
 // inverse of its condensed diagonal from pmid[s][mode] (0 for the singular mode).
 hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *pmid, double *out, uint32_t nmodes,

@@ -499,7 +499,7 @@ __global__ __launch_bounds__(64) void tridiag_z(const double *b, const double *p
 }
 
 // The same eliminations with the columns staged in LDS: one work-group of 256 threads per
-// MODES modes of one segment (MODES * planes <= 8192).  All threads stage the right-hand side
+// MODES modes of one segment of at most LMAX planes (MODES * LMAX <= 8192).  All threads stage the right-hand side
 // and pivots with coalesced loads, issued sixteen at a time; 2 MODES threads run the
 // recurrences from LDS, from both ends of the segment; all threads write the result back.
 // The work-group holding mode 0 removes its segment mean before and after the elimination
@@ -516,12 +516,13 @@ __device__ __forceinline__ uint32_t folded(uint32_t z, uint32_t m, uint32_t L, u
     return z < mid ? z * 2 * MODES + m : z > mid ? (L - 1 - z) * 2 * MODES + MODES + m : cells + m;
 }
 
-// Mean over planes z < L (L <= 256) of mode 0 in the folded layout, by all 256 threads in a
-// fixed order; every thread receives it.
+// Mean over planes z < L of mode 0 in the folded layout, by all 256 threads in a fixed
+// order; every thread receives it.
 template <uint32_t MODES, uint32_t CELLS>
 __device__ double column0_mean(const double *s, uint32_t L, double *red) {
     const uint32_t t = threadIdx.x;
-    double v = t < L ? s[folded<MODES>(t, 0, L, CELLS)] : 0.0;
+    double v = 0.0;
+    for (uint32_t z = t; z < L; z += 256) v += s[folded<MODES>(z, 0, L, CELLS)];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((t & 63) == 0) red[t >> 6] = v;
@@ -531,10 +532,11 @@ __device__ double column0_mean(const double *s, uint32_t L, double *red) {
     return m;
 }
 
-template <uint32_t MODES>
+template <uint32_t MODES, uint32_t LMAX>
 __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double *piv, const double *pmid,
                                                    double *out, uint32_t nmodes, const uint32_t *seg) {
-    constexpr uint32_t CELLS = MODES * TRI_LDS_MAX < TRI_CELLS ? MODES * TRI_LDS_MAX : TRI_CELLS;
+    constexpr uint32_t CELLS = MODES * LMAX;   // segments of at most LMAX planes
+    static_assert(CELLS <= TRI_CELLS, "LDS");
     constexpr uint32_t RS = 2 * MODES;   // row stride of the folded layout
     __shared__ double sb[CELLS + MODES], sp[CELLS + MODES];
     __shared__ double red[4];
@@ -564,7 +566,7 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
     __syncthreads();
     if (m0 == 0) {   // mode 0: project onto zero segment mean
         const double bm = column0_mean<MODES, CELLS>(sb, L, red);
-        if (t < L) sb[folded<MODES>(t, 0, L, CELLS)] -= bm;
+        for (uint32_t z = t; z < L; z += 256) sb[folded<MODES>(z, 0, L, CELLS)] -= bm;
         __syncthreads();
     }
     // Elimination from both ends towards the middle plane mid: thread c < MODES sweeps down
@@ -601,7 +603,7 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
     __syncthreads();
     if (m0 == 0) {   // and gauge it to zero segment mean
         const double mean = column0_mean<MODES, CELLS>(sb, L, red);
-        if (t < L) sb[folded<MODES>(t, 0, L, CELLS)] -= mean;
+        for (uint32_t z = t; z < L; z += 256) sb[folded<MODES>(z, 0, L, CELLS)] -= mean;
         __syncthreads();
     }
     for (uint32_t k = t; k < cells; k += 256) {
@@ -1062,12 +1064,20 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
 hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *pmid, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream) {
     if (longest > TRI_LDS_MAX) return hipErrorInvalidValue;
-    // 16 modes per work-group: 64 KB of LDS, so two work-groups share a compute unit and one
-    // stages its columns while the other runs its recurrences.  On 64 stacked channels of
-    // 32 x 32 planes this took 85 us against 91 (8 modes), 102 (32) and 98 (64, pivots
-    // read from the caches).
-    hipLaunchKernelGGL((tridiag_lds<16>), dim3((nmodes + 15) / 16, nseg), dim3(256), 0, stream, b, piv, pmid, out,
-                       nmodes, seg);
+    // Up to 256 planes: 16 modes per work-group, 64 KB of LDS, so two work-groups share a
+    // compute unit and one stages its columns while the other runs its recurrences (on 64
+    // stacked channels of 32 x 32 planes, 71-76 us against 81 with 8 modes and 97 with 32).
+    // Longer segments: fewer modes per work-group in 128 KB of LDS.
+    const dim3 blk(256);
+    if (longest <= 256)
+        hipLaunchKernelGGL((tridiag_lds<16, 256>), dim3((nmodes + 15) / 16, nseg), blk, 0, stream, b, piv, pmid, out,
+                           nmodes, seg);
+    else if (longest <= 1024)
+        hipLaunchKernelGGL((tridiag_lds<8, 1024>), dim3((nmodes + 7) / 8, nseg), blk, 0, stream, b, piv, pmid, out,
+                           nmodes, seg);
+    else
+        hipLaunchKernelGGL((tridiag_lds<4, 2048>), dim3((nmodes + 3) / 4, nseg), blk, 0, stream, b, piv, pmid, out,
+                           nmodes, seg);
     return hipGetLastError();
 }
 

@@ -364,9 +364,11 @@ def test_multigrid_cycles_on_the_charged_slit(P):
 
 DIRECT_CASES = [("slit", (16, 8, 34)), ("periodic", (16, 8, 12)), ("slit", (7, 5, 13)), ("periodic", (9, 6, 7)),
                 ("slit", (1, 1, 12)), ("periodic", (70, 3, 5)), ("slit", (130, 66, 8)),
-                # more planes than transform work-groups (256 of 64 x 64, 1024 of 32 x 32), and
-                # a segment longer than the LDS elimination takes
-                ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100)),
+                # more planes than transform work-groups (256 of 64 x 64, 1024 of 32 x 32); LDS
+                # eliminations of 8 modes (segments of 257-1024 planes) and 4 modes (1025-2048),
+                # and a segment longer than the LDS eliminations take
+                ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100)), ("slit", (6, 4, 1100)),
+                ("slit", (2, 2, 2100)),
                 # planes between 32 and 64 wide, fewer than 256: split in halves
                 ("slit", (40, 36, 34)), ("periodic", (48, 33, 10))]
 
