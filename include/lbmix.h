@@ -230,8 +230,9 @@ int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_
  * lbmix_set_poisson caps (or, with rel_tol == 0, fixes) the number of V-cycles per solve and
  * lbmix_stats counts cycles in place of sweeps.  2 direct: the operator of eq. `Poisson` is
  * diagonalised along x and y by orthonormal real Fourier bases (planes of up to 64 x 64
- * nodes in LDS, larger ones by batched FP64 products) and solved exactly along z, by one
- * tridiagonal elimination per (x, y) mode and channel in a slit or stack, by a third
+ * nodes one at a time on the FP64 matrix cores, larger ones by batched FP64 products) and
+ * solved exactly along z, by a tridiagonal elimination per (x, y) mode and channel in a
+ * slit or stack (from both ends towards the middle plane), by a third
  * Fourier basis in a periodic box; its result is exact to rounding, takes any extents and
  * needs no warm start (rel_tol and max_sweeps do not apply; lbmix_stats counts one sweep
  * per solve and reports the residual of every check_every-th solve).  SOR and multigrid
