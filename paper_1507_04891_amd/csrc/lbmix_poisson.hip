@@ -386,10 +386,15 @@ __global__ __launch_bounds__(BLOCK) void shift(double *psi, uint32_t N, const do
 // batched products C_b = A_b B_b in FP64; the zero-flux z direction of a slit is solved by
 // one tridiagonal system per transformed (x, y) mode.
 
+// FP64 matrix cores, v_mfma_f64_16x16x4f64: lane l holds A(i, k) and B(k, j) with
+// i, j = l mod 16 and k = l / 16 of its 16 x 4 and 4 x 16 fragments, and the result rows
+// l / 16 + 4 r, r < 4, of column l mod 16 (checked on the GPU with a one-wave probe).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 // C_b[m][n] = sum_k A_b[m][k] B_b[k][n]; 64 x 64 output tile per work-group of 256 threads,
-// 4 x 4 outputs per thread, k in steps of 16 through LDS.  AK1: the unit stride of A is its
-// k index (else its m index); BN1: the unit stride of B is its n index (else its k index),
-// so that consecutive threads load consecutive addresses.
+// k in steps of 16 through LDS, each wave a 32 x 32 block on the FP64 matrix cores.  AK1: the
+// unit stride of A is its k index (else its m index); BN1: the unit stride of B is its n
+// index (else its k index), so that consecutive threads load consecutive addresses.
 constexpr int GT = 64, GK = 16;
 
 template <bool AK1, bool BN1>
@@ -400,12 +405,13 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
     const double *B = g.B + (size_t)blockIdx.z * g.sBb;
     double *C = g.C + (size_t)blockIdx.z * g.sCb;
     const uint32_t t = threadIdx.x;
-    const uint32_t tm = (t >> 4) * 4, tn = (t & 15) * 4;
-    double acc[4][4];
+    const int w = t >> 6, lane = t & 63, li = lane & 15, lk = lane >> 4;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+        for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     for (uint32_t k0 = 0; k0 < g.K; k0 += GK) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -419,29 +425,29 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][tm + i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn + j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+        for (int ks = 0; ks < GK / 4; ++ks) {
+            const int k = 4 * ks + lk;
+            const double a0 = As[k][r0 + li], a1 = As[k][r0 + 16 + li];
+            const double b0 = Bs[k][c0 + li], b1 = Bs[k][c0 + 16 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t m = m0 + tm + i;
-        if (m >= g.M) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t n = n0 + tn + j;
-            if (n < g.N) C[(size_t)m * g.sCm + n] = acc[i][j];
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t m = m0 + r0 + 16 * i + lk + 4 * r;
+            if (m >= g.M) continue;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const uint32_t n = n0 + c0 + 16 * j + li;
+                if (n < g.N) C[(size_t)m * g.sCm + n] = acc[i][j][r];
+            }
         }
-    }
 }
 
 // One thread per (mode, segment): rows psi_{z-1} - (2 + mu) psi_z + psi_{z+1} = b_z of a
@@ -614,11 +620,8 @@ __global__ __launch_bounds__(256) void tridiag_lds(const double *b, const double
 
 // C(r, c) = sum_k A(r, k) B(k, c) for r < RN, c < CN (multiples of 32), k < KN, with
 // A(r, k) = A[r ar + k ak], B(k, c) = B[k bk + c bc] and C(r, c) = C[r ldc + c] (operands in
-// LDS or device memory), on the FP64 matrix cores.  Each wave takes 32 x 32 blocks of four 16 x 16 tiles, so that every
-// operand fragment feeds two products.  v_mfma_f64_16x16x4f64: lane l holds A(i, k) and
-// B(k, j) with i, j = l mod 16 and k = l / 16 of its 16 x 4 and 4 x 16 fragments, and the
-// result rows l / 16 + 4 r, r < 4, of column l mod 16.
-typedef double f64x4 __attribute__((ext_vector_type(4)));
+// LDS or device memory), on the FP64 matrix cores.  Each wave takes 32 x 32 blocks of four
+// 16 x 16 tiles, so that every operand fragment feeds two products.
 
 template <int RN, int CN, int KN>
 __device__ void mfma_product(const double *A, int ar, int ak, const double *B, int bk, int bc, double *C, int ldc) {
