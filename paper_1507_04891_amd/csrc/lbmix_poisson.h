@@ -92,12 +92,18 @@ hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream);
 hipError_t launch_extrapolate(double *psi, double *p1, double *p2, uint32_t N, hipStream_t stream);
 
 // Batched FP64 product C_b[m][n] = sum_k A_b[m][k] B_b[k][n] with element strides (the
-// unit stride of C is n).
+// unit stride of C is n).  With rhs set, A holds q and the product takes
+// A[m][k] = -rhs_K (q + lump of plane m / rows_per_plane) instead (lumps from planes, which
+// may be null), the right-hand side of the Poisson equation formed on the fly.
 struct SpecGemm {
     const double *A, *B;
     double *C;
     uint32_t M, N, K, batch;
     size_t sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm;
+    int rhs;
+    double rhs_K;
+    const PlaneInfo *planes;
+    uint32_t rows_per_plane;
 };
 // a_k_unit: sAk == 1 (else sAm == 1); b_n_unit: sBn == 1 (else sBk == 1); these choose the
 // coalesced load pattern only.

@@ -418,7 +418,12 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
             const uint32_t e = t + 256 * i;
             const uint32_t ak = AK1 ? e % GK : e / GT, am = AK1 ? e / GK : e % GT;
             const uint32_t m = m0 + am, ka = k0 + ak;
-            As[ak][am] = (m < g.M && ka < g.K) ? A[(size_t)m * g.sAm + (size_t)ka * g.sAk] : 0.0;
+            double av = 0.0;
+            if (m < g.M && ka < g.K) {
+                av = A[(size_t)m * g.sAm + (size_t)ka * g.sAk];
+                if (g.rhs) av = -g.rhs_K * (av + (g.planes ? g.planes[m / g.rows_per_plane].lump : 0.0));
+            }
+            As[ak][am] = av;
             const uint32_t bk = BN1 ? e / GT : e % GK, bn = BN1 ? e % GT : e / GK;
             const uint32_t n = n0 + bn, kb = k0 + bk;
             Bs[bk][bn] = (n < g.N && kb < g.K) ? B[(size_t)kb * g.sBk + (size_t)n * g.sBn] : 0.0;

@@ -706,9 +706,15 @@ int spec_build(lbmix_ctx *c) {
 
 // Transforms along x (rows of nx), y (per plane) and z (whole array) into `out`;
 // inverse = the transposed basis.
-int spec_x(lbmix_ctx *c, const double *in, double *out, bool inverse) {
+int spec_x(lbmix_ctx *c, const double *in, double *out, bool inverse, bool from_q = false) {
     SpecGemm g{};
     g.A = in; g.C = out; g.B = c->sp_tx;
+    if (from_q) {   // in = q: the product forms b = -K (q + lump) as it loads it
+        g.rhs = 1;
+        g.rhs_K = 4.0 * kPi * c->lB;
+        g.planes = c->slit ? c->d_planes : nullptr;
+        g.rows_per_plane = (uint32_t)c->ny;
+    }
     g.M = (uint32_t)c->ny * c->nzf; g.N = c->nx; g.K = c->nx; g.batch = 1;
     g.sAm = c->nx; g.sAk = 1; g.sCm = c->nx;
     // forward: C[m][k] = sum_x A[m][x] T[k][x];  inverse: C[m][x] = sum_k A[m][k] T[k][x]
@@ -728,9 +734,10 @@ int spec_left(lbmix_ctx *c, const double *T, uint32_t n, uint32_t inner, uint32_
 }
 
 // The direct solve.  Planes of at most 64 x 64 nodes are transformed per plane (in
-// registers up to 32 x 32, in LDS above), straight from q (b = -K (q + lump); the
-// projection onto zero channel mean acts on the constant mode only and is applied there);
-// larger planes go through the batched products.
+// registers up to 32 x 32, in LDS above), larger planes by the batched products; both read
+// q and form b = -K (q + lump) as they load it.  The projection onto zero channel mean acts
+// on the constant mode only and is applied there: by the z elimination of a slit or stack,
+// by the spectral scale of a periodic box.
 int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     int rc;
     if ((rc = spec_build(c))) return rc;
@@ -745,9 +752,9 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
         xy.q = c->q; xy.in = nullptr; xy.out = a;
         if ((rc = c->hip(launch_spec_xy(xy, true, c->stream), "spec_xy"))) return rc;
     } else {
-        if ((rc = channel_means(c, c->q, 0, 0))) return rc;
-        if ((rc = c->hip(launch_make_rhs(pa, a, c->stream), "make_rhs"))) return rc;
-        if ((rc = spec_x(c, a, b, false))) return rc;
+        // b = -K (q + lump) formed by the x product as it loads q; its projection onto zero
+        // channel mean acts on the constant mode only, which the z solve projects
+        if ((rc = spec_x(c, c->q, b, false, true))) return rc;
         if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, false, "gemm(y)"))) return rc;
     }
     if (c->slit) {
