@@ -126,7 +126,8 @@ DTYPE = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f16", "bf16s": "bf1
 
 def bench_slit(args):
     """The charged ternary slit: 64 x 64 x 130 (walls z = 0, 129), solvent + cation + anion,
-    lambda_D = 8, sigma = -1e-4 per wall, E_x = 1e-4, Sc = 100, Poisson to 1e-8 every step.
+    lambda_D = 8, sigma = -1e-4 per wall, E_x = 1e-4, Sc = 100, Poisson to 1e-8 every step;
+    with --size large the precision configuration's slit, 128 x 128 x 258.
     Prints its own JSON line (step time with and without the Poisson solve, solver work)."""
     import torch
 
@@ -134,10 +135,11 @@ def bench_slit(args):
     import workloads as WL
 
     torch.cuda.set_device(0)
-    w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4,
+    nxy, nz = (128, 258) if args.size == "large" else (64, 130)
+    w = WL.charged_slit(nx=nxy, ny=nxy, nz=nz, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4,
                         sc=100.0)
     stream = torch.cuda.current_stream()
-    out = {"workload": "charged ternary slit 64x64x130 (fluid 64x64x128), Sc=100, lambda_D=8, "
+    out = {"workload": f"charged ternary slit {nxy}x{nxy}x{nz} (fluid {nxy}x{nxy}x{nz - 2}), Sc=100, lambda_D=8, "
                        "sigma=-1e-4, E_x=1e-4, Poisson rel. residual 1e-8 per step",
            "storage": args.storage}
     lat = P.from_workload(w, storage=args.storage, stream=stream,
@@ -160,7 +162,7 @@ def bench_slit(args):
     torch.cuda.synchronize()
     ms = start.elapsed_time(end) / args.steps
     st1 = lat.stats()
-    sites = 3 * 64 * 64 * 128
+    sites = 3 * nxy * nxy * (nz - 2)
     out.update({"ms_per_step": round(ms, 4), "glups": round(sites / (ms * 1e-3) / 1e9, 4),
                 "poisson_work_per_step": round((st1["total_sweeps"] - st0["total_sweeps"]) / args.steps, 2),
                 "poisson_method": args.poisson, "warm_start": args.warm_start,
@@ -466,7 +468,8 @@ def main():
     ap.add_argument("--check-every", type=int, default=10)
     ap.add_argument("--train-steps", type=int, default=300, help="training steps of the warm-start network")
     ap.add_argument("--size", default="small", choices=["small", "large"],
-                    help="precision workload: small lattices (default) or the 512^3 configuration")
+                    help="precision workload: small lattices (default) or the 512^3 configuration; "
+                         "slit workload: 64x64x130 (default) or 128x128x258")
     ap.add_argument("--warm-start", default="previous", choices=["previous", "extrapolated"])
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="also run a plain device copy of this many GiB (3 times), the reference "
