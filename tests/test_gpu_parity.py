@@ -669,7 +669,7 @@ def test_full_size_ternary_slit_128x128x258_sixteen_bit(P, oracle_mod, storage):
         assert err > 0.0
 
 
-@pytest.mark.parametrize("case", ["binary_f32s", "slit_direct_f32s", "channels_bf16s"])
+@pytest.mark.parametrize("case", ["binary_f32s", "slit_direct_f32s", "slit_batched_f32s", "channels_bf16s"])
 def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
     """Captured steps (fused step + direct solve + step count) replay exactly the uncaptured
     sequence, including the stochastic-rounding stream of the 16-bit forms."""
@@ -677,6 +677,9 @@ def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
         w, storage, poisson = WL.binary_multimode(n=24, amp=1e-2, nmodes=4, shear=1e-2, sc=30.0, seed=3), "f32s", None
     elif case == "slit_direct_f32s":
         w = WL.charged_slit(nx=16, ny=8, nz=34, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+        storage, poisson = "f32s", dict(method="direct")
+    elif case == "slit_batched_f32s":   # planes wider than 64: the batched products
+        w = WL.charged_slit(nx=70, ny=66, nz=12, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
         storage, poisson = "f32s", dict(method="direct")
     else:
         w, storage, poisson = WL.channel_stack(**SMALL_STACK), "bf16s", dict(method="direct")
