@@ -69,7 +69,7 @@ def test_parameter_validation_without_device(L):
     assert L.lbmix_step(h, 1) == -4
     assert L.lbmix_autotune(h, 3) == -4
     assert b"no state" in L.lbmix_last_error(h)
-    # the first device call reports the missing GPU as EDEVICE (on a GPU machine it allocates)
+    # the first device call reports the missing GPU as EDEVICE (with a GPU present it allocates)
     st = L.lbmix_set_state(h, 0, (ctypes.c_double * (8 * 8 * 10))(), None)
     assert st in (0, -3)
     L.lbmix_destroy(h)
