@@ -412,7 +412,11 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    for (uint32_t k0 = 0; k0 < g.K; k0 += GK) {
+    // with BN1 the next k step's tile is read into registers while the current one is
+    // multiplied (the other layout measured slower that way, so it reads each tile in turn)
+    constexpr bool PIPE = BN1;
+    double ra[4], rb[4];
+    auto fetch = [&](uint32_t k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint32_t e = t + 256 * i;
@@ -423,12 +427,34 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
                 av = A[(size_t)m * g.sAm + (size_t)ka * g.sAk];
                 if (g.rhs) av = -g.rhs_K * (av + (g.planes ? g.planes[m / g.rows_per_plane].lump : 0.0));
             }
-            As[ak][am] = av;
+            ra[i] = av;
             const uint32_t bk = BN1 ? e / GT : e % GK, bn = BN1 ? e % GT : e / GK;
             const uint32_t n = n0 + bn, kb = k0 + bk;
-            Bs[bk][bn] = (n < g.N && kb < g.K) ? B[(size_t)kb * g.sBk + (size_t)n * g.sBn] : 0.0;
+            rb[i] = (n < g.N && kb < g.K) ? B[(size_t)kb * g.sBk + (size_t)n * g.sBn] : 0.0;
         }
+    };
+    auto stage = [&]() {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t e = t + 256 * i;
+            As[AK1 ? e % GK : e / GT][AK1 ? e / GK : e % GT] = ra[i];
+            Bs[BN1 ? e / GT : e % GK][BN1 ? e % GT : e / GK] = rb[i];
+        }
+    };
+    if (PIPE) {
+        fetch(0);
+        stage();
         __syncthreads();
+    }
+    for (uint32_t k0 = 0; k0 < g.K; k0 += GK) {
+        const bool more = k0 + GK < g.K;
+        if (!PIPE) {
+            fetch(k0);
+            stage();
+            __syncthreads();
+        } else if (more) {
+            fetch(k0 + GK);
+        }
 #pragma unroll
         for (int ks = 0; ks < GK / 4; ++ks) {
             const int k = 4 * ks + lk;
@@ -440,6 +466,10 @@ __global__ __launch_bounds__(256) void gemm_f64(const SpecGemm g) {
             acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
+        if (PIPE && more) {
+            stage();
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
