@@ -30,16 +30,23 @@ MAXS = 8
 Q = 19
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain ISO C, no FMA contraction, OpenMP over nodes)."""
-    if not force and os.path.exists(LIB_PATH):
-        return LIB_PATH
-    tmp = LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
-           "-o", tmp, _SRC, "-lm"]
+BUILD_FLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC"]
+# the same source built for the host it runs on, for timing it as the CPU baseline (no FMA
+# contraction either, so the arithmetic is that of the default build)
+NATIVE_FLAGS = ["-O3", "-march=native", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC"]
+
+
+def build(force: bool = True, native: bool = False, path: str | None = None) -> str:
+    """Compile the oracle with gcc (plain ISO C, no FMA contraction, OpenMP over nodes).
+    native: optimise for this host's CPU (-O3 -march=native) into `path`."""
+    out = path or LIB_PATH
+    if not force and os.path.exists(out):
+        return out
+    tmp = out + ".tmp"
+    cmd = ["gcc", *(NATIVE_FLAGS if native else BUILD_FLAGS), "-shared", "-o", tmp, _SRC, "-lm"]
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, out)
+    return out
 
 
 class _Params(ctypes.Structure):
@@ -58,15 +65,16 @@ class _Params(ctypes.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            build()
-        L = ctypes.CDLL(LIB_PATH)
+def lib(path: str | None = None):
+    """The loaded oracle library (the default build, or the one at `path`)."""
+    path = path or LIB_PATH
+    if path not in _libs:
+        if not os.path.exists(path):
+            build(path=path)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)
         L.ora_create.restype = ctypes.c_void_p
@@ -87,8 +95,8 @@ def lib():
         L.ora_forcing.argtypes = [ctypes.c_double, dp, dp, dp]
         L.ora_drag.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp]
         L.ora_drag_pair.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, dp]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _dp(a: np.ndarray):
@@ -150,12 +158,15 @@ class Oracle:
 
     geometry: "periodic" (periodic in x, y, z) or "slit" (solid planes z = 0 and z = nz-1).
     poisson: "direct" (spectral solve of the 7-point operator) or "sor" (red-black SOR).
+    forcing: "paper" (drag on mid-step velocities, reading R3b), "guo" (the Guo-type
+    variant) or "literal" (drag on the plain first moments; only for the tests that pin R3b).
+    lib_path: another build of the same source (e.g. the host-optimised one of build(native=True)).
     """
 
     def __init__(self, nx, ny, nz, nspecies, omega_visc, omega_drag, geometry="periodic",
                  valence=None, bjerrum=0.0, sigma=(0.0, 0.0), E=(0.0, 0.0, 0.0),
                  poisson="direct", lagged=True, sor_omega=None, sor_tol=1e-8,
-                 sor_max=100000, sor_check=10, drag_pair=None, forcing="paper"):
+                 sor_max=100000, sor_check=10, drag_pair=None, forcing="paper", lib_path=None):
         if nspecies > MAXS:
             raise ValueError("too many species")
         p = _Params()
@@ -177,7 +188,7 @@ class Oracle:
         p.sor_tol = sor_tol
         p.sor_max = sor_max
         p.sor_check = sor_check
-        p.forcing = {"paper": 0, "guo": 1}[forcing]
+        p.forcing = {"paper": 0, "guo": 1, "literal": 2}[forcing]
         if drag_pair is not None:   # [ns][ns] drag frequencies omega^{ab}
             om = np.asarray(drag_pair, dtype=np.float64).reshape(nspecies, nspecies)
             p.pair_drag = 1
@@ -188,54 +199,55 @@ class Oracle:
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.ns = nspecies
-        self._h = lib().ora_create(ctypes.byref(p))
+        self._L = lib(lib_path)
+        self._h = self._L.ora_create(ctypes.byref(p))
         if not self._h:
             raise ValueError("oracle rejected the lattice parameters")
 
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().ora_destroy(h)
+            self._L.ora_destroy(h)
             self._h = None
 
     def set_state(self, s, n, u=None):
         n = _f64(n).reshape(self.shape)
         uu = None if u is None else _f64(u).reshape((3,) + self.shape)
-        rc = lib().ora_set_state(self._h, s, _dp(n), None if uu is None else _dp(uu))
+        rc = self._L.ora_set_state(self._h, s, _dp(n), None if uu is None else _dp(uu))
         if rc:
             raise ValueError("bad species")
 
     def set_populations(self, s, f):
         f = _f64(f).reshape((19,) + self.shape)
-        lib().ora_set_f(self._h, s, _dp(f))
+        self._L.ora_set_f(self._h, s, _dp(f))
 
     def populations(self, s):
         f = np.zeros((19,) + self.shape)
-        lib().ora_get_f(self._h, s, _dp(f))
+        self._L.ora_get_f(self._h, s, _dp(f))
         return f
 
     def step(self, n=1):
-        return lib().ora_step(self._h, int(n))
+        return self._L.ora_step(self._h, int(n))
 
     def moments(self, s):
         n = np.zeros(self.shape)
         j = np.zeros((3,) + self.shape)
-        lib().ora_moments(self._h, s, _dp(n), _dp(j))
+        self._L.ora_moments(self._h, s, _dp(n), _dp(j))
         return n, j
 
     def mass_totals(self):
         out = np.zeros(self.ns)
-        lib().ora_mass_totals(self._h, _dp(out))
+        self._L.ora_mass_totals(self._h, _dp(out))
         return out
 
     def potential(self):
         out = np.zeros(self.shape)
-        lib().ora_get_psi(self._h, _dp(out))
+        self._L.ora_get_psi(self._h, _dp(out))
         return out
 
     def charge(self):
         out = np.zeros(self.shape)
-        lib().ora_get_q(self._h, _dp(out))
+        self._L.ora_get_q(self._h, _dp(out))
         return out
 
     def poisson(self, q, psi0=None):
@@ -244,12 +256,12 @@ class Oracle:
         psi = np.zeros(self.shape) if psi0 is None else _f64(psi0).reshape(self.shape).copy()
         sw = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
-        st = lib().ora_poisson(self._h, _dp(q), _dp(psi), ctypes.byref(sw), ctypes.byref(rr))
+        st = self._L.ora_poisson(self._h, _dp(q), _dp(psi), ctypes.byref(sw), ctypes.byref(rr))
         return psi, sw.value, rr.value, st
 
     def stats(self):
         step = ctypes.c_long(0)
         sw = ctypes.c_int(0)
         rr = ctypes.c_double(0.0)
-        st = lib().ora_stats(self._h, ctypes.byref(step), ctypes.byref(sw), ctypes.byref(rr))
+        st = self._L.ora_stats(self._h, ctypes.byref(step), ctypes.byref(sw), ctypes.byref(rr))
         return {"step": step.value, "sweeps": sw.value, "resid": rr.value, "status": st}

@@ -55,6 +55,13 @@
  * implicit in F, F^alpha = a^alpha - omega_drag sum_b (n^b / n)(v^alpha - v^b), and the
  * forcing term is (1 - omega_visc / 2) g_p(F^alpha, v) with v the barycentric average of the
  * v^alpha.  The implicit drag is solved per node as the dense linear system it is.
+ *
+ * Literal variant (forcing = 2), kept only to pin reading [R3b]: the drag of Sec. II is
+ * evaluated on the plain first moments u^alpha of the pre-collision populations (and their
+ * barycentric average), everything else as forcing = 0.  Its uniform steady current is
+ * (n^+ + n^-) E / omega_drag instead of (D / v_T^2)(n^+ + n^-) E, and its zero-flux profile
+ * under a constant force a is n ~ exp(a z / (v_T^2 (1 - omega_drag / 2))) instead of the
+ * Boltzmann factor exp(a z / v_T^2).
  */
 #include <math.h>
 #include <stdio.h>
@@ -110,7 +117,8 @@ typedef struct {
     int sor_check;         /* sweeps between residual evaluations */
     int pair_drag;         /* 1: drag frequency per pair of species from drag_pair */
     double drag_pair[ORA_MAXS * ORA_MAXS]; /* omega^{ab} at [a * ORA_MAXS + b], symmetric */
-    int forcing;           /* 0: g with u^alpha, drag on mid-step velocities; 1: the Guo-type variant */
+    int forcing;           /* 0: g with u^alpha, drag on mid-step velocities; 1: the Guo-type variant;
+                              2: drag on the plain first moments (literal reading) */
 } ora_params;
 
 typedef struct {
@@ -539,8 +547,8 @@ static int solve_potential(ora_ctx *c, const double *q) {
 ora_ctx *ora_create(const ora_params *p) {
     if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->ns < 1 || p->ns > ORA_MAXS) return NULL;
     if (p->slit && p->nz < 3) return NULL;
-    if (p->forcing != 0 && p->forcing != 1) return NULL;
-    if (p->forcing == 1 && p->pair_drag) return NULL;
+    if (p->forcing < 0 || p->forcing > 2) return NULL;
+    if (p->forcing != 0 && p->pair_drag) return NULL;
     ora_ctx *c = (ora_ctx *)calloc(1, sizeof(ora_ctx));
     c->p = *p;
     c->N = (long)p->nx * p->ny * p->nz;
@@ -726,11 +734,12 @@ static int one_step(ora_ctx *c) {
             }
             gscale = 1.0 - 0.5 * P->omega_visc;
         } else {
-            /* drag on the mid-step velocities [R3b], then the total force */
+            /* drag on the mid-step velocities [R3b] (forcing = 2: on the plain first
+             * moments), then the total force */
             if (P->pair_drag)
                 ora_drag_pair(ns, n, umid, P->drag_pair, ORA_MAXS, F);
             else
-                ora_drag(ns, n, umid, P->omega_drag, F);
+                ora_drag(ns, n, P->forcing == 2 ? ua : umid, P->omega_drag, F);
             for (int s = 0; s < ns; ++s)
                 for (int d = 0; d < 3; ++d) F[3 * s + d] += acc[3 * s + d];
         }
