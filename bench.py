@@ -5,12 +5,16 @@ stored as deviations from rest (f - w rho0), rest density 0.5 per species, 8 see
 concentration modes (amplitude 1e-3, antiphase between species) plus a shear wave
 u_y = 1e-3 sin(2 pi x / 256), tau_visc = 1, Sc = 100 (synthetic inputs from
 workloads.binary_multimode, seed 2).  One step = one fused stream-collide launch (pull
-streaming, moments, drag, collision, store, FP64 mass partials).  The same workload is also
-timed with plain FP32, FP16 and BF16 storage ("variants").
+streaming, moments, drag, collision, store, FP64 mass partials).  The timed steps run as 5
+windows and the median per-step time is reported.  The same workload is also timed with
+plain FP32, FP16 and BF16 storage and with stochastically rounded FP32 ("variants").
 
 Prints one JSON line: species-site updates per second (GLUPS), the roofline of the
-stream-collide kernel against MI355X HBM bandwidth, and the FP64 CPU oracle timed on a
-bounded sample of the same workload on this host.
+stream-collide kernel against MI355X HBM bandwidth (with the measured ceiling of a plain
+device copy), every other configuration ("configs": the charged ternary slit 64 x 64 x 130
+with the direct, SOR and multigrid solvers, the 128 x 128 x 258 slit, 64 batched channels and
+the 512^3 binary), and the FP64 CPU oracle, built for this host, timed on a bounded sample of
+the headline workload.
 """
 from __future__ import annotations
 
@@ -51,11 +55,27 @@ def traffic_from_profile(storage: str, n: int):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, sc: float, target_s: float = 12.0):
-    """The FP64 oracle on the same 256^3 workload, a bounded number of steps."""
+    """The FP64 oracle on the same 256^3 workload, a bounded number of steps, built for this
+    host (gcc -O3 -march=native, no FMA contraction, OpenMP) in a temporary directory."""
+    import tempfile
+
     import oracle
 
-    o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag)
+    tmpdir = tempfile.mkdtemp(prefix="lbmix_oracle_")
+    path = oracle.build(native=True, path=os.path.join(tmpdir, "liblbmix_oracle_native.so"))
+    o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag, lib_path=path)
     for s in range(w.nspecies):
         o.set_state(s, w.n[s], w.u[s])
     t0 = time.perf_counter()
@@ -66,20 +86,22 @@ def cpu_baseline(w, sc: float, target_s: float = 12.0):
     if extra:
         o.step(extra)
     t2 = time.perf_counter() - t0
+    del o
     steps = 1 + extra
     elapsed = t1 + t2
     sites = w.nspecies * w.nx * w.ny * w.nz
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = {"value": sites * steps / elapsed / 1e9, "unit": "GLUPS", "cores": threads, "kind": "oracle",
            "sample": f"{steps} of the 2000 steps of the {w.nx}^3 binary workload, FP64, "
-                     f"{elapsed:.1f} s on {threads} OpenMP threads"}
+                     f"{elapsed:.1f} s on {threads} OpenMP threads",
+           "cpu_model": cpu_model(), "build": "gcc " + " ".join(oracle.NATIVE_FLAGS)}
     # the same oracle on one thread, one step, in a child process (OpenMP reads its thread
     # count at start-up); the child does not touch the GPU
     code = ("import sys, time; sys.path.insert(0, %r); import oracle, workloads as WL; "
             "w = WL.binary_multimode(n=%d, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=%r, seed=2); "
-            "o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag); "
+            "o = oracle.Oracle(w.nx, w.ny, w.nz, w.nspecies, w.omega_visc, w.omega_drag, lib_path=%r); "
             "[o.set_state(s, w.n[s], w.u[s]) for s in range(w.nspecies)]; "
-            "t0 = time.perf_counter(); o.step(1); print(time.perf_counter() - t0)") % (ROOT, w.nx, sc)
+            "t0 = time.perf_counter(); o.step(1); print(time.perf_counter() - t0)") % (ROOT, w.nx, sc, path)
     try:
         env = dict(os.environ, OMP_NUM_THREADS="1")
         r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
@@ -91,23 +113,66 @@ def cpu_baseline(w, sc: float, target_s: float = 12.0):
     return out
 
 
+WINDOWS = 5
+
+
+def timed_windows(run, stream, steps, windows=WINDOWS):
+    """Run `steps` steps as `windows` consecutive windows (run(k) issues k steps on `stream`),
+    each bracketed by HIP events; returns the per-step milliseconds of every window."""
+    import torch
+
+    sizes = [steps // windows + (1 if i < steps % windows else 0) for i in range(windows)]
+    sizes = [k for k in sizes if k > 0]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(sizes) + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i, k in enumerate(sizes):
+        run(k)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) / k for i, k in enumerate(sizes)]
+
+
+def median(v):
+    v = sorted(v)
+    m = len(v) // 2
+    return v[m] if len(v) % 2 else 0.5 * (v[m - 1] + v[m])
+
+
+def copy_ceiling(nbytes=2 << 30):
+    """HBM bandwidth of the library's plain device copy (lbmix_device_copy: 16-byte
+    non-temporal loads and stores, each byte read once and written once) of nbytes: the median
+    of 5 timed copies after 2 untimed ones."""
+    import torch
+
+    import paper_1507_04891_amd as P
+
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        P.device_copy(dst, src, stream)
+    ms = timed_windows(lambda k: [P.device_copy(dst, src, stream) for _ in range(k)], stream, 5)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(dst, src))
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = [2 * nbytes / (t * 1e-3) / 1e9 for t in ms]
+    return {"gbs": round(median(gbs), 1), "bytes": nbytes, "kernel": "lbmix_device_copy (plain copy kernel)",
+            "frac_of_peak": round(median(gbs) / HBM_PEAK_GBS, 4), "copy_ok": ok}
+
+
 def time_storage(P, w, storage, steps, warmup, autotune=False, stochastic=None):
-    """Time `steps` steps of the workload with one storage form; one fused launch per step
-    (work-group shape: the library's default, or its autotuner's pick)."""
+    """Time `steps` steps of the workload with one storage form, as 5 windows whose median
+    per-step time is reported; one fused launch per step (work-group shape: the library's
+    default, or its autotuner's pick)."""
     import torch
 
     stream = torch.cuda.current_stream()
     lat = P.from_workload(w, storage=storage, stream=stream, stochastic=stochastic)
     shape = lat.autotune(reps=5) if autotune else None
     lat.step(warmup)
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    lat.step(steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(end)
+    ms = timed_windows(lat.step, stream, steps)
     totals = lat.mass_totals()
     nodes = w.nx * w.ny * w.nz
     assert all(abs(t / (0.5 * nodes) - 1) < 1e-5 for t in totals), (storage, totals)
@@ -115,10 +180,88 @@ def time_storage(P, w, storage, steps, warmup, autotune=False, stochastic=None):
     torch.cuda.empty_cache()
     sites = w.nspecies * nodes
     esize = P.ELEMENT_BYTES[P.STORAGE[storage]]
-    ms_per_step = ms / steps
+    ms_per_step = median(ms)
     achieved = 2 * Q * esize * sites / (ms_per_step * 1e-3) / 1e9   # 19 reads + 19 writes
-    return {"glups": sites * steps / (ms * 1e-3) / 1e9, "ms_per_step": ms_per_step,
-            "achieved_gbs": achieved, "frac": achieved / HBM_PEAK_GBS, "launch": shape}
+    return {"glups": sites / (ms_per_step * 1e-3) / 1e9, "ms_per_step": ms_per_step,
+            "window_ms": [round(t, 5) for t in ms], "achieved_gbs": achieved,
+            "frac": achieved / HBM_PEAK_GBS, "launch": shape}
+
+
+def lattice_config(P, w, storage, steps, warmup, poisson=None, charged=False):
+    """ms/step (median of 5 windows), GLUPS and the step's HBM fraction (the stream-collide's
+    algorithmic bytes, plus the potential read and charge write of a charged run, over the
+    whole step's time) of one workload; with a Poisson solve, its work per step too."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    lat = P.from_workload(w, storage=storage, stream=stream, poisson=poisson)
+    lat.step(warmup)
+    st0 = lat.stats()
+    ms = timed_windows(lat.step, stream, steps)
+    st1 = lat.stats()
+    nodes = int(st1["fluid_nodes"])
+    sites = w.nspecies * nodes
+    esize = P.ELEMENT_BYTES[P.STORAGE[storage]]
+    t = median(ms)
+    nbytes = 2 * Q * esize * sites + (16 * nodes if charged else 0)
+    out = {"storage": storage, "ms_per_step": round(t, 5), "spread_ms": [round(min(ms), 5), round(max(ms), 5)],
+           "glups": round(sites / (t * 1e-3) / 1e9, 3),
+           "step_hbm_frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if poisson:
+        out["poisson"] = poisson.get("method", "sor")
+        out["poisson_work_per_step"] = round((st1["total_sweeps"] - st0["total_sweeps"]) / steps, 2)
+        out["last_residual"] = st1["last_residual"]
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_configs(P, WL, steps, warmup):
+    """Every configuration beyond the headline, each timed as 5 windows of `steps` steps."""
+    import torch
+
+    out = {}
+    mark = lambda k: print(f"config {k} done", file=sys.stderr, flush=True)
+    slit = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    for st in ("f32s", "f16s"):
+        k = f"charged_slit_64x64x130_direct_{st}"
+        out[k] = lattice_config(P, slit, st, steps, warmup, dict(method="direct"), charged=True)
+        mark(k)
+    k = "charged_slit_64x64x130_sor_f32s"
+    out[k] = lattice_config(P, slit, "f32s", steps, warmup,
+                            dict(method="sor", rel_tol=1e-8, max_sweeps=1000000, check_every=10), charged=True)
+    mark(k)
+    k = "charged_slit_64x64x130_sor_f32"
+    out[k] = lattice_config(P, slit, "f32", steps, warmup,
+                            dict(method="sor", rel_tol=1e-8, max_sweeps=1000000, check_every=10), charged=True)
+    mark(k)
+    k = "charged_slit_64x64x130_multigrid_f32s"
+    out[k] = lattice_config(P, slit, "f32s", steps, warmup,
+                            dict(method="multigrid", rel_tol=1e-8, max_sweeps=100000, warm_start="extrapolated"),
+                            charged=True)
+    mark(k)
+    del slit
+    big = WL.charged_slit(nx=128, ny=128, nz=258, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
+    for st in ("f16s", "f32s"):
+        k = f"charged_slit_128x128x258_direct_{st}"
+        out[k] = lattice_config(P, big, st, steps, warmup, dict(method="direct"), charged=True)
+        mark(k)
+    del big
+    ch = WL.batched_channels()
+    for st in ("f32s", "f16s"):
+        k = f"channels_64x32x32xW_direct_{st}"
+        out[k] = lattice_config(P, ch, st, steps, warmup, dict(method="direct"), charged=True)
+        out[k]["fluid_nodes"] = sum(ch.widths) * ch.nx * ch.ny
+        mark(k)
+    del ch
+    w = WL.binary_multimode(n=512, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=100.0, seed=4)
+    for st in ("f16s", "bf16s", "f32s"):
+        k = f"binary_512cubed_{st}"
+        out[k] = lattice_config(P, w, st, steps, warmup)
+        mark(k)
+    del w
+    torch.cuda.empty_cache()
+    return out
 
 
 DTYPE = {"f64": "f64", "f32": "f32", "f32s": "f32", "f16s": "f16", "bf16s": "bf16"}
@@ -337,8 +480,11 @@ def bench_electrokinetics(args):
     out = {"workload": "charged ternary slit 64x64x130 (fluid 64x64x128), lambda_D=8, sigma=-1e-4, E_x=1e-4, "
                        "Sc=100, direct Poisson solve, from rest", "steps": args.steps}
     for name in args.storage.split(","):
-        st, sr = (name[:-3], True) if name.endswith(":sr") else (name, None)
-        lat = P.from_workload(w, storage=st, stream=stream, stochastic=sr, poisson=dict(method="direct"))
+        # storage[:sr][:narrow]: stochastic rounding of an FP32 form; FP32 collision arithmetic
+        st, *flags = name.split(":")
+        sr = True if "sr" in flags else None
+        lat = P.from_workload(w, storage=st, stream=stream, stochastic=sr, poisson=dict(method="direct"),
+                              wide="narrow" not in flags)
         s0 = torch.cuda.Event(enable_timing=True)
         s1 = torch.cuda.Event(enable_timing=True)
         s0.record(stream)
@@ -395,38 +541,41 @@ def bench_precision(args):
     L = 128
     k = 2 * math.pi / L
     basis = np.sin(k * np.arange(L))[None, None, :]
-    forms = [("f64", None), ("f32", None), ("f32s", None), ("f32s", True), ("f16s", True), ("f16s", False),
-             ("bf16s", True)]
-    name = lambda st, sr: st + ("" if sr is None else (" SR" if sr else " RNE"))
+    # (storage, stochastic rounding, density deviation carried in FP64); "narrow": FP32
+    # collision arithmetic throughout
+    forms = [("f64", None, True), ("f32", None, True), ("f32s", None, True), ("f32s", None, False),
+             ("f32s", True, True), ("f16s", True, True), ("f16s", True, False), ("f16s", False, True),
+             ("bf16s", True, True), ("bf16s", True, False)]
+    name = lambda st, sr, wd=True: st + ("" if sr is None else (" SR" if sr else " RNE")) + ("" if wd else " narrow")
     out = {"workload": "D: binary sine 128x64x64 (amp 1e-3); nu: shear wave 128x64x64, tau 0.8; "
                        "mobility: charged slit 16x16x34, lambda_D 4, sigma -1e-4, E_x 1e-5, Sc 100"}
     for sc, t1, t2 in [(10.0, 300, 6300), (100.0, 2000, 22000)]:
         w = WL.binary_sine(L, 64, 64, amp=1e-3, tau_visc=1.0, sc=sc)
-        for st, sr in forms:
-            lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
+        for st, sr, wd in forms:
+            lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, wide=wd)
             lat.step(t1)
             a1 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
             lat.step(t2 - t1)
             a2 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
-            out[f"D Sc={sc:g} {name(st, sr)}"] = -math.log(a2 / a1) / (t2 - t1) / k ** 2 if a2 / a1 > 0 else None
+            out[f"D Sc={sc:g} {name(st, sr, wd)}"] = -math.log(a2 / a1) / (t2 - t1) / k ** 2 if a2 / a1 > 0 else None
             del lat
-            print(f"D Sc={sc:g} {name(st, sr)} done", file=sys.stderr, flush=True)
+            print(f"D Sc={sc:g} {name(st, sr, wd)} done", file=sys.stderr, flush=True)
     shape = (64, 64, L)
     u = np.zeros((3,) + shape)
     u[1] = 1e-3 * basis
     w = WL.Workload("shear", L, 64, 64, "periodic", [0.5, 0.5], [0, 0], 0.8, WL.tau_drag_for_schmidt(0.8, 100.0),
                     [np.full(shape, 0.5)] * 2, [u, u])
-    for st, sr in forms:
-        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7)
+    for st, sr, wd in forms:
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, wide=wd)
         amp = lambda: sum(float((lat.moments(q)[1][1] * basis).sum()) for q in range(2))
         lat.step(100)
         a1 = amp()
         lat.step(3000)
-        out[f"nu {name(st, sr)}"] = -math.log(amp() / a1) / 3000 / k ** 2
+        out[f"nu {name(st, sr, wd)}"] = -math.log(amp() / a1) / 3000 / k ** 2
         del lat
     w = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
-    for st, sr in forms:
-        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, poisson=dict(method="direct"))
+    for st, sr, wd in forms:
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, poisson=dict(method="direct"), wide=wd)
         lat.step(28000)
         acc = None
         for _ in range(20):
@@ -435,9 +584,9 @@ def bench_precision(args):
             acc = pr if acc is None else acc + pr
         pr = acc / 20
         rho = pr[:, 0, 1:-1].sum(0)
-        out[f"mobility {name(st, sr)}"] = float(pr[:, 1, 1:-1].sum(0)[16] / rho[16] / 1e-5)
+        out[f"mobility {name(st, sr, wd)}"] = float(pr[:, 1, 1:-1].sum(0)[16] / rho[16] / 1e-5)
         del lat
-        print(f"mobility {name(st, sr)} done", file=sys.stderr, flush=True)
+        print(f"mobility {name(st, sr, wd)} done", file=sys.stderr, flush=True)
     for key in list(out):
         if key == "workload" or " f64" in key or out[key] is None:
             continue
@@ -457,6 +606,11 @@ def main():
     ap.add_argument("--sc", type=float, default=100.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (slits, channels, 512^3)")
+    ap.add_argument("--no-copy-ceiling", action="store_true")
+    ap.add_argument("--config-steps", type=int, default=20, help="timed steps of each other configuration")
+    ap.add_argument("--config-warmup", type=int, default=5)
     ap.add_argument("--graph", action="store_true", help="replay steps as captured HIP graphs")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library pick the work-group shape of the step (default: its default shape)")
@@ -524,7 +678,9 @@ def main():
         "config": {"workload": f"neutral binary D3Q19 {args.n}^3 periodic, {args.storage} populations, "
                                f"Sc={args.sc:g}, tau_visc=1, multimode noise + shear wave (seed 2)",
                    "species": 2, "lattice": [args.n] * 3, "storage": args.storage, "schmidt": args.sc,
-                   "launch": head["launch"]},
+                   "launch": head["launch"], "timing": f"median per-step time of {WINDOWS} windows over "
+                                                       f"the {args.steps} timed steps"},
+        "window_ms_per_step": head["window_ms"],
         "roofline": {"bound": "hbm", "achieved": round(head["achieved_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(head["frac"], 4),
                      "traffic": traffic_from_profile(args.storage, args.n)},
@@ -536,14 +692,18 @@ def main():
                 continue
             r = time_storage(P, w, st, args.steps, args.warmup, autotune=args.autotune)
             var[st] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
-                       "hbm_frac": round(r["frac"], 4),
+                       "window_ms_per_step": r["window_ms"], "hbm_frac": round(r["frac"], 4),
                        "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}
-        # shifted FP32 with FP64 arithmetic and stochastically rounded stores
+        # shifted FP32 with stochastically rounded stores
         r = time_storage(P, w, "f32s", args.steps, args.warmup, autotune=args.autotune, stochastic=True)
         var["f32s_stochastic"] = {"glups": round(r["glups"], 3), "ms_per_step": round(r["ms_per_step"], 5),
-                                  "hbm_frac": round(r["frac"], 4),
+                                  "window_ms_per_step": r["window_ms"], "hbm_frac": round(r["frac"], 4),
                                   "speedup_vs_headline": round(r["glups"] / head["glups"], 3), "launch": r["launch"]}
         out["variants"] = var
+    if not args.no_copy_ceiling:
+        cc = copy_ceiling()
+        cc["headline_frac_of_copy"] = round(head["achieved_gbs"] / cc["gbs"], 4)
+        out["roofline"]["copy_ceiling"] = cc
     if args.copy_probe > 0:
         nbytes = int(args.copy_probe * 2 ** 30)
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -553,6 +713,11 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = nbytes
         del src, dst
+    if not args.no_configs:
+        del w
+        torch.cuda.empty_cache()
+        out["configs"] = bench_configs(P, WL, args.config_steps, args.config_warmup)
+        w = WL.binary_multimode(n=args.n, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=args.sc, seed=2)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.sc)
     print(json.dumps(out), flush=True)

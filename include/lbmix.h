@@ -317,6 +317,18 @@ int lbmix_train_warm_start(lbmix_ctx *ctx, lbmix_net *net, int nsteps, float lr,
  * mode 1 with FP64 storage; ESTATE for a change of mode after the first step. */
 int lbmix_set_rounding(lbmix_ctx *ctx, int mode, unsigned long long seed);
 
+/* Arithmetic of the collision in the FP32 and 16-bit storage forms (nearest rounding, and the
+ * 16-bit forms with stochastic rounding).  mode 1 (default): the density deviation of each
+ * node and species, dn = sum_p (f_p - w_p rho0), and the term w_p omega_visc dn of the update
+ * (eq. latboeq with the equilibrium of the Appendix, whose density part is w_p n) are carried
+ * beyond FP32 (an FP64 sum; for the 16-bit forms an FP64 combination of exact FP32 sums per
+ * weight class), so the deterministic FP32 rounding of w_p omega_visc dn does not bias slow
+ * modes; everything else is FP32.  mode 0: FP32 collision arithmetic throughout, FP64 only for
+ * the mass totals, the charge density and the Poisson solve.  No effect on FP64 storage or on
+ * the FP32 forms with stochastic rounding (FP64 arithmetic).  Errors: EINVAL for another mode;
+ * ESTATE for a change of mode after the first step. */
+int lbmix_set_arithmetic(lbmix_ctx *ctx, int mode);
+
 /* FP16 storage scale of one species: the bound `rel_range` of |f_p - w_p rho0| / (w_p rho0)
  * the lattice is expected to reach (default 0.1).  The power-of-two scale per direction
  * maps that bound near 2^12, leaving a factor 16 of headroom below the FP16 maximum and
@@ -370,6 +382,14 @@ int lbmix_get_zprofiles(lbmix_ctx *ctx, double *out);
 
 /* Counters of the context. */
 int lbmix_get_stats(lbmix_ctx *ctx, lbmix_stats *out);
+
+/* Plain device copy of `bytes` bytes from src to dst (device pointers, 16-byte aligned, bytes
+ * a multiple of 16, not overlapping) on the hipStream_t `stream` (NULL: the null stream),
+ * with 16-byte non-temporal loads and stores.  It is the copy kernel whose bandwidth the
+ * fused step's HBM bandwidth is compared with (each byte read once and written once, as each
+ * population is by the step).  Errors: EINVAL for null or misaligned pointers or a size that
+ * is not a multiple of 16; EDEVICE for a launch failure. */
+int lbmix_device_copy(void *dst, const void *src, unsigned long long bytes, void *stream);
 
 /* Block until all work issued on the context stream has finished. */
 int lbmix_sync(lbmix_ctx *ctx);

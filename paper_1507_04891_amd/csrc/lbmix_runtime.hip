@@ -75,6 +75,7 @@ struct lbmix_ctx {
     int have_prev = 0;
     int mg_last = 0;                  // V-cycles of the last multigrid solve
     int rounding = 0;                 // FP32 and 16-bit forms: 0 nearest-even, 1 stochastic
+    int wide = 1;                     // FP32 and 16-bit forms: density deviation carried in FP64
     unsigned long long round_seed = 0;
     int sor_max = 200000, sor_check = 10;
     // device
@@ -207,6 +208,13 @@ struct lbmix_ctx {
                 a.inv_scale[s][p] = inv_scale[s][p];
             }
             if (s < ns) a.q_rest += valence[s] * a.rho_bar[s];
+            for (int k = 0; k < 3; ++k) {
+                const int rep = k == 0 ? 0 : (k == 1 ? 1 : 7);
+                a.cw[s][k] = kW[rep] * (double)scale[s][rep];
+                a.cwo[s][k] = kW[rep] * (1.0 / tau_v) * (double)scale[s][rep];
+                a.cwf[s][k] = (float)a.cw[s][k];
+                a.cwof[s][k] = (float)a.cwo[s][k];
+            }
         }
         a.omega_v = 1.0 / tau_v;
         a.omega_d = omega_drag();
@@ -223,6 +231,7 @@ struct lbmix_ctx {
         a.nzfull = (uint32_t)nz;
         a.partials = step_partials;
         a.stochastic = rounding;
+        a.wide = wide;
         a.block_x = blk_x;
         a.block_y = blk_y;
         a.seed = step_seed(round_seed, (unsigned long long)(steps + 1));
@@ -1104,6 +1113,7 @@ struct Header {
     int64_t steps;
     int32_t pair_ns, forcing;
     double tau_pair[MAXS * MAXS];
+    int32_t wide, pad;
 };
 
 }  // namespace
@@ -1426,6 +1436,15 @@ int lbmix_set_rounding(lbmix_ctx *c, int mode, unsigned long long seed) {
         return c->fail(LBMIX_ESTATE, "the rounding mode is fixed once stepping has started");
     c->rounding = mode;
     c->round_seed = seed;
+    return LBMIX_OK;
+}
+
+int lbmix_set_arithmetic(lbmix_ctx *c, int mode) {
+    if (!c) return LBMIX_EINVAL;
+    if (mode != 0 && mode != 1) return c->fail(LBMIX_EINVAL, "arithmetic mode is 0 or 1");
+    if (c->started && mode != c->wide)
+        return c->fail(LBMIX_ESTATE, "the arithmetic mode is fixed once stepping has started");
+    c->wide = mode;
     return LBMIX_OK;
 }
 
@@ -1771,6 +1790,13 @@ int lbmix_get_stats(lbmix_ctx *c, lbmix_stats *out) {
     return LBMIX_OK;
 }
 
+int lbmix_device_copy(void *dst, const void *src, unsigned long long bytes, void *stream) {
+    if (!dst || !src || bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0) return LBMIX_EINVAL;
+    if (bytes == 0) return LBMIX_OK;
+    const hipError_t e = launch_copy16(src, dst, (size_t)(bytes / 16), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? LBMIX_OK : LBMIX_EDEVICE;
+}
+
 int lbmix_sync(lbmix_ctx *c) {
     if (!c) return LBMIX_EINVAL;
     if (!c->allocated) return LBMIX_OK;
@@ -1786,11 +1812,13 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 4;
+    h.version = 5;
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
     h.nch = c->nch;
     h.pair_ns = c->pair_ns;
     h.forcing = c->forcing;
+    h.wide = c->wide;
+    h.pad = 0;
     for (int a = 0; a < MAXS; ++a)
         for (int b = 0; b < MAXS; ++b) h.tau_pair[a * MAXS + b] = c->tau_pair[a][b];
     for (int s = 0; s < MAXS; ++s) {
@@ -1837,7 +1865,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 4;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 5;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
          h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
     constexpr int kPerChan = 4 + MAXS;
@@ -1871,6 +1899,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     for (int d = 0; d < 3; ++d) c->E[d] = h.E[d];
     c->pair_ns = h.pair_ns;
     c->forcing = h.forcing;
+    c->wide = h.wide;
     for (int a = 0; a < MAXS; ++a)
         for (int b = 0; b < MAXS; ++b) c->tau_pair[a][b] = h.tau_pair[a * MAXS + b];
     for (int ch = 0; ch < c->nch; ++ch) {

@@ -39,6 +39,10 @@ struct StepArgs {
     double rho_bar[MAXS];            // storage shift per species (0: plain f)
     float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)
     float inv_scale[MAXS][Q];
+    // per species and weight class k (rest, axis, diagonal): w_k scale_k and
+    // w_k omega_visc scale_k, in FP64 and FP32
+    double cw[MAXS][3], cwo[MAXS][3];
+    float cwf[MAXS][3], cwof[MAXS][3];
     double omega_v, omega_d;
     int pair_drag;                   // 1: drag frequency per pair (three or more species)
     double omega_pair[MAXS][MAXS];   // symmetric; the diagonal is not used
@@ -53,6 +57,8 @@ struct StepArgs {
     uint32_t nzfull;                 // planes of the full-lattice arrays
     double *partials;                // out: [species][block] FP64 sums of n - rho_bar
     int stochastic;                  // 16-bit forms: 1 = stochastic rounding, 0 = nearest-even
+    int wide;                        // FP32 / 16-bit forms: 1 = density deviation carried in FP64,
+                                     // 0 = FP32 collision arithmetic throughout
     uint32_t seed;                   // per-step seed of the rounding hash
     const unsigned long long *step_dev;  // non-null (captured steps): seed from the step count
     unsigned long long round_seed;       // ... here, as the host derives it
@@ -77,6 +83,9 @@ __host__ __device__ inline uint32_t step_seed(unsigned long long seed, unsigned 
     z ^= z >> 31;
     return (uint32_t)(z ^ (z >> 32));
 }
+
+// Plain device copy of n16 16-byte elements (16-byte aligned buffers).
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, hipStream_t stream);
 
 // *step += 1 (one thread): the step count of captured steps; set_step: *step = value.
 hipError_t launch_advance_step(unsigned long long *step, hipStream_t stream);

@@ -211,6 +211,34 @@ hipError_t launch_set_step(unsigned long long *step, unsigned long long value, h
     return hipGetLastError();
 }
 
+// Plain device copy, 16-byte non-temporal loads and stores, four in flight per thread (the
+// ceiling the fused step's HBM bandwidth is compared with).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(BLOCK) void copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n) {
+    const size_t stride = (size_t)gridDim.x * BLOCK;
+    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const u32x4 a0 = __builtin_nontemporal_load(src + i);
+        const u32x4 a1 = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 a2 = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 a3 = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a0, dst + i);
+        __builtin_nontemporal_store(a1, dst + i + stride);
+        __builtin_nontemporal_store(a2, dst + i + 2 * stride);
+        __builtin_nontemporal_store(a3, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, hipStream_t stream) {
+    size_t blocks = (n16 + 4 * BLOCK - 1) / (4 * BLOCK);
+    if (blocks > 256 * 32) blocks = 256 * 32;   // 32 work-groups per compute unit, then grid-stride
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(copy16, dim3((uint32_t)blocks), dim3(BLOCK), 0, stream, static_cast<const u32x4 *>(src),
+                       static_cast<u32x4 *>(dst), n16);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(Store st, bool slit, int s, const StepArgs &a, const double *n, const double *u,
                        hipStream_t stream) {
     return by_store<InitK>(st, slit, s, a, n, u, stream);

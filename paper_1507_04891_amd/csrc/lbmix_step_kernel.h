@@ -52,7 +52,12 @@ __host__ __device__ constexpr C wgt(int p) {
 
 // ---------------------------------------------------------------------------------------
 // Storage codecs.  C is the arithmetic type, S the stored element; a stored element is
-// (f - w rho_bar) * scale.
+// (f - w rho_bar) * scale.  raw / put convert between S and C in stored units (the fused
+// step works in those); decode / encode apply the scale too (the other kernels).
+//   kScaled: the stored values carry a power-of-two scale per species and weight class;
+//   kWide: how the fused step carries the density deviation beyond C when asked to:
+//     0 C is FP64 already; 1 an FP64 sum of every population; 2 an FP64 combination of the
+//     three per-class FP32 sums, which are exact for 16-bit values of similar magnitude.
 
 struct BF16 {};
 struct F16 {};
@@ -63,7 +68,12 @@ template <> struct Codec<double> {
     using C = double;
     using S = double;
     static constexpr bool kRounds = false;
-    static constexpr bool kWideSum = true;   // density deviation summed in FP64
+    static constexpr bool kScaled = false;
+    static constexpr bool kPacked = false;
+    static constexpr int kWide = 0;
+    __device__ static C raw(S v) { return v; }
+    template <bool SR = false>
+    __device__ static S put(C v, uint32_t = 0) { return v; }
     __device__ static C decode(S v, float) { return v; }
     template <bool SR = false>
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
@@ -72,7 +82,12 @@ template <> struct Codec<float> {
     using C = float;
     using S = float;
     static constexpr bool kRounds = false;
-    static constexpr bool kWideSum = true;   // density deviation summed in FP64
+    static constexpr bool kScaled = false;
+    static constexpr bool kPacked = false;
+    static constexpr int kWide = 1;
+    __device__ static C raw(S v) { return v; }
+    template <bool SR = false>
+    __device__ static S put(C v, uint32_t = 0) { return v; }
     __device__ static C decode(S v, float) { return v; }
     template <bool SR = false>
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
@@ -108,9 +123,13 @@ __device__ inline uint16_t f32_to_bf16_rne(float f) {
 // random 32-bit operand below the kept mantissa and truncate, so the magnitude goes up with
 // probability equal to the dropped fraction and the expected stored value is the exact one
 // (checked on the device: mean error below 0.003 unit in the last place over 65536 draws,
-// binary16 subnormals included; only the operand's high bits are used).
+// binary16 subnormals included; only the operand's high bits are used).  Each conversion
+// writes one half of a 32-bit register and keeps the other, so a species pair is converted
+// straight into the packed word that is stored.
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 __device__ inline uint16_t f32_to_bf16_sr(float f, uint32_t rnd) {
     bf16x2 t = {};
     t = __builtin_amdgcn_cvt_sr_bf16_f32(t, f, rnd, false);
@@ -126,25 +145,48 @@ template <> struct Codec<BF16> {
     using C = float;
     using S = uint16_t;
     static constexpr bool kRounds = true;
-    static constexpr bool kWideSum = false;  // density deviation summed in FP32
-    __device__ static C decode(S v, float inv) { return __uint_as_float(uint32_t(v) << 16) * inv; }
+    static constexpr bool kScaled = false;
+    static constexpr bool kPacked = true;
+    static constexpr int kWide = 2;
+    __device__ static C raw(S v) { return __uint_as_float(uint32_t(v) << 16); }
     template <bool SR = false>
-    __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
-        if constexpr (SR) return f32_to_bf16_sr(v * sc, rnd);
-        else return f32_to_bf16_rne(v * sc);
+    __device__ static S put(C v, uint32_t rnd = 0) {
+        if constexpr (SR) return f32_to_bf16_sr(v, rnd);
+        else return f32_to_bf16_rne(v);
     }
+    // stochastically rounded pair (lo, hi) in one word
+    __device__ static u16x2 put_pair_sr(C lo, C hi, uint32_t rlo, uint32_t rhi) {
+        bf16x2 t = {};
+        t = __builtin_amdgcn_cvt_sr_bf16_f32(t, lo, rlo, false);
+        t = __builtin_amdgcn_cvt_sr_bf16_f32(t, hi, rhi, true);
+        return __builtin_bit_cast(u16x2, t);
+    }
+    __device__ static C decode(S v, float inv) { return raw(v) * inv; }
+    template <bool SR = false>
+    __device__ static S encode(C v, float sc, uint32_t rnd = 0) { return put<SR>(v * sc, rnd); }
 };
 template <> struct Codec<F16> {
     using C = float;
     using S = uint16_t;
     static constexpr bool kRounds = true;
-    static constexpr bool kWideSum = true;   // density deviation summed in FP64
-    __device__ static C decode(S v, float inv) { return __half2float(__ushort_as_half(v)) * inv; }
+    static constexpr bool kScaled = true;
+    static constexpr bool kPacked = true;
+    static constexpr int kWide = 2;
+    __device__ static C raw(S v) { return __half2float(__ushort_as_half(v)); }
     template <bool SR = false>
-    __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
-        if constexpr (SR) return f32_to_f16_sr(v * sc, rnd);
-        else return __half_as_ushort(__float2half_rn(v * sc));   // IEEE nearest-even
+    __device__ static S put(C v, uint32_t rnd = 0) {
+        if constexpr (SR) return f32_to_f16_sr(v, rnd);
+        else return __half_as_ushort(__float2half_rn(v));   // IEEE nearest-even
     }
+    __device__ static u16x2 put_pair_sr(C lo, C hi, uint32_t rlo, uint32_t rhi) {
+        f16x2 t = {};
+        t = __builtin_amdgcn_cvt_sr_f16_f32(t, lo, rlo, false);
+        t = __builtin_amdgcn_cvt_sr_f16_f32(t, hi, rhi, true);
+        return __builtin_bit_cast(u16x2, t);
+    }
+    __device__ static C decode(S v, float inv) { return raw(v) * inv; }
+    template <bool SR = false>
+    __device__ static S encode(C v, float sc, uint32_t rnd = 0) { return put<SR>(v * sc, rnd); }
 };
 
 // FP32 storage, stochastically rounded from FP64 arithmetic: the nearest FP32 value f of v and
@@ -171,14 +213,25 @@ template <> struct Codec<F32X> {
     using C = double;
     using S = float;
     static constexpr bool kRounds = true;
-    static constexpr bool kWideSum = true;
+    static constexpr bool kScaled = false;
+    static constexpr bool kPacked = false;
+    static constexpr int kWide = 0;
+    __device__ static C raw(S v) { return double(v); }
+    template <bool SR = false>
+    __device__ static S put(C v, uint32_t rnd = 0) {
+        if constexpr (SR) return f64_to_f32_sr(v, rnd);
+        else return float(v);
+    }
     __device__ static C decode(S v, float inv) { return double(v) * double(inv); }
     template <bool SR = false>
-    __device__ static S encode(C v, float sc, uint32_t rnd = 0) {
-        if constexpr (SR) return f64_to_f32_sr(v * double(sc), rnd);
-        else return float(v * double(sc));
-    }
+    __device__ static S encode(C v, float sc, uint32_t rnd = 0) { return put<SR>(v * double(sc), rnd); }
 };
+
+// The stochastically rounded pair of a packed codec (instantiated only for those).
+template <class CD>
+__device__ __forceinline__ u16x2 put_pair_sr(float lo, float hi, uint32_t rlo, uint32_t rhi) {
+    return CD::put_pair_sr(lo, hi, rlo, rhi);
+}
 
 // Species-interleaved layout: the NS values of one direction at one node are contiguous,
 // element (s, p, node) at ((p * N) + node) * NS + s.  One vector access per direction and
@@ -189,8 +242,6 @@ typedef float f32x3 __attribute__((ext_vector_type(3), aligned(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
-typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 template <class S, int NS> struct VecIO {
     __device__ static void load(const S *p, S (&o)[NS]) {
@@ -298,6 +349,11 @@ enum : int {
     kDragGuo = 2,    // one frequency, second-order (Guo-type) forcing
 };
 
+// Weight class of direction p: 0 rest, 1 the axis directions, 2 the face diagonals.  A
+// class shares the lattice weight and, in the scaled storage forms, the storage scale.
+__host__ __device__ constexpr int wclass(int p) { return p == 0 ? 0 : (p < 7 ? 1 : 2); }
+constexpr int kClassRep[3] = {0, 1, 7};   // a direction of each class
+
 template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED, int DRAG>
 __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     using CD = Codec<T>;
@@ -313,9 +369,15 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     const uint32_t own_in = pl.own_inplane();
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
+    // FP64 carry of the density deviation (uniform; see step 2)
+    const bool wide = CD::kWide != 0 && a.wide != 0;
 
-    // 1. pull streaming with bounce-back: one vector load of all species per direction
-    C d[NS][Q];
+    // inverse storage scale of each species and weight class (1 in the unscaled forms)
+    auto isc = [&](int s, int k) -> C { return CD::kScaled ? C(a.inv_scale[s][kClassRep[k]]) : C(1); };
+
+    // 1. pull streaming with bounce-back: one vector load of all species per direction; the
+    //    values stay in stored units (h = d * scale)
+    C h[NS][Q];
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
@@ -324,46 +386,61 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         S raw[NS];
         VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
 #pragma unroll
-        for (int s = 0; s < NS; ++s) d[s][p] = CD::decode(raw[s], a.inv_scale[s][arr]);
+        for (int s = 0; s < NS; ++s) h[s][p] = CD::raw(raw[s]);
     });
 
-    // 2. moments (Sec. III): n = rho_bar + sum d, j = sum d c.  The density deviation is also
-    //    summed in FP64 (dnh): with deviations stored, the update of a direction is
-    //    w dn + (flux and force terms), and FP32 rounding at the scale of w dn would be about
-    //    1 % of the per-step change of a slow diffusion mode at Sc = 100.  That rounding is
-    //    deterministic, so it biases slow modes where stochastic rounding of the stored values
-    //    only adds noise that averages out: with FP32 sums the spread of the FP16 form's
-    //    electro-osmotic mobility over rounding seeds grows by 40 %.  BF16 storage is the
-    //    exception: its own rounding noise is 8 times FP16's and the FP32 sum leaves its
-    //    spread unchanged, so it keeps the FP32 sum.
+    // 2. moments (Sec. III): n = rho_bar + dn, dn = sum d, j = sum d c, formed per weight class
+    //    (the classes share a storage scale, so each class sum is scaled once).  The density
+    //    deviation is also carried in FP64 (dnh) unless the FP32 form is asked for: with
+    //    deviations stored, the update of a direction is w dn + (flux and force terms), and
+    //    FP32 rounding at the scale of w dn is deterministic, where stochastic rounding of the
+    //    stored values only adds noise that averages out, so it would bias slow modes (about 1 %
+    //    of the per-step change of a slow diffusion mode at Sc = 100).  The 16-bit forms get dnh
+    //    from the three FP32 class sums, which hold their 8- or 11-bit values exactly unless the
+    //    values of a class span more than 2^13 (FP16) or 2^16 (BF16).
     C dn[NS], jx[NS], jy[NS], jz[NS], n[NS];
     double dnh[NS];
     C ntot = 0, sjx = 0, sjy = 0, sjz = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        C m0 = 0, mx = 0, my = 0, mz = 0;
-        double m0h = 0.0;
-        static_for<Q>([&](auto pc) {
-            constexpr int p = decltype(pc)::value;
-            m0 += d[s][p];
-            if constexpr (CD::kWideSum) m0h += double(d[s][p]);
-            if constexpr (cx(p) == 1) mx += d[s][p];
-            if constexpr (cx(p) == -1) mx -= d[s][p];
-            if constexpr (cy(p) == 1) my += d[s][p];
-            if constexpr (cy(p) == -1) my -= d[s][p];
-            if constexpr (cz(p) == 1) mz += d[s][p];
-            if constexpr (cz(p) == -1) mz -= d[s][p];
-        });
-        dn[s] = m0;
-        dnh[s] = CD::kWideSum ? m0h : double(m0);
-        jx[s] = mx;
-        jy[s] = my;
-        jz[s] = mz;
-        n[s] = C(a.rho_bar[s]) + m0;
+        const C *v = h[s];
+        const C m1 = ((v[1] + v[2]) + (v[3] + v[4])) + (v[5] + v[6]);
+        const C m2 = (((v[7] + v[8]) + (v[9] + v[10])) + ((v[11] + v[12]) + (v[13] + v[14]))) +
+                     ((v[15] + v[16]) + (v[17] + v[18]));
+        const C d78 = v[7] - v[8], d910 = v[9] - v[10], d1112 = v[11] - v[12];
+        const C d1314 = v[13] - v[14], d1516 = v[15] - v[16], d1718 = v[17] - v[18];
+        const C x2 = (d78 + d910) + (d1112 + d1314);
+        const C y2 = (d78 - d910) + (d1516 + d1718);
+        const C z2 = (d1112 - d1314) + (d1516 - d1718);
+        if constexpr (CD::kScaled) {
+            dn[s] = (v[0] * isc(s, 0) + m1 * isc(s, 1)) + m2 * isc(s, 2);
+            jx[s] = (v[1] - v[2]) * isc(s, 1) + x2 * isc(s, 2);
+            jy[s] = (v[3] - v[4]) * isc(s, 1) + y2 * isc(s, 2);
+            jz[s] = (v[5] - v[6]) * isc(s, 1) + z2 * isc(s, 2);
+        } else {
+            dn[s] = (v[0] + m1) + m2;
+            jx[s] = (v[1] - v[2]) + x2;
+            jy[s] = (v[3] - v[4]) + y2;
+            jz[s] = (v[5] - v[6]) + z2;
+        }
+        dnh[s] = double(dn[s]);
+        if constexpr (CD::kWide == 1) {
+            if (wide) {
+                double t = 0.0;
+#pragma unroll
+                for (int p = 0; p < Q; ++p) t += double(v[p]);
+                dnh[s] = t;
+            }
+        } else if constexpr (CD::kWide == 2) {
+            if (wide)
+                dnh[s] = (double(v[0]) * double(isc(s, 0)) + double(m1) * double(isc(s, 1))) +
+                         double(m2) * double(isc(s, 2));
+        }
+        n[s] = C(a.rho_bar[s]) + dn[s];
         ntot += n[s];
-        sjx += mx;
-        sjy += my;
-        sjz += mz;
+        sjx += jx[s];
+        sjy += jy[s];
+        sjz += jz[s];
     }
     const C inv_ntot = ntot != C(0) ? C(1) / ntot : C(0);
     C ux = sjx * inv_ntot, uy = sjy * inv_ntot, uz = sjz * inv_ntot;   // barycentric
@@ -403,8 +480,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     //    Guo-type variant), then the coefficients of the collision that are common to
     //    every direction
     const C ov = C(a.omega_v), od = C(SLIT ? a.planes[z].omega_d : a.omega_d);
-    C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS], base[NS], ov45[NS], n9[NS], n3[NS];
-    C bhi[NS][3], blo[NS][3];   // w ov dn (FP64) split hi + lo for the three weight classes
+    C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const C inv_n = n[s] != C(0) ? C(1) / n[s] : C(0);
@@ -429,10 +505,10 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         C vx[NS], vy[NS], vz[NS];
 #pragma unroll
         for (int b = 0; b < NS; ++b) {
-            const C h = FIELD ? C(0.5) * C(a.valence[b]) : C(0);
-            vx[b] = uax[b] + h * fx;
-            vy[b] = uay[b] + h * fy;
-            vz[b] = uaz[b] + h * fz;
+            const C hb = FIELD ? C(0.5) * C(a.valence[b]) : C(0);
+            vx[b] = uax[b] + hb * fx;
+            vy[b] = uay[b] + hb * fy;
+            vz[b] = uaz[b] + hb * fz;
         }
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -478,28 +554,42 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         uy += C(0.5) * kbar * fy;
         uz += C(0.5) * kbar * fz;
     }
+
+    // Collision coefficients per species and weight class k, in stored units (W_k = w_k x the
+    // class's storage scale):
+    //   f*_p = (1 - ov) d_p + W_k [base + 4.5 ov n (c.u_s)^2 + 9 n (c.F)(c.u)]
+    //          +- 3 W_k n (ov c.u_s + c.F) + W_k ov dn
+    // The last term is split hi + lo: lo joins the symmetric part B_k, hi is added last, so the
+    // stored value rounds like the FP64 sum (the other terms are far below hi, or carry their
+    // own FP32 rounding).
+    C B[NS][3], O[NS][3], N9[NS][3], M3[NS][3], bhi[NS][3];
+    constexpr bool kF64 = sizeof(C) == 8;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const C uu = uax[s] * uax[s] + uay[s] * uay[s] + uaz[s] * uaz[s];
         const C Fu = Fx[s] * ux + Fy[s] * uy + Fz[s] * uz;
-        // f*_p = [(1 - ov) d_p + w (base + ov45 (c.u_s)^2 + n9 (c.F)(c.u)) +- w n3 (ov c.u_s + c.F)]
-        //        + w ov dn, the last term in FP64, added as hi + lo: (t + lo) + hi rounds like the
-        //        FP64 sum (t is far below the scale of hi, or carries its own FP32 rounding)
-        base[s] = -C(1.5) * ov * n[s] * uu - C(3) * n[s] * Fu;
+        const C base = -C(1.5) * ov * n[s] * uu - C(3) * n[s] * Fu;
+        const C t45 = C(4.5) * ov * n[s], t9 = C(9) * n[s], t3 = C(3) * n[s];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double big = wgt<double>(k == 0 ? 0 : (k == 1 ? 1 : 7)) * a.omega_v * dnh[s];
-            bhi[s][k] = C(big);
-            blo[s][k] = CD::kWideSum ? C(big - double(bhi[s][k])) : C(0);
+            const C W = kF64 ? C(a.cw[s][k]) : C(a.cwf[s][k]);          // w_k scale_k
+            B[s][k] = W * base;
+            O[s][k] = W * t45;
+            N9[s][k] = W * t9;
+            M3[s][k] = W * t3;
+            if (wide) {
+                const double big = a.cwo[s][k] * dnh[s];                  // w_k ov scale_k dn
+                bhi[s][k] = C(big);
+                B[s][k] += C(big - double(bhi[s][k]));
+            } else {
+                bhi[s][k] = (kF64 ? C(a.cwo[s][k]) : C(a.cwof[s][k])) * dn[s];
+            }
         }
-        ov45[s] = C(4.5) * ov * n[s];
-        n9[s] = C(9) * n[s];
-        n3[s] = C(3) * n[s];
     }
 
     // 5. collision and store, one direction pair at a time, all species per vector store.
-    //    Stochastic rounding (16-bit forms) draws 32 random bits per direction from a
-    //    per-node xorshift stream, 16 bits per species of each pair.
+    //    Stochastic rounding draws 32 random bits per direction from a per-node xorshift
+    //    stream, 16 bits per species of each pair.
     const C keep = C(1) - ov;
     auto collide_store = [&](auto sr_tag) {
         constexpr bool SR = decltype(sr_tag)::value;
@@ -510,41 +600,47 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             if ((s & 1) == 0) rs = xorshift32(rs);
             return (s & 1) ? (rs << 16) : rs;
         };
-        auto plus_dn = [&](C v, int s, int cls) -> C {   // + w ov dn (hi + lo with the FP64 sum)
-            if constexpr (CD::kWideSum)
-                return (v + blo[s][cls]) + bhi[s][cls];
-            else
-                return v + bhi[s][cls];
-        };
-        S o0[NS];
+        // encode the values of direction P and store them with one vector store
+        auto put_all = [&](auto pc, const C (&v)[NS]) {
+            constexpr int p = decltype(pc)::value;
+            S o[NS];
+            if constexpr (SR && CD::kPacked && NS % 2 == 0) {
 #pragma unroll
-        for (int s = 0; s < NS; ++s)
-            o0[s] = CD::template encode<SR>(plus_dn(keep * d[s][0] + wgt<C>(0) * base[s], s, 0),
-                                            a.scale[s][0], rbits(s));
-        VecIO<S, NS>::store(slot<NS>(fout, 0, pl.p0, own_in, a.N), o0);
+                for (int s = 0; s < NS; s += 2) {
+                    const uint32_t r0 = rbits(s), r1 = rbits(s + 1);
+                    const u16x2 pr = put_pair_sr<CD>(v[s], v[s + 1], r0, r1);
+                    o[s] = pr[0];
+                    o[s + 1] = pr[1];
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < NS; ++s) o[s] = CD::template put<SR>(v[s], rbits(s));
+            }
+            VecIO<S, NS>::store(slot<NS>(fout, p, pl.p0, own_in, a.N), o);
+        };
+        {
+            C v0[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) v0[s] = (keep * h[s][0] + B[s][0]) + bhi[s][0];
+            put_all(std::integral_constant<int, 0>{}, v0);
+        }
         static_for<9>([&](auto kc) {
             constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
             constexpr int pb = p + 1;
-            constexpr C w = wgt<C>(p);
-            constexpr int cls = p < 7 ? 1 : 2;
-            S op[NS], ob[NS];
+            constexpr int k = wclass(p);
+            const C cub = C(cx(p)) * ux + C(cy(p)) * uy + C(cz(p)) * uz;
             C vp[NS], vb[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const C cu = C(cx(p)) * uax[s] + C(cy(p)) * uay[s] + C(cz(p)) * uaz[s];
-                const C cub = C(cx(p)) * ux + C(cy(p)) * uy + C(cz(p)) * uz;
                 const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
-                const C sym = w * (base[s] + ov45[s] * cu * cu + n9[s] * cF * cub);
-                const C anti = w * n3[s] * (ov * cu + cF);
-                vp[s] = plus_dn(keep * d[s][p] + sym + anti, s, cls);
-                vb[s] = plus_dn(keep * d[s][pb] + sym - anti, s, cls);
+                const C sym = (B[s][k] + O[s][k] * (cu * cu)) + N9[s][k] * (cF * cub);
+                const C anti = M3[s][k] * (ov * cu + cF);
+                vp[s] = ((keep * h[s][p] + sym) + anti) + bhi[s][k];
+                vb[s] = ((keep * h[s][pb] + sym) - anti) + bhi[s][k];
             }
-#pragma unroll
-            for (int s = 0; s < NS; ++s) op[s] = CD::template encode<SR>(vp[s], a.scale[s][p], rbits(s));
-#pragma unroll
-            for (int s = 0; s < NS; ++s) ob[s] = CD::template encode<SR>(vb[s], a.scale[s][pb], rbits(s));
-            VecIO<S, NS>::store(slot<NS>(fout, p, pl.p0, own_in, a.N), op);
-            VecIO<S, NS>::store(slot<NS>(fout, pb, pl.p0, own_in, a.N), ob);
+            put_all(std::integral_constant<int, p>{}, vp);
+            put_all(std::integral_constant<int, pb>{}, vb);
         });
     };
     if (active) {

@@ -30,9 +30,9 @@ EXPORTS = (
     "lbmix_set_tau_visc", "lbmix_set_tau_drag", "lbmix_set_schmidt", "lbmix_set_drag_pairs", "lbmix_set_forcing",
     "lbmix_set_electrostatics",
     "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
-    "lbmix_set_storage_range", "lbmix_set_state", "lbmix_autotune", "lbmix_set_step_graph", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
+    "lbmix_set_storage_range", "lbmix_set_arithmetic", "lbmix_set_state", "lbmix_autotune", "lbmix_set_step_graph", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
     "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
-    "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_save", "lbmix_load",
+    "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_device_copy", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
     "lbmix_net_create", "lbmix_net_num_params", "lbmix_net_get_params", "lbmix_net_set_params",
     "lbmix_net_get_gradient", "lbmix_net_forward", "lbmix_net_gradient", "lbmix_net_adam",
@@ -90,6 +90,7 @@ def load_library():
         "lbmix_set_poisson_warm_start": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_set_rounding": ([vp, ctypes.c_int, ctypes.c_ulonglong], ctypes.c_int),
         "lbmix_set_storage_range": ([vp, ctypes.c_int, ctypes.c_double], ctypes.c_int),
+        "lbmix_set_arithmetic": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_set_state": ([vp, ctypes.c_int, dp, dp], ctypes.c_int),
         "lbmix_step": ([vp, ctypes.c_int], ctypes.c_int),
         "lbmix_autotune": ([vp, ctypes.c_int], ctypes.c_int),
@@ -102,6 +103,7 @@ def load_library():
         "lbmix_get_zprofiles": ([vp, dp], ctypes.c_int),
         "lbmix_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
         "lbmix_sync": ([vp], ctypes.c_int),
+        "lbmix_device_copy": ([vp, vp, ctypes.c_ulonglong, vp], ctypes.c_int),
         "lbmix_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "lbmix_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "lbmix_last_error": ([vp], ctypes.c_char_p),
@@ -139,6 +141,21 @@ def _f64(a, shape):
     if a.shape != shape:
         a = a.reshape(shape)
     return a
+
+
+def device_copy(dst, src, stream=None):
+    """Copy the torch CUDA tensor src into dst (same byte size, 16-byte aligned, a multiple of
+    16 bytes) with the library's plain copy kernel (lbmix_device_copy), stream-ordered."""
+    import torch
+    L = load_library()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("dst and src must be CUDA tensors of the same byte size")
+    s = (stream or torch.cuda.current_stream()).cuda_stream
+    rc = L.lbmix_device_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                             ctypes.c_void_p(s))
+    if rc:
+        raise LbmixError(rc, "lbmix_device_copy rejected the buffers")
 
 
 class Lattice:
@@ -244,6 +261,11 @@ class Lattice:
 
     def set_rounding(self, stochastic=True, seed=0):
         self._check(self._L.lbmix_set_rounding(self._h, 1 if stochastic else 0, int(seed)))
+
+    def set_arithmetic(self, wide=True):
+        """wide: carry the density deviation beyond FP32 (default); False: FP32 collision
+        arithmetic throughout (lbmix_set_arithmetic)."""
+        self._check(self._L.lbmix_set_arithmetic(self._h, 1 if wide else 0))
 
     def set_storage_range(self, s, rel_range):
         self._check(self._L.lbmix_set_storage_range(self._h, int(s), float(rel_range)))
@@ -431,10 +453,13 @@ class Net:
 
 
 def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, seed=0, drag_pairs=None,
-                  forcing="paper"):
+                  forcing="paper", schmidt=None, wide=True):
     """Build a Lattice from a workloads.Workload or workloads.ChannelStack description
     (parameters and initial fields).  stochastic: rounding of the stored populations (default:
-    stochastic for the 16-bit forms, nearest for the FP32 ones); forcing: "paper" or "guo"."""
+    stochastic for the 16-bit forms, nearest for the FP32 ones); forcing: "paper" or "guo";
+    schmidt: set the drag through lbmix_set_schmidt with this Schmidt number instead of the
+    workload's tau_drag (single lattices only); wide: False for FP32 collision arithmetic
+    throughout (lbmix_set_arithmetic)."""
     stack = w.geometry == "channels"
     lat = Lattice(w.nx, w.ny, w.nz, geometry=w.geometry, storage=storage, stream=stream,
                   widths=w.widths if stack else None)
@@ -444,6 +469,8 @@ def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, 
         lat.set_rounding(True if stochastic is None else stochastic, seed)
     elif storage in ("f32", "f32s") and stochastic:
         lat.set_rounding(True, seed)
+    if not wide:
+        lat.set_arithmetic(False)
     lat.set_tau_visc(w.tau_visc)
     if stack:
         for c in range(len(w.widths)):
@@ -451,7 +478,10 @@ def from_workload(w, storage="f64", stream=None, poisson=None, stochastic=None, 
         if w.bjerrum > 0 or any(w.E):
             lat.set_electrostatics(w.bjerrum, 0.0, 0.0, w.E)
     else:
-        lat.set_tau_drag(w.tau_drag)
+        if schmidt is None:
+            lat.set_tau_drag(w.tau_drag)
+        else:
+            lat.set_schmidt(schmidt)
         if w.bjerrum > 0 or any(w.E):
             lat.set_electrostatics(w.bjerrum, w.sigma[0], w.sigma[1], w.E)
     if drag_pairs is not None:
