@@ -278,6 +278,18 @@ int lbmix_net_get_gradient(lbmix_net *net, float *grad);
  * Errors: EINVAL for null pointers or bad extents. */
 int lbmix_net_forward(lbmix_net *net, const float *x_dev, float *y_dev, int nx, int ny, int nz, int z_walls,
                       void *stream);
+/* lbmix_net_forward for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result, bitwise, but the
+ * hidden layers' outputs live in a static device array of 64 MiB that every GPU the library
+ * runs on holds until the process ends, so the call allocates nothing.  It needs
+ * min(2, layers - 1) x hidden x nx ny nz x 4 bytes of it: up to 524288 nodes with 16 hidden
+ * channels.  The caller passes x_dev and y_dev as for lbmix_net_forward, with the network's
+ * device current.  All calls on one GPU share the array, so calls that overlap on one GPU
+ * (other streams, other threads, other networks) race and must be serialised by the caller.
+ * Errors: EINVAL for null pointers, bad extents, a lattice beyond the scratch size (nothing
+ * launched) or another device current; EDEVICE. */
+int lbmix_net_forward_noalloc(lbmix_net *net, const float *x_dev, float *y_dev, int nx, int ny, int nz,
+                              int z_walls, void *stream);
 /* Mean-square loss mean((net(x) - t)^2) and its gradient with respect to every parameter by
  * back-propagation (kept on the device for lbmix_net_adam; lbmix_net_get_gradient copies it
  * out).  loss may be NULL (else the call synchronises the stream). */

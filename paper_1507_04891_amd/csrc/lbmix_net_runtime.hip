@@ -9,10 +9,27 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 using namespace lbmix;
+
+namespace {
+
+// Activation scratch of lbmix_net_forward_noalloc: the outputs of the hidden layers, in two
+// buffers used in turn, held in a static device array instead of allocated memory.  Each GPU
+// the library runs on holds its own copy until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it only stands in for the symbol): the device address
+// comes from hipGetSymbolAddress, once per device, and is kept in scratch_addr.
+constexpr size_t NET_SCRATCH_BYTES = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[NET_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_addr[MAX_DEVICES] = {};
+
+}  // namespace
 
 struct lbmix_net {
     std::vector<int> ch;              // channels at each layer boundary: cin, hidden..., 1
@@ -279,6 +296,48 @@ int lbmix_net_forward(lbmix_net *net, const float *x_dev, float *y_dev, int nx, 
     int rc = check_dims(net, nx, ny, nz);
     if (rc) return rc;
     return net_forward(net, x_dev, y_dev, nx, ny, nz, z_walls ? 1 : 0, static_cast<hipStream_t>(stream));
+}
+
+int lbmix_net_forward_noalloc(lbmix_net *net, const float *x_dev, float *y_dev, int nx, int ny, int nz,
+                              int z_walls, void *stream) {
+    if (!net || !x_dev || !y_dev) return LBMIX_EINVAL;
+    int rc = check_dims(net, nx, ny, nz);
+    if (rc) return rc;
+    const size_t N = (size_t)nx * ny * nz;
+    const int L = net->layers();
+    int cmax = 0;
+    for (int k = 1; k < L; ++k) cmax = net->ch[k] > cmax ? net->ch[k] : cmax;
+    const size_t nbuf = L > 2 ? 2 : (size_t)(L - 1);   // hidden outputs alive at once
+    const size_t need = nbuf * (size_t)cmax * N * sizeof(float);
+    if (need > NET_SCRATCH_BYTES)
+        return net->fail(LBMIX_EINVAL, "%zu nodes need %zu bytes of activation scratch; the static scratch holds %zu",
+                         N, need, NET_SCRATCH_BYTES);
+    int dev = -1;
+    if ((rc = net->hip(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+    if (dev != net->device)
+        return net->fail(LBMIX_EINVAL, "device %d is current; the network lives on device %d", dev, net->device);
+    if (dev < 0 || dev >= MAX_DEVICES) return net->fail(LBMIX_EINVAL, "device ordinal %d out of range", dev);
+    float *buf = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (!scratch_addr[dev]) {
+            void *p = nullptr;
+            if ((rc = net->hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)")))
+                return rc;
+            scratch_addr[dev] = p;
+        }
+        buf = static_cast<float *>(scratch_addr[dev]);
+    }
+    // every output element of a layer is written, so nothing in the scratch needs clearing
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t ux = (uint32_t)nx, uy = (uint32_t)ny, uz = (uint32_t)nz;
+    const float *in = x_dev;
+    for (int l = 0; l < L; ++l) {
+        float *out = (l + 1 == L) ? y_dev : buf + (size_t)(l & 1) * (size_t)cmax * N;
+        if ((rc = net->hip(launch_conv3(net->conv(l, in, out, ux, uy, uz, z_walls ? 1 : 0), st), "conv3"))) return rc;
+        in = out;
+    }
+    return LBMIX_OK;
 }
 
 int lbmix_net_gradient(lbmix_net *net, const float *x_dev, const float *t_dev, int nx, int ny, int nz, int z_walls,

@@ -35,7 +35,7 @@ EXPORTS = (
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_device_copy", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
     "lbmix_net_create", "lbmix_net_num_params", "lbmix_net_get_params", "lbmix_net_set_params",
-    "lbmix_net_get_gradient", "lbmix_net_forward", "lbmix_net_gradient", "lbmix_net_adam",
+    "lbmix_net_get_gradient", "lbmix_net_forward", "lbmix_net_forward_noalloc", "lbmix_net_gradient", "lbmix_net_adam",
     "lbmix_net_output_scale", "lbmix_net_last_error", "lbmix_net_destroy", "lbmix_set_warm_start_net", "lbmix_train_warm_start",
 )
 
@@ -115,6 +115,8 @@ def load_library():
         "lbmix_net_set_params": ([vp, fp], ctypes.c_int),
         "lbmix_net_get_gradient": ([vp, fp], ctypes.c_int),
         "lbmix_net_forward": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp], ctypes.c_int),
+        "lbmix_net_forward_noalloc": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
+                                      ctypes.c_int),
         "lbmix_net_gradient": ([vp, vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, vp],
                                ctypes.c_int),
         "lbmix_net_adam": ([vp, ctypes.c_float, vp], ctypes.c_int),
@@ -434,6 +436,19 @@ class Net:
         s = (stream or torch.cuda.current_stream()).cuda_stream
         self._check(self._L.lbmix_net_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                               nx, ny, nz, 1 if z_walls else 0, ctypes.c_void_p(s)))
+        return y
+
+    def forward_noalloc(self, x, y, z_walls=False, stream=None):
+        """y = net(x) into the caller's tensor y [1][nz][ny][nx], with the activation scratch in
+        the library's static device array (lbmix_net_forward_noalloc: no allocation)."""
+        import torch
+        nx, ny, nz = self._dims(x)
+        if tuple(self._dims(y)) != (nx, ny, nz) or y.shape[0] != 1:
+            raise ValueError("y must be a float32 CUDA tensor [1][nz][ny][nx]")
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        self._check(self._L.lbmix_net_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()),
+                                                      ctypes.c_void_p(y.data_ptr()), nx, ny, nz,
+                                                      1 if z_walls else 0, ctypes.c_void_p(s)))
         return y
 
     def loss_and_gradient(self, x, t, z_walls=False, stream=None):

@@ -103,9 +103,11 @@ int main(int argc, char **argv) {
     if (nr == LBMIX_OK) {
         EXPECT(lbmix_net_num_params(net) > 0);
         EXPECT(lbmix_net_forward(net, nullptr, nullptr, 4, 4, 4, 0, nullptr) == LBMIX_EINVAL);
+        EXPECT(lbmix_net_forward_noalloc(net, nullptr, nullptr, 4, 4, 4, 0, nullptr) == LBMIX_EINVAL);
         lbmix_net_destroy(net);
     }
     lbmix_net_destroy(nullptr);
+    EXPECT(lbmix_net_forward_noalloc(nullptr, nullptr, nullptr, 4, 4, 4, 0, nullptr) == LBMIX_EINVAL);
 
     if (failures) std::fprintf(stderr, "%d expectation(s) failed\n", failures);
     else std::printf("host ABI checks passed\n");
