@@ -115,7 +115,8 @@ int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int stor
  * from plane sum_{c' < c} (widths[c'] + 2) (its lower wall) upwards.  Channels share the
  * species, tau_visc, the Bjerrum length, the field and the storage; each has its own drag
  * and wall charges (lbmix_set_channel) and is neutral and gauged on its own.  One fused
- * launch steps all channels; the Poisson solve is the direct one or SOR (not multigrid).
+ * launch steps all channels; the Poisson solve is any of the three (multigrid in its channel form,
+ * see lbmix_set_poisson_method).
  * Errors: as lbmix_create; EINVAL for nchannels < 1 or a width < 1. */
 int lbmix_create_channels(lbmix_ctx **out, int nx, int ny, int nchannels, const int *widths,
                           int storage, void *hip_stream);
@@ -235,10 +236,14 @@ int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_
  * slit or stack (from both ends towards the middle plane), by a third
  * Fourier basis in a periodic box; its result is exact to rounding, takes any extents and
  * needs no warm start (rel_tol and max_sweeps do not apply; lbmix_stats counts one sweep
- * per solve and reports the residual of every check_every-th solve).  SOR and multigrid
- * need even periodic extents (or 1); multigrid does not take channel stacks.  Errors:
- * EINVAL for another method, multigrid on a stack, or SOR or multigrid on odd extents once
- * stepping has started (checked by lbmix_step before). */
+ * per solve and reports the residual of every check_every-th solve).  On a stack of channels
+ * (lbmix_create_channels), whose widths are arbitrary, multigrid keeps every plane on every
+ * level and halves x and y only, relaxing whole z lines instead of points: a red-black sweep
+ * over the columns (colour (x + y) mod 2) solves the tridiagonal z-system of each column in
+ * each channel exactly, its lateral neighbours held fixed; V(1,1) cycles down to one column
+ * per channel, where the line solve is the exact coarse solve.  SOR and multigrid need even
+ * periodic extents (or 1).  Errors: EINVAL for another method, or SOR or multigrid on odd
+ * extents once stepping has started (checked by lbmix_step before). */
 int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
 
 /* Warm start of each Poisson solve: 0 the previous potential (default); 1 the

@@ -191,7 +191,11 @@ __device__ inline MGNb mg_nb(const MGLevel &L, const double *e, uint32_t x, uint
         s += L.ay * (e[(z * L.ny + yp) * L.nx + x] + e[(z * L.ny + ym) * L.nx + x]);
         dg += 2.0 * L.ay;
     }
-    if (L.nz > 1) {
+    if (L.planes) {   // a stack of channels: no neighbour across a wall
+        const uint32_t w = L.planes[z].walls;
+        if (!(w & 2u)) { s += L.az * e[((z + 1) * L.ny + y) * L.nx + x]; dg += L.az; }
+        if (!(w & 1u)) { s += L.az * e[((z - 1) * L.ny + y) * L.nx + x]; dg += L.az; }
+    } else if (L.nz > 1) {
         if (L.periodic_z) {
             const uint32_t zm = z == 0 ? L.nz - 1 : z - 1, zp = z + 1 == L.nz ? 0 : z + 1;
             s += L.az * (e[(zp * L.ny + y) * L.nx + x] + e[(zm * L.ny + y) * L.nx + x]);
@@ -212,6 +216,78 @@ __global__ __launch_bounds__(BLOCK) void mg_smooth(const MGLevel L, int colour) 
     const uint32_t i = (z * L.ny + y) * L.nx + x;
     const MGNb nb = mg_nb(L, L.e, x, y, z);
     if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
+}
+
+// Line relaxation along z for channel stacks, whose channels may be of any width: the z
+// lines of the columns of one colour (x + y) mod 2 are solved exactly, their lateral
+// neighbours (the other colour) held fixed.  First the right-hand sides g = (lateral terms) - r
+// of the line equations (Ld + az n_z) e - az (e_up + e_down) = g, written over e (the line's
+// own values are not needed), then one thread per line and channel eliminates and substitutes.
+__global__ __launch_bounds__(BLOCK) void mg_line_rhs(const MGLevel L, int colour) {
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= L.nx) return;
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    if (((x + y) & 1u) != (uint32_t)colour) return;
+    double s = 0.0;
+    if (L.nx > 1) {
+        const uint32_t xm = x == 0 ? L.nx - 1 : x - 1, xp = x + 1 == L.nx ? 0 : x + 1;
+        s += L.ax * (L.e[(z * L.ny + y) * L.nx + xp] + L.e[(z * L.ny + y) * L.nx + xm]);
+    }
+    if (L.ny > 1) {
+        const uint32_t ym = y == 0 ? L.ny - 1 : y - 1, yp = y + 1 == L.ny ? 0 : y + 1;
+        s += L.ay * (L.e[(z * L.ny + yp) * L.nx + x] + L.e[(z * L.ny + ym) * L.nx + x]);
+    }
+    const uint32_t i = (z * L.ny + y) * L.nx + x;
+    L.e[i] = s - L.r[i];
+}
+
+constexpr uint32_t LINE_CHUNK = 8;   // planes whose loads a line thread keeps in flight together
+
+__global__ __launch_bounds__(BLOCK) void mg_line_solve(const MGLevel L, int colour, const double *idn,
+                                                      const double *idn_last, const uint32_t *first, uint32_t nch) {
+    const uint32_t ncol = L.nx * L.ny;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t c = blockIdx.y;
+    if (t >= ncol || c >= nch) return;
+    if (((t % L.nx + t / L.nx) & 1u) != (uint32_t)colour) return;
+    const uint32_t W = first[c + 1] - first[c];   // >= 1
+    double *e = L.e + (size_t)first[c] * ncol + t;   // plane k of the line: e[k * ncol]
+    const double az = L.az;
+    // forward elimination: d_k = (g_k + az d_{k-1}) idn[k], then the last plane
+    double d = 0.0;
+    uint32_t k = 0;
+    for (; k + LINE_CHUNK < W; k += LINE_CHUNK) {
+        double g[LINE_CHUNK];
+#pragma unroll
+        for (uint32_t j = 0; j < LINE_CHUNK; ++j) g[j] = e[(size_t)(k + j) * ncol];
+#pragma unroll
+        for (uint32_t j = 0; j < LINE_CHUNK; ++j) {
+            d = (g[j] + az * d) * idn[k + j];
+            e[(size_t)(k + j) * ncol] = d;
+        }
+    }
+    for (; k + 1 < W; ++k) {
+        d = (e[(size_t)k * ncol] + az * d) * idn[k];
+        e[(size_t)k * ncol] = d;
+    }
+    d = (e[(size_t)(W - 1) * ncol] + az * d) * idn_last[c];
+    e[(size_t)(W - 1) * ncol] = d;
+    // back substitution: e_k = d_k + az idn[k] e_{k+1}
+    int kk = (int)W - 2;
+    for (; kk + 1 >= (int)LINE_CHUNK; kk -= (int)LINE_CHUNK) {
+        double v[LINE_CHUNK];
+#pragma unroll
+        for (uint32_t j = 0; j < LINE_CHUNK; ++j) v[j] = e[(size_t)(kk - (int)j) * ncol];
+#pragma unroll
+        for (uint32_t j = 0; j < LINE_CHUNK; ++j) {
+            d = v[j] + az * idn[kk - (int)j] * d;
+            e[(size_t)(kk - (int)j) * ncol] = d;
+        }
+    }
+    for (; kk >= 0; --kk) {
+        d = e[(size_t)kk * ncol] + az * idn[kk] * d;
+        e[(size_t)kk * ncol] = d;
+    }
 }
 
 // one thread per coarse cell: average of the fine residuals of its children
@@ -1022,6 +1098,19 @@ hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t str
     dim3 b;
     const dim3 g = node_grid(F.nx, F.ny, F.nz, &b);
     hipLaunchKernelGGL(mg_prolong, g, b, 0, stream, F, C);
+    return hipGetLastError();
+}
+hipError_t launch_mg_line_rhs(const MGLevel &L, int colour, hipStream_t stream) {
+    dim3 b;
+    const dim3 g = node_grid(L.nx, L.ny, L.nz, &b);
+    hipLaunchKernelGGL(mg_line_rhs, g, b, 0, stream, L, colour);
+    return hipGetLastError();
+}
+hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *idn_last,
+                                const uint32_t *first, uint32_t nch, hipStream_t stream) {
+    const uint32_t ncol = L.nx * L.ny;
+    hipLaunchKernelGGL(mg_line_solve, dim3((ncol + BLOCK - 1) / BLOCK, nch), dim3(BLOCK), 0, stream, L, colour, idn,
+                       idn_last, first, nch);
     return hipGetLastError();
 }
 hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream) {

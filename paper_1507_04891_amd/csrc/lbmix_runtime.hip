@@ -95,6 +95,8 @@ struct lbmix_ctx {
     size_t scratch_cap = 0;
     // multigrid: level 0 is (psi, b); coarser levels own their arrays
     std::vector<MGLevel> mg;
+    bool mg_lines = false;            // channel stack: lateral coarsening, z-line relaxation
+    std::vector<double *> mg_idn, mg_idn_last;   // per level: inverse pivots of the z lines
     double *mg_b = nullptr;
     double *mg_cinv = nullptr;        // exact inverse of the coarsest level (<= 64 cells)
     hipStream_t cap_stream = nullptr;  // capture-only stream (graphs replay on `stream`)
@@ -425,10 +427,43 @@ int residual(lbmix_ctx *c, const PoissonArgs &pa) {
 // one), two on the coarser grid levels
 constexpr int kPre0 = 1, kPost0 = 1, kPre = 2, kPost = 2;
 
+// Inverse pivots of the z-line systems of a channel-stack level, (Ld + az n_z) e - az (e_up +
+// e_down) = g with Ld its lateral diagonal: one forward recurrence from the first plane of a
+// channel, shared by every channel before its last plane (idn[k], k < longest - 1), and the
+// last plane of each channel (idn_last[c]; 0 where the line is singular, which pins that plane).
+int mg_line_pivots(lbmix_ctx *c, const MGLevel &L) {
+    const double Ld = (L.nx > 1 ? 2.0 * L.ax : 0.0) + (L.ny > 1 ? 2.0 * L.ay : 0.0), az = L.az;
+    int longest = 1;
+    for (int w : c->ch_width) longest = std::max(longest, w);
+    std::vector<double> denom(std::max(longest - 1, 1), 1.0), idn(denom.size(), 0.0), last(c->nch, 0.0);
+    for (int k = 0; k + 1 < longest; ++k) {
+        denom[k] = k == 0 ? Ld + az : (Ld + 2.0 * az) - az * az / denom[k - 1];
+        idn[k] = 1.0 / denom[k];
+    }
+    for (int ch = 0; ch < c->nch; ++ch) {
+        const int W = c->ch_width[ch];
+        const double d = W == 1 ? Ld : (Ld + az) - az * az / denom[W - 2];
+        last[ch] = d > 1e-12 * (Ld + 2.0 * az) ? 1.0 / d : 0.0;
+    }
+    double *di = nullptr, *dl = nullptr;
+    int rc;
+    if ((rc = c->hip(hipMalloc((void **)&di, idn.size() * sizeof(double)), "hipMalloc(mg)"))) return rc;
+    c->mg_idn.push_back(di);
+    if ((rc = c->hip(hipMalloc((void **)&dl, last.size() * sizeof(double)), "hipMalloc(mg)"))) return rc;
+    c->mg_idn_last.push_back(dl);
+    if ((rc = c->hip(hipMemcpy(di, idn.data(), idn.size() * sizeof(double), hipMemcpyHostToDevice), "copy pivots")))
+        return rc;
+    return c->hip(hipMemcpy(dl, last.data(), last.size() * sizeof(double), hipMemcpyHostToDevice), "copy pivots");
+}
+
 int mg_build(lbmix_ctx *c) {
     if (!c->mg.empty()) return LBMIX_OK;
     int rc = c->hip(hipMalloc((void **)&c->mg_b, (size_t)c->Nf * sizeof(double)), "hipMalloc(mg)");
     if (rc) return rc;
+    // a stack of channels of any widths keeps every plane on every level and coarsens x and y
+    // only, relaxing whole z lines of each channel (their systems are solved exactly), down to
+    // one column per channel, where the line solve is the exact coarse solve
+    c->mg_lines = c->nch > 1;
     MGLevel L{};
     L.e = c->psi;
     L.r = c->mg_b;
@@ -437,6 +472,7 @@ int mg_build(lbmix_ctx *c) {
     L.nz = c->nzf;
     L.ax = L.ay = L.az = 1.0;
     L.periodic_z = c->slit ? 0 : 1;
+    L.planes = c->mg_lines ? c->d_planes : nullptr;
     double hx = 1.0, hy = 1.0, hz = 1.0;
     for (;;) {
         // a periodic axis halves while the red-black colouring stays consistent (even size
@@ -445,9 +481,11 @@ int mg_build(lbmix_ctx *c) {
         auto neu_ok = [](uint32_t n) { return n >= 2 && n % 2 == 0; };
         L.fx = per_ok(L.nx) ? 2 : 1;
         L.fy = per_ok(L.ny) ? 2 : 1;
-        L.fz = (L.periodic_z ? per_ok(L.nz) : neu_ok(L.nz)) ? 2 : 1;
-        const bool last = (L.fx == 1 && L.fy == 1 && L.fz == 1) || (size_t)L.nx * L.ny * L.nz <= 64;
+        L.fz = (!c->mg_lines && (L.periodic_z ? per_ok(L.nz) : neu_ok(L.nz))) ? 2 : 1;
+        const bool last = (L.fx == 1 && L.fy == 1 && L.fz == 1) ||
+                          (!c->mg_lines && (size_t)L.nx * L.ny * L.nz <= 64);
         if (last) L.fx = L.fy = L.fz = 1;
+        if (c->mg_lines && (rc = mg_line_pivots(c, L))) return rc;
         c->mg.push_back(L);
         if (last) break;
         MGLevel C{};
@@ -461,6 +499,7 @@ int mg_build(lbmix_ctx *c) {
         C.ay = 1.0 / (hy * hy);
         C.az = 1.0 / (hz * hz);
         C.periodic_z = L.periodic_z;
+        C.planes = L.planes;
         const size_t n = (size_t)C.nx * C.ny * C.nz;
         if ((rc = c->hip(hipMalloc((void **)&C.e, n * sizeof(double)), "hipMalloc(mg)"))) return rc;
         if ((rc = c->hip(hipMalloc((void **)&C.r, n * sizeof(double)), "hipMalloc(mg)"))) return rc;
@@ -470,7 +509,7 @@ int mg_build(lbmix_ctx *c) {
     // Gauss-Jordan elimination with partial pivoting in FP64
     const MGLevel &B = c->mg.back();
     const int m = (int)(B.nx * B.ny * B.nz);
-    if (c->mg.size() >= 2 && m <= 64) {
+    if (!c->mg_lines && c->mg.size() >= 2 && m <= 64) {
         std::vector<double> A((size_t)m * m, 0.0), I((size_t)m * m, 0.0);
         auto id = [&](int x, int y, int z) { return (z * (int)B.ny + y) * (int)B.nx + x; };
         for (int z = 0; z < (int)B.nz; ++z)
@@ -541,7 +580,43 @@ int mg_build(lbmix_ctx *c) {
 // (their cells together must fit MG_BOTTOM_LDS).
 constexpr size_t kBottomCells = 2048;
 
+// One V(1,1) cycle of z-line red-black relaxation on a channel stack, then the residual norms.
+int mg_line_vcycle(lbmix_ctx *c, const PoissonArgs &pa, hipStream_t st) {
+    const int nl = (int)c->mg.size();
+    int rc;
+    auto sweep = [&](int l) -> int {
+        for (int col = 0; col < 2; ++col) {
+            int r = c->hip(launch_mg_line_rhs(c->mg[l], col, st), "mg_line_rhs");
+            if (r) return r;
+            if ((r = c->hip(launch_mg_line_solve(c->mg[l], col, c->mg_idn[l], c->mg_idn_last[l], c->d_first,
+                                                 (uint32_t)c->nch, st),
+                            "mg_line_solve")))
+                return r;
+        }
+        return LBMIX_OK;
+    };
+    for (int l = 0; l + 1 < nl; ++l) {
+        if ((rc = sweep(l))) return rc;
+        if ((rc = c->hip(launch_mg_restrict(c->mg[l], c->mg[l + 1], st), "mg_restrict"))) return rc;
+    }
+    // coarsest level: one column per channel is solved exactly by its line solve; a level that
+    // could not be coarsened that far gets repeated sweeps
+    const MGLevel &B = c->mg[nl - 1];
+    const int count = (B.nx == 1 && B.ny == 1) ? 1 : std::max(4, 2 * (int)std::max(B.nx, B.ny));
+    for (int k = 0; k < count; ++k)
+        if ((rc = sweep(nl - 1))) return rc;
+    for (int l = nl - 2; l >= 0; --l) {
+        if ((rc = c->hip(launch_mg_prolong(c->mg[l], c->mg[l + 1], st), "mg_prolong"))) return rc;
+        if ((rc = sweep(l))) return rc;
+    }
+    uint32_t nb = 0;
+    if ((rc = c->hip(launch_residual(pa, c->partials, &nb, st), "residual"))) return rc;
+    return c->hip(launch_finalize(c->partials, nb, 3, c->dred + 4, 2, 0.0, 0.0, (double)c->Nf, st),
+                  "finalize(residual)");
+}
+
 int mg_vcycle(lbmix_ctx *c, const PoissonArgs &pa, hipStream_t st) {
+    if (c->mg_lines) return mg_line_vcycle(c, pa, st);
     const int nl = (int)c->mg.size();
     // levels [0, lb) run as grid kernels, levels [lb, nl) inside one work-group; a hierarchy
     // of one level (no axis could be halved) is plain red-black Gauss-Seidel
@@ -1069,8 +1144,6 @@ int validate_start(lbmix_ctx *c) {
     if (c->poisson_method != 2 && !redblack_extents(c))
         return c->fail(LBMIX_EINVAL, "charged runs need even periodic extents (or 1) for red-black SOR and "
                                      "multigrid (the direct solve takes any)");
-    if (c->poisson_method == 1 && c->nch > 1)
-        return c->fail(LBMIX_EINVAL, "multigrid solves a single lattice; use SOR or the direct solve for channels");
     const double area = (double)c->nx * c->ny;
     for (int ch = 0; ch < c->nch; ++ch) {   // every channel is neutral on its own
         double qtot = 0.0, scale = 0.0;
@@ -1333,7 +1406,6 @@ int lbmix_set_poisson(lbmix_ctx *c, double rel_tol, int max_sweeps, int check_ev
 int lbmix_set_poisson_method(lbmix_ctx *c, int method) {
     if (!c) return LBMIX_EINVAL;
     if (method < 0 || method > 2) return c->fail(LBMIX_EINVAL, "Poisson method is 0 (SOR), 1 (multigrid) or 2 (direct)");
-    if (method == 1 && c->nch > 1) return c->fail(LBMIX_EINVAL, "multigrid solves a single lattice, not channels");
     if (c->started && method != 2 && c->charged() && !redblack_extents(c))
         return c->fail(LBMIX_EINVAL, "SOR and multigrid need even periodic extents (or 1)");
     drop_graph(c);
@@ -1959,6 +2031,8 @@ void lbmix_destroy(lbmix_ctx *c) {
         for (void *p : {(void *)c->d_planes, (void *)c->d_fof, (void *)c->d_first, (void *)c->d_chan,
                         (void *)c->d_psums})
             if (p) (void)hipFree(p);
+        for (double *p : c->mg_idn) (void)hipFree(p);
+        for (double *p : c->mg_idn_last) (void)hipFree(p);
         for (size_t l = 1; l < c->mg.size(); ++l) {
             (void)hipFree(c->mg[l].e);
             (void)hipFree(c->mg[l].r);

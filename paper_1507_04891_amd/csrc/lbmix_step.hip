@@ -211,29 +211,31 @@ hipError_t launch_set_step(unsigned long long *step, unsigned long long value, h
     return hipGetLastError();
 }
 
-// Plain device copy, 16-byte non-temporal loads and stores, four in flight per thread (the
-// ceiling the fused step's HBM bandwidth is compared with).
+// Plain device copy, 16-byte non-temporal loads and stores: each work-group copies 4 x 256
+// contiguous elements, each thread four of them 256 apart, all four loads issued before the
+// stores (6.1-6.2 TB/s for 2 GiB on MI355X, against 5.0 for a grid-stride loop over 8192
+// work-groups).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+constexpr uint32_t COPY_PER_THREAD = 4;
 __global__ __launch_bounds__(BLOCK) void copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n) {
-    const size_t stride = (size_t)gridDim.x * BLOCK;
-    size_t i = (size_t)blockIdx.x * BLOCK + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const u32x4 a0 = __builtin_nontemporal_load(src + i);
-        const u32x4 a1 = __builtin_nontemporal_load(src + i + stride);
-        const u32x4 a2 = __builtin_nontemporal_load(src + i + 2 * stride);
-        const u32x4 a3 = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a0, dst + i);
-        __builtin_nontemporal_store(a1, dst + i + stride);
-        __builtin_nontemporal_store(a2, dst + i + 2 * stride);
-        __builtin_nontemporal_store(a3, dst + i + 3 * stride);
+    const size_t base = (size_t)blockIdx.x * (BLOCK * COPY_PER_THREAD) + threadIdx.x;
+    u32x4 v[COPY_PER_THREAD];
+#pragma unroll
+    for (uint32_t k = 0; k < COPY_PER_THREAD; ++k) {
+        const size_t i = base + (size_t)BLOCK * k;
+        if (i < n) v[k] = __builtin_nontemporal_load(src + i);
     }
-    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+#pragma unroll
+    for (uint32_t k = 0; k < COPY_PER_THREAD; ++k) {
+        const size_t i = base + (size_t)BLOCK * k;
+        if (i < n) __builtin_nontemporal_store(v[k], dst + i);
+    }
 }
 
 hipError_t launch_copy16(const void *src, void *dst, size_t n16, hipStream_t stream) {
-    size_t blocks = (n16 + 4 * BLOCK - 1) / (4 * BLOCK);
-    if (blocks > 256 * 32) blocks = 256 * 32;   // 32 work-groups per compute unit, then grid-stride
-    if (blocks < 1) blocks = 1;
+    const size_t per_block = (size_t)BLOCK * COPY_PER_THREAD;
+    const size_t blocks = (n16 + per_block - 1) / per_block;
+    if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
     hipLaunchKernelGGL(copy16, dim3((uint32_t)blocks), dim3(BLOCK), 0, stream, static_cast<const u32x4 *>(src),
                        static_cast<u32x4 *>(dst), n16);
     return hipGetLastError();

@@ -156,7 +156,8 @@ template <> struct Codec<BF16> {
     }
     // stochastically rounded pair (lo, hi) in one word
     __device__ static u16x2 put_pair_sr(C lo, C hi, uint32_t rlo, uint32_t rhi) {
-        bf16x2 t = {};
+        // both halves are written, so the register starts as any live value (no clearing move)
+        bf16x2 t = __builtin_bit_cast(bf16x2, lo);
         t = __builtin_amdgcn_cvt_sr_bf16_f32(t, lo, rlo, false);
         t = __builtin_amdgcn_cvt_sr_bf16_f32(t, hi, rhi, true);
         return __builtin_bit_cast(u16x2, t);
@@ -179,7 +180,8 @@ template <> struct Codec<F16> {
         else return __half_as_ushort(__float2half_rn(v));   // IEEE nearest-even
     }
     __device__ static u16x2 put_pair_sr(C lo, C hi, uint32_t rlo, uint32_t rhi) {
-        f16x2 t = {};
+        // both halves are written, so the register starts as any live value (no clearing move)
+        f16x2 t = __builtin_bit_cast(f16x2, lo);
         t = __builtin_amdgcn_cvt_sr_f16_f32(t, lo, rlo, false);
         t = __builtin_amdgcn_cvt_sr_f16_f32(t, hi, rhi, true);
         return __builtin_bit_cast(u16x2, t);
@@ -288,6 +290,17 @@ __device__ __forceinline__ S *slot(S *base, int arr, uint32_t plane, uint32_t in
     return reinterpret_cast<S *>(reinterpret_cast<B *>(start) + (uint32_t)(inplane * (NS * sizeof(S))));
 }
 
+// The same for a byte offset already formed within the plane.  The empty asm makes the offset
+// a fresh 32-bit value where the access is, so the access keeps the scalar-base form (a
+// 64-bit scalar address plus the 32-bit lane offset) instead of a 64-bit vector address.
+template <int NS, class S>
+__device__ __forceinline__ S *slot_at(S *base, int arr, uint32_t plane, uint32_t byte_off, uint32_t N) {
+    S *start = base + ((size_t)arr * N + plane) * NS;
+    asm volatile("" : "+v"(byte_off));
+    using B = std::conditional_t<std::is_const_v<S>, const char, char>;
+    return reinterpret_cast<S *>(reinterpret_cast<B *>(start) + byte_off);
+}
+
 // ---------------------------------------------------------------------------------------
 // Pull addressing shared by every kernel that reads a pre-collision state: the value of
 // direction p at node (x, y, z) comes from slot (p, node - c_p), or from slot (opp(p),
@@ -348,6 +361,20 @@ enum : int {
     kDragPair = 1,   // one frequency per pair of species, on the same velocities
     kDragGuo = 2,    // one frequency, second-order (Guo-type) forcing
 };
+
+// 1 / x, or 0 where x is 0 (a species or mixture with no particles has no velocity).  FP32:
+// the hardware reciprocal refined by one Newton step (within one unit in the last place, where
+// the IEEE division takes four times the instructions); FP64: the division.
+template <class C>
+__device__ __forceinline__ C recip_or_zero(C x) {
+    if constexpr (sizeof(C) == 4) {
+        const float r0 = __builtin_amdgcn_rcpf(x);
+        const float r = fmaf(r0, fmaf(-x, r0, 1.0f), r0);
+        return x != 0.0f ? r : 0.0f;
+    } else {
+        return x != C(0) ? C(1) / x : C(0);
+    }
+}
 
 // Weight class of direction p: 0 rest, 1 the axis directions, 2 the face diagonals.  A
 // class shares the lattice weight and, in the scaled storage forms, the storage scale.
@@ -442,7 +469,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         sjy += jy[s];
         sjz += jz[s];
     }
-    const C inv_ntot = ntot != C(0) ? C(1) / ntot : C(0);
+    const C inv_ntot = recip_or_zero(ntot);
     C ux = sjx * inv_ntot, uy = sjy * inv_ntot, uz = sjz * inv_ntot;   // barycentric
 
     // 3. field acceleration a_s = z_s (E - cs2 grad psi) and its charge-weighted mean
@@ -483,7 +510,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const C inv_n = n[s] != C(0) ? C(1) / n[s] : C(0);
+        const C inv_n = recip_or_zero(n[s]);
         uax[s] = jx[s] * inv_n;
         uay[s] = jy[s] * inv_n;
         uaz[s] = jz[s] * inv_n;
@@ -616,7 +643,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) o[s] = CD::template put<SR>(v[s], rbits(s));
             }
-            VecIO<S, NS>::store(slot<NS>(fout, p, pl.p0, own_in, a.N), o);
+            VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, own_in * (uint32_t)(NS * sizeof(S)), a.N), o);
         };
         {
             C v0[NS];

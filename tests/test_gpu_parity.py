@@ -485,10 +485,30 @@ def test_channel_stack_sor_fixed_sweeps_fp64(P, oracle_mod):
         check_potential(view.potential(), o.potential(), wc)
 
 
-def test_channel_stack_rejects_multigrid_and_charged_channels(P):
-    st = WL.channel_stack(**SMALL_STACK)
-    with pytest.raises(P.LbmixError):
-        P.from_workload(st, storage="f64", poisson=dict(method="multigrid"))
+@pytest.mark.parametrize("lateral", [(8, 6), (8, 8)], ids=["8x6", "8x8"])
+def test_channel_stack_multigrid_fp64_matches_each_channel(P, oracle_mod, lateral):
+    """Multigrid in its channel form (x and y halved, whole z lines of each channel relaxed
+    exactly) to a relative residual of 1e-13 on the same stack: every channel follows its own
+    oracle slit with the direct solve at the FP64 bar, the potential to the tolerance times the
+    condition number of the operator (about (L / pi)^2), below the FP64 bar.  8 x 8 coarsens
+    down to one column per channel, where the line solve is the exact coarse solve; 8 x 6 stops
+    at 1 x 6 and relaxes that level repeatedly."""
+    st = WL.channel_stack(**dict(SMALL_STACK, nx=lateral[0], ny=lateral[1]))
+    lat = P.from_workload(st, storage="f64", poisson=dict(method="multigrid", rel_tol=1e-13, max_sweeps=200))
+    lat.step(25)
+    stats = lat.stats()
+    assert stats["last_residual"] <= 1e-13
+    assert stats["total_sweeps"] / stats["poisson_solves"] < 40      # V-cycles per solve
+    for c in range(len(st.widths)):
+        wc = st.channel(c)
+        o = oracle_for(oracle_mod, wc, poisson="direct")
+        o.step(25)
+        view = ChannelView(lat, st.planes(c), 3)
+        compare_fp64(view, o, wc)
+        check_potential(view.potential(), o.potential(), wc)
+
+
+def test_channel_stack_rejects_charged_channels(P):
     bad = WL.channel_stack(**SMALL_STACK)
     bad.sigmas[1] = (-4e-4, -3e-4)   # the fluid no longer balances the walls of channel 1
     lat = P.from_workload(bad, storage="f64", poisson=dict(method="direct"))
