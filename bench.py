@@ -253,6 +253,13 @@ def bench_configs(P, WL, steps, warmup):
         out[k] = lattice_config(P, ch, st, steps, warmup, dict(method="direct"), charged=True)
         out[k]["fluid_nodes"] = sum(ch.widths) * ch.nx * ch.ny
         mark(k)
+    # the stated fallback of the batched form: multigrid to 1e-8 (the channel form: lateral
+    # coarsening, z-line relaxation), extrapolated warm start
+    k = "channels_64x32x32xW_multigrid_f32s"
+    out[k] = lattice_config(P, ch, "f32s", steps, max(warmup, 20),
+                            dict(method="multigrid", rel_tol=1e-8, max_sweeps=1000, warm_start="extrapolated"),
+                            charged=True)
+    mark(k)
     del ch
     w = WL.binary_multimode(n=512, amp=1e-3, nmodes=8, shear=1e-3, tau_visc=1.0, sc=100.0, seed=4)
     for st in ("f16s", "bf16s", "f32s"):

@@ -1856,7 +1856,9 @@ int lbmix_get_stats(lbmix_ctx *c, lbmix_stats *out) {
     out->fluid_nodes = (double)c->Nf;
     out->bytes_per_step = 2.0 * Q * c->ns * (double)c->esize * c->Nf;
     dim3 b;
-    (void)step_grid(c->nx, c->ny, c->nzf, &b, c->blk_x, c->blk_y);
+    uint32_t bx, by;
+    step_shape(c->st, c->rounding != 0, c->ns, (uint32_t)c->nx, c->blk_x, c->blk_y, &bx, &by);
+    (void)step_grid(c->nx, c->ny, c->nzf, &b, bx, by);
     out->block_x = (int)b.x;
     out->block_y = (int)b.y;
     return LBMIX_OK;

@@ -71,6 +71,11 @@ dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
 // nodes 512 / nx whole rows per work-group.
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx = 0, uint32_t by = 0);
 
+// The work-group shape launch_stream_collide uses: the set one (bx_set, by_set), or 0 x 0 for
+// step_grid's default, except one row of up to 256 nodes for FP32 with stochastic rounding and
+// at most two species (its register budget allows three waves per SIMD).
+void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set, uint32_t by_set, uint32_t *bx,
+                uint32_t *by);
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
                                  const StepArgs &a, hipStream_t stream);
 

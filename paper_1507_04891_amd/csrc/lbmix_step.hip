@@ -30,7 +30,7 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
         int arr;
         uint32_t node;
         pl.template src<p>(arr, node);
-        f[elem(arr, node, a.N, a.ns) + s] = CD::template encode<false>(typename CD::C(dev), a.scale[s][arr]);
+        f[elem_at<S>(s, arr, node, a.N, a.ns)] = CD::template encode<false>(typename CD::C(dev), a.scale[s][arr]);
     });
 }
 
@@ -62,7 +62,7 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
         int arr;
         uint32_t node;
         pl.template src<p>(arr, node);
-        const double dv = double(CD::decode(fin[elem(arr, node, a.N, a.ns) + s], a.inv_scale[s][arr]));
+        const double dv = double(CD::decode(fin[elem_at<S>(s, arr, node, a.N, a.ns)], a.inv_scale[s][arr]));
         if constexpr (MODE == 1) {
             out0[(size_t)p * Nfull + fi] = dv + wgt<double>(p) * a.rho_bar[s];
         } else {
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
             int arr;
             uint32_t node;
             pl.template src<p>(arr, node);
-            m0 += double(CD::decode(fin[elem(arr, node, a.N, a.ns) + s], a.inv_scale[s][arr]));
+            m0 += double(CD::decode(fin[elem_at<S>(s, arr, node, a.N, a.ns)], a.inv_scale[s][arr]));
         });
         qq += a.valence[s] * m0;
     }
@@ -133,10 +133,24 @@ dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx,
     return dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nzf);
 }
 
+void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set, uint32_t by_set, uint32_t *bx,
+                uint32_t *by) {
+    *bx = bx_set;
+    *by = by_set;
+    // FP32 with stochastic rounding (FP64 arithmetic, 166 VGPRs for one or two species): three
+    // waves per SIMD need work-groups of one row (four waves, one per SIMD)
+    if (bx_set == 0 && st == Store::F32 && stochastic && ns <= 2 && nx >= 64) {
+        *bx = ((nx + 63) / 64) * 64 < (uint32_t)BLOCK ? ((nx + 63) / 64) * 64 : (uint32_t)BLOCK;
+        *by = 1;
+    }
+}
+
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged, const StepArgs &a,
                                  hipStream_t stream) {
     dim3 b;
-    const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b, a.block_x, a.block_y);
+    uint32_t bx, by;
+    step_shape(st, a.stochastic != 0, ns, a.nx, a.block_x, a.block_y, &bx, &by);
+    const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b, bx, by);
     switch (st) {
         case Store::F64: return stream_collide_store<double>(ns, slit, field, charged, a, g, b, stream);
         case Store::F32:

@@ -57,7 +57,9 @@ __host__ __device__ constexpr C wgt(int p) {
 //   kScaled: the stored values carry a power-of-two scale per species and weight class;
 //   kWide: how the fused step carries the density deviation beyond C when asked to:
 //     0 C is FP64 already; 1 an FP64 sum of every population; 2 an FP64 combination of the
-//     three per-class FP32 sums, which are exact for 16-bit values of similar magnitude.
+//     three per-class FP32 sums, which are exact for 16-bit values of similar magnitude;
+//   kHold: the fused step keeps the loaded values as S and converts them where they are used;
+//   kMinWaves: waves per SIMD the fused step's register budget must allow.
 
 struct BF16 {};
 struct F16 {};
@@ -71,6 +73,8 @@ template <> struct Codec<double> {
     static constexpr bool kScaled = false;
     static constexpr bool kPacked = false;
     static constexpr int kWide = 0;
+    static constexpr bool kHold = false;
+    static constexpr int kMinWaves = 1;
     __device__ static C raw(S v) { return v; }
     template <bool SR = false>
     __device__ static S put(C v, uint32_t = 0) { return v; }
@@ -85,6 +89,8 @@ template <> struct Codec<float> {
     static constexpr bool kScaled = false;
     static constexpr bool kPacked = false;
     static constexpr int kWide = 1;
+    static constexpr bool kHold = false;
+    static constexpr int kMinWaves = 1;
     __device__ static C raw(S v) { return v; }
     template <bool SR = false>
     __device__ static S put(C v, uint32_t = 0) { return v; }
@@ -93,10 +99,12 @@ template <> struct Codec<float> {
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
 };
 // Counter-based 32-bit hash (the "lowbias32" integer mixer: xor-shift / multiply rounds
-// with the published constants 0x7feb352d and 0x846ca68b).  It seeds, once per node and
-// step, a Marsaglia xorshift32 stream (shifts 13, 17, 5) that supplies the random bits of
-// stochastic rounding: one 32-bit draw per direction, its high and low halves for the two
-// species of a pair.
+// with the published constants 0x7feb352d and 0x846ca68b).  Two of its values seed, once per
+// node and step, a Marsaglia xorshift64 stream (shifts 13, 7, 17, a full-period triple of his
+// "Xorshift RNGs") that supplies the random bits of stochastic rounding: each 64-bit draw gives
+// the 32-bit words of two directions (its high, then its low half), and a word's high and low
+// halves go to the two species of a pair.  The 64-bit shifts are single instructions on
+// gfx950, so a word costs half the instructions of a 32-bit xorshift draw.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -105,10 +113,10 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
     x ^= x >> 16;
     return x;
 }
-__device__ __forceinline__ uint32_t xorshift32(uint32_t x) {
+__device__ __forceinline__ uint64_t xorshift64(uint64_t x) {
     x ^= x << 13;
-    x ^= x >> 17;
-    x ^= x << 5;
+    x ^= x >> 7;
+    x ^= x << 17;
     return x;
 }
 
@@ -148,6 +156,8 @@ template <> struct Codec<BF16> {
     static constexpr bool kScaled = false;
     static constexpr bool kPacked = true;
     static constexpr int kWide = 2;
+    static constexpr bool kHold = false;
+    static constexpr int kMinWaves = 1;
     __device__ static C raw(S v) { return __uint_as_float(uint32_t(v) << 16); }
     template <bool SR = false>
     __device__ static S put(C v, uint32_t rnd = 0) {
@@ -173,6 +183,8 @@ template <> struct Codec<F16> {
     static constexpr bool kScaled = true;
     static constexpr bool kPacked = true;
     static constexpr int kWide = 2;
+    static constexpr bool kHold = false;
+    static constexpr int kMinWaves = 1;
     __device__ static C raw(S v) { return __half2float(__ushort_as_half(v)); }
     template <bool SR = false>
     __device__ static S put(C v, uint32_t rnd = 0) {
@@ -198,17 +210,16 @@ template <> struct Codec<F16> {
 __device__ inline float f64_to_f32_sr(double v, uint32_t rnd) {
     const float f = float(v);
     const double r = v - double(f);
-    if (r == 0.0 || !isfinite(f)) return f;
     const uint32_t bits = __float_as_uint(f);
-    uint32_t gb;
-    if (f == 0.0f)
-        gb = r > 0.0 ? 1u : 0x80000001u;                       // smallest subnormal, sign of r
-    else
-        gb = ((f > 0.0f) == (r > 0.0)) ? bits + 1u : bits - 1u;   // away from / toward zero
+    // the neighbour on the side of v: away from zero when r has the sign of f, else toward
+    // zero; from a zero, the smallest subnormal with the sign of r
+    const uint32_t gb = f == 0.0f ? (r > 0.0 ? 1u : 0x80000001u)
+                                  : (((f > 0.0f) == (r > 0.0)) ? bits + 1u : bits - 1u);
     const float g = __uint_as_float(gb);
     const double s = fabs(double(g) - double(f));
     const double u = (double(rnd >> 16) + 0.5) * (1.0 / 65536.0);
-    return fabs(r) > u * s ? g : f;
+    // r == 0 keeps f; a non-finite f is kept as it is
+    return (fabs(r) > u * s && isfinite(f)) ? g : f;
 }
 
 template <> struct Codec<F32X> {
@@ -218,6 +229,11 @@ template <> struct Codec<F32X> {
     static constexpr bool kScaled = false;
     static constexpr bool kPacked = false;
     static constexpr int kWide = 0;
+    // hold the loaded FP32 values and convert them at each use (the FP64 copies would take twice
+    // the registers), and ask for three waves per SIMD (at most 168 VGPRs: 166 for two species
+    // without spilling; four waves would spill)
+    static constexpr bool kHold = true;
+    static constexpr int kMinWaves = 3;
     __device__ static C raw(S v) { return double(v); }
     template <bool SR = false>
     __device__ static S put(C v, uint32_t rnd = 0) {
@@ -278,6 +294,20 @@ template <> struct VecIO<uint16_t, 4> : VecIOv<uint16_t, u16x4, 4> {};
 
 __device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int ns) {
     return ((size_t)arr * N + node) * ns;
+}
+
+// Three species in 2-byte elements would make 6-byte records that no single access fits, so
+// that layout is split: species 0 and 1 interleaved as above with NS = 2 (one 4-byte access per
+// direction and node), species 2 in a region of its own after them (one 2-byte access).
+template <class S, int NS>
+constexpr bool kSplit = sizeof(S) == 2 && NS == 3;
+
+// Element index of species s, slot arr, node, for ns species of element type S.
+template <class S>
+__device__ __forceinline__ size_t elem_at(int s, int arr, uint32_t node, uint32_t N, int ns) {
+    if (sizeof(S) == 2 && ns == 3)
+        return s < 2 ? ((size_t)arr * N + node) * 2 + s : (size_t)2 * Q * N + (size_t)arr * N + node;
+    return ((size_t)arr * N + node) * ns + s;
 }
 
 // The elements of direction slot arr at node plane + inplane in the fused step's layout: the
@@ -362,12 +392,13 @@ enum : int {
     kDragGuo = 2,    // one frequency, second-order (Guo-type) forcing
 };
 
-// 1 / x, or 0 where x is 0 (a species or mixture with no particles has no velocity).  FP32:
-// the hardware reciprocal refined by one Newton step (within one unit in the last place, where
-// the IEEE division takes four times the instructions); FP64: the division.
-template <class C>
+// 1 / x, or 0 where x is 0 (a species or mixture with no particles has no velocity).  The
+// issue-bound 16-bit forms (FAST): the hardware reciprocal refined by one Newton step (within
+// one unit in the last place, where the IEEE division takes four times the instructions);
+// otherwise the division.
+template <class C, bool FAST>
 __device__ __forceinline__ C recip_or_zero(C x) {
-    if constexpr (sizeof(C) == 4) {
+    if constexpr (FAST && sizeof(C) == 4) {
         const float r0 = __builtin_amdgcn_rcpf(x);
         const float r = fmaf(r0, fmaf(-x, r0, 1.0f), r0);
         return x != 0.0f ? r : 0.0f;
@@ -381,11 +412,28 @@ __device__ __forceinline__ C recip_or_zero(C x) {
 __host__ __device__ constexpr int wclass(int p) { return p == 0 ? 0 : (p < 7 ? 1 : 2); }
 constexpr int kClassRep[3] = {0, 1, 7};   // a direction of each class
 
+// A value made opaque to the compiler where it is used, so a conversion of it is redone there
+// instead of being kept alive in registers from an earlier use.
+template <class V>
+__device__ __forceinline__ V fresh(V x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
+// Waves per SIMD the register budget of stream_collide must allow: the codec's request for one
+// or two species (three or four species need more registers than it allows).
+template <int NS, class T>
+constexpr int step_min_waves() {
+    return (NS <= 2) ? Codec<T>::kMinWaves : 1;
+}
+
 template <int NS, class T, bool SLIT, bool FIELD, bool CHARGED, int DRAG>
-__global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
+__global__ __launch_bounds__(STEP_BLOCK) __attribute__((amdgpu_waves_per_eu(step_min_waves<NS, T>())))
+void stream_collide(const StepArgs a) {
     using CD = Codec<T>;
     using C = typename CD::C;
     using S = typename CD::S;
+    using H = std::conditional_t<CD::kHold, S, C>;   // how the loaded values are held
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;   // uniform per wave if nx >= 64
     const bool active = x < a.nx && y < a.ny;
@@ -404,20 +452,37 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
 
     // 1. pull streaming with bounce-back: one vector load of all species per direction; the
     //    values stay in stored units (h = d * scale)
-    C h[NS][Q];
+    H h[NS][Q];
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
         uint32_t plane, inplane;
         pl.template src<p>(arr, plane, inplane);
         S raw[NS];
-        VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
+        if constexpr (kSplit<S, NS>) {
+            S pair[2];
+            VecIO<S, 2>::load(slot<2>(fin, arr, plane, inplane, a.N), pair);
+            raw[0] = pair[0];
+            raw[1] = pair[1];
+            raw[2] = __builtin_nontemporal_load(slot<1>(fin + (size_t)2 * Q * a.N, arr, plane, inplane, a.N));
+        } else {
+            VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
+        }
 #pragma unroll
-        for (int s = 0; s < NS; ++s) h[s][p] = CD::raw(raw[s]);
+        for (int s = 0; s < NS; ++s) {
+            if constexpr (CD::kHold) h[s][p] = raw[s];
+            else h[s][p] = CD::raw(raw[s]);
+        }
     });
+    // a loaded value in arithmetic precision where the collision uses it
+    auto hc = [&](int s, int p) -> C {
+        if constexpr (CD::kHold) return CD::raw(fresh(h[s][p]));
+        else return h[s][p];
+    };
 
-    // 2. moments (Sec. III): n = rho_bar + dn, dn = sum d, j = sum d c, formed per weight class
-    //    (the classes share a storage scale, so each class sum is scaled once).  The density
+    // 2. moments (Sec. III): n = rho_bar + dn, dn = sum d, j = sum d c; in the 16-bit forms per
+    //    weight class (the classes share a storage scale, so each class sum is scaled once,
+    //    and the sums take fewer instructions, which these issue-bound forms need).  The density
     //    deviation is also carried in FP64 (dnh) unless the FP32 form is asked for: with
     //    deviations stored, the update of a direction is w dn + (flux and force terms), and
     //    FP32 rounding at the scale of w dn is deterministic, where stochastic rounding of the
@@ -430,7 +495,36 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     C ntot = 0, sjx = 0, sjy = 0, sjz = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const C *v = h[s];
+        const H *v = h[s];
+        if constexpr (!CD::kScaled && !CD::kPacked) {
+            // FP32 and FP64 storage (bound by HBM, not by instruction issue): one pass over the
+            // directions as they arrive, the FP64 carry alongside
+            C m0 = 0, mx = 0, my = 0, mz = 0;
+            double m0h = 0.0;
+            static_for<Q>([&](auto pc) {
+                constexpr int p = decltype(pc)::value;
+                const C vp = CD::raw(v[p]);
+                m0 += vp;
+                if constexpr (CD::kWide == 1) m0h += double(v[p]);
+                if constexpr (cx(p) == 1) mx += vp;
+                if constexpr (cx(p) == -1) mx -= vp;
+                if constexpr (cy(p) == 1) my += vp;
+                if constexpr (cy(p) == -1) my -= vp;
+                if constexpr (cz(p) == 1) mz += vp;
+                if constexpr (cz(p) == -1) mz -= vp;
+            });
+            dn[s] = m0;
+            jx[s] = mx;
+            jy[s] = my;
+            jz[s] = mz;
+            dnh[s] = (CD::kWide == 1 && wide) ? m0h : double(m0);
+            n[s] = C(a.rho_bar[s]) + dn[s];
+            ntot += n[s];
+            sjx += jx[s];
+            sjy += jy[s];
+            sjz += jz[s];
+            continue;
+        }
         const C m1 = ((v[1] + v[2]) + (v[3] + v[4])) + (v[5] + v[6]);
         const C m2 = (((v[7] + v[8]) + (v[9] + v[10])) + ((v[11] + v[12]) + (v[13] + v[14]))) +
                      ((v[15] + v[16]) + (v[17] + v[18]));
@@ -451,14 +545,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             jz[s] = (v[5] - v[6]) + z2;
         }
         dnh[s] = double(dn[s]);
-        if constexpr (CD::kWide == 1) {
-            if (wide) {
-                double t = 0.0;
-#pragma unroll
-                for (int p = 0; p < Q; ++p) t += double(v[p]);
-                dnh[s] = t;
-            }
-        } else if constexpr (CD::kWide == 2) {
+        if constexpr (CD::kWide == 2) {
             if (wide)
                 dnh[s] = (double(v[0]) * double(isc(s, 0)) + double(m1) * double(isc(s, 1))) +
                          double(m2) * double(isc(s, 2));
@@ -469,7 +556,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         sjy += jy[s];
         sjz += jz[s];
     }
-    const C inv_ntot = recip_or_zero(ntot);
+    const C inv_ntot = recip_or_zero<C, CD::kPacked>(ntot);
     C ux = sjx * inv_ntot, uy = sjy * inv_ntot, uz = sjz * inv_ntot;   // barycentric
 
     // 3. field acceleration a_s = z_s (E - cs2 grad psi) and its charge-weighted mean
@@ -510,7 +597,7 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const C inv_n = recip_or_zero(n[s]);
+        const C inv_n = recip_or_zero<C, CD::kPacked>(n[s]);
         uax[s] = jx[s] * inv_n;
         uay[s] = jy[s] * inv_n;
         uaz[s] = jz[s] * inv_n;
@@ -589,8 +676,13 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     // The last term is split hi + lo: lo joins the symmetric part B_k, hi is added last, so the
     // stored value rounds like the FP64 sum (the other terms are far below hi, or carry their
     // own FP32 rounding).
-    C B[NS][3], O[NS][3], N9[NS][3], M3[NS][3], bhi[NS][3];
+    //   The 16-bit forms (bound by instruction issue) take the weight into per-class
+    //   coefficients here; the others (bound by HBM) multiply by the constant weight where a
+    //   direction is collided, which keeps this block, and the time before a wave's first
+    //   store, short.
     constexpr bool kF64 = sizeof(C) == 8;
+    constexpr bool kPre = CD::kPacked;
+    C B[NS][3], O[NS][3], N9[NS][3], M3[NS][3], bhi[NS][3], blo[NS][3];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const C uu = uax[s] * uax[s] + uay[s] * uay[s] + uaz[s] * uaz[s];
@@ -599,15 +691,17 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
         const C t45 = C(4.5) * ov * n[s], t9 = C(9) * n[s], t3 = C(3) * n[s];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const C W = kF64 ? C(a.cw[s][k]) : C(a.cwf[s][k]);          // w_k scale_k
+            const C W = kPre ? (kF64 ? C(a.cw[s][k]) : C(a.cwf[s][k])) : C(1);   // w_k scale_k
             B[s][k] = W * base;
             O[s][k] = W * t45;
             N9[s][k] = W * t9;
             M3[s][k] = W * t3;
+            blo[s][k] = C(0);
             if (wide) {
                 const double big = a.cwo[s][k] * dnh[s];                  // w_k ov scale_k dn
                 bhi[s][k] = C(big);
-                B[s][k] += C(big - double(bhi[s][k]));
+                blo[s][k] = C(big - double(bhi[s][k]));
+                if constexpr (kPre) B[s][k] += blo[s][k];
             } else {
                 bhi[s][k] = (kF64 ? C(a.cwo[s][k]) : C(a.cwof[s][k])) * dn[s];
             }
@@ -615,17 +709,29 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
     }
 
     // 5. collision and store, one direction pair at a time, all species per vector store.
-    //    Stochastic rounding draws 32 random bits per direction from a per-node xorshift
-    //    stream, 16 bits per species of each pair.
+    //    Stochastic rounding takes 32 random bits per direction and species pair from a
+    //    per-node xorshift64 stream, 16 bits per species.
     const C keep = C(1) - ov;
     auto collide_store = [&](auto sr_tag) {
         constexpr bool SR = decltype(sr_tag)::value;
         const uint32_t seed = a.step_dev ? step_seed(a.round_seed, *a.step_dev + 1ull) : a.seed;
-        uint32_t rs = SR ? (mix32(own ^ seed) | 1u) : 0u;
+        uint64_t rs = SR ? ((uint64_t(mix32(own ^ seed)) << 32) | uint64_t(mix32(own ^ seed ^ 0x9e3779b9u)) | 1ull)
+                         : 0ull;
+        uint32_t word = 0u, spare = 0u;
+        bool have_spare = false;
         auto rbits = [&](int s) -> uint32_t {     // the conversions use the high bits
             if constexpr (!SR) return 0u;
-            if ((s & 1) == 0) rs = xorshift32(rs);
-            return (s & 1) ? (rs << 16) : rs;
+            if ((s & 1) == 0) {
+                if (have_spare) {
+                    word = spare;
+                } else {
+                    rs = xorshift64(rs);
+                    word = uint32_t(rs >> 32);
+                    spare = uint32_t(rs);
+                }
+                have_spare = !have_spare;
+            }
+            return (s & 1) ? (word << 16) : word;
         };
         // encode the values of direction P and store them with one vector store
         auto put_all = [&](auto pc, const C (&v)[NS]) {
@@ -643,12 +749,24 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) o[s] = CD::template put<SR>(v[s], rbits(s));
             }
-            VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, own_in * (uint32_t)(NS * sizeof(S)), a.N), o);
+            if constexpr (kSplit<S, NS>) {
+                const S pair[2] = {o[0], o[1]};
+                VecIO<S, 2>::store(slot_at<2>(fout, p, pl.p0, own_in * (uint32_t)(2 * sizeof(S)), a.N), pair);
+                __builtin_nontemporal_store(o[2], slot_at<1>(fout + (size_t)2 * Q * a.N, p, pl.p0,
+                                                             own_in * (uint32_t)sizeof(S), a.N));
+            } else {
+                VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, own_in * (uint32_t)(NS * sizeof(S)), a.N), o);
+            }
         };
         {
             C v0[NS];
 #pragma unroll
-            for (int s = 0; s < NS; ++s) v0[s] = (keep * h[s][0] + B[s][0]) + bhi[s][0];
+            for (int s = 0; s < NS; ++s) {
+                if constexpr (kPre)
+                    v0[s] = (keep * hc(s, 0) + B[s][0]) + bhi[s][0];
+                else
+                    v0[s] = ((keep * hc(s, 0) + wgt<C>(0) * B[s][0]) + blo[s][0]) + bhi[s][0];
+            }
             put_all(std::integral_constant<int, 0>{}, v0);
         }
         static_for<9>([&](auto kc) {
@@ -661,10 +779,18 @@ __global__ __launch_bounds__(STEP_BLOCK) void stream_collide(const StepArgs a) {
             for (int s = 0; s < NS; ++s) {
                 const C cu = C(cx(p)) * uax[s] + C(cy(p)) * uay[s] + C(cz(p)) * uaz[s];
                 const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
-                const C sym = (B[s][k] + O[s][k] * (cu * cu)) + N9[s][k] * (cF * cub);
-                const C anti = M3[s][k] * (ov * cu + cF);
-                vp[s] = ((keep * h[s][p] + sym) + anti) + bhi[s][k];
-                vb[s] = ((keep * h[s][pb] + sym) - anti) + bhi[s][k];
+                if constexpr (kPre) {
+                    const C sym = (B[s][k] + O[s][k] * (cu * cu)) + N9[s][k] * (cF * cub);
+                    const C anti = M3[s][k] * (ov * cu + cF);
+                    vp[s] = ((keep * hc(s, p) + sym) + anti) + bhi[s][k];
+                    vb[s] = ((keep * hc(s, pb) + sym) - anti) + bhi[s][k];
+                } else {
+                    constexpr C w = wgt<C>(p);
+                    const C sym = w * (B[s][k] + O[s][k] * cu * cu + N9[s][k] * cF * cub);
+                    const C anti = w * M3[s][k] * (ov * cu + cF);
+                    vp[s] = (((keep * hc(s, p) + sym) + anti) + blo[s][k]) + bhi[s][k];
+                    vb[s] = (((keep * hc(s, pb) + sym) - anti) + blo[s][k]) + bhi[s][k];
+                }
             }
             put_all(std::integral_constant<int, p>{}, vp);
             put_all(std::integral_constant<int, pb>{}, vb);
