@@ -362,9 +362,11 @@ def bench_channels(args):
 
 def bench_warmstart(args):
     """Learned warm start on the charged ternary slit 64 x 64 x 130 (f32s): train the network
-    (4 -> 16 -> 16 -> 16 -> 1, 3 x 3 x 3) for --train-steps steps on exact corrections of the
-    extrapolated guess, then time multigrid to 1e-8 per step from the previous potential, the
-    extrapolation and the learned guess (the direct solve alongside).  Prints one JSON line."""
+    (5 -> 16 -> 16 -> 16 -> 1, 3 x 3 x 3, BF16 operands with FP32 accumulation; inputs: the
+    residual of the extrapolated guess, its coarse-grid solution, two potential increments and
+    the wall mask) for --train-steps steps on exact corrections of the extrapolated guess, then
+    time multigrid to 1e-8 per step from the previous potential, the extrapolation and the
+    learned guess (the direct solve alongside).  Prints one JSON line."""
     import torch
 
     import paper_1507_04891_amd as P
@@ -373,14 +375,14 @@ def bench_warmstart(args):
     torch.cuda.set_device(0)
     w = WL.charged_slit(nx=64, ny=64, nz=130, n_ion=1e-3, debye_length=8.0, sigma=-1e-4, Ex=1e-4, sc=100.0)
     stream = torch.cuda.current_stream()
-    net = P.Net(4, 16, 4, seed=1)
+    net = P.Net(5, 16, 4, seed=1)
     lat = P.from_workload(w, storage=args.storage, stream=stream, poisson=dict(method="direct"))
     lat.step(200)   # train on developed dynamics, not on the first transient
     t0 = time.perf_counter()
     losses = lat.train_warm_start(net, args.train_steps, lr=1e-3)
     torch.cuda.synchronize()
     out = {"workload": "charged ternary slit 64x64x130, Sc=100, lambda_D=8, multigrid to rel. residual 1e-8",
-           "storage": args.storage, "network": "4-16-16-16-1, 3x3x3, %d parameters" % net.num_params,
+           "storage": args.storage, "network": "5-16-16-16-1, 3x3x3, BF16 operands, FP32 accumulate, %d parameters" % net.num_params,
            "train_steps": args.train_steps, "train_s": round(time.perf_counter() - t0, 2),
            "output_scale": net.output_scale(),
            "loss_first50": float(losses[3:53].mean()), "loss_last50": float(losses[-50:].mean())}
@@ -391,7 +393,7 @@ def bench_warmstart(args):
         if warm == "learned":
             lat.set_warm_start_net(net)
         lat.set_poisson(method=method, rel_tol=1e-8, max_sweeps=100000, warm_start=warm)
-        lat.step(args.warmup)
+        lat.step(max(args.warmup, 200))   # the developed dynamics the network was trained on
         torch.cuda.synchronize()
         st0 = lat.stats()
         start = torch.cuda.Event(enable_timing=True)

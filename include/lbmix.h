@@ -251,20 +251,27 @@ int lbmix_set_poisson_method(lbmix_ctx *ctx, int method);
  * in time plus an oscillation of period two steps (the interdiffusion flux relaxes with the
  * factor 1 - omega_drag per step, which is close to -1 at large Schmidt number).  A plain
  * linear extrapolation 2 psi(t-1) - psi(t-2) triples that oscillation instead.  2 learned:
- * the extrapolation, then psi += alpha s net(r / s, dpsi_1 / s, dpsi_2 / s, wall mask) with
- * r = b - A psi the residual of the extrapolated guess, s its root mean square, dpsi_1 =
- * psi(t-1) - psi(t-2), dpsi_2 = psi(t-2) - psi(t-3) and alpha the network's output scale
- * (the network of lbmix_set_warm_start_net; applied once three previous solutions exist).  Applies to SOR and multigrid; the direct solve needs none.
+ * the extrapolation, then psi += alpha s net(r / s, c / s, dpsi_1 / s, dpsi_2 / s, wall mask)
+ * with r = b - A psi the residual of the extrapolated guess, s its root mean square, c the
+ * coarse-grid solution of A c = r (r restricted down the multigrid hierarchy, the coarse end
+ * solved as in a V-cycle, interpolated back without smoothing: the global part of A^-1 r that
+ * a few 3 x 3 x 3 layers cannot reach), dpsi_1 = psi(t-1) - psi(t-2), dpsi_2 = psi(t-2) -
+ * psi(t-3) and alpha the network's output scale (the network of lbmix_set_warm_start_net;
+ * applied once three previous solutions exist).  Applies to SOR and multigrid; the direct
+ * solve needs none.
  * Errors: EINVAL for another mode, or 2 without a network. */
 int lbmix_set_poisson_warm_start(lbmix_ctx *ctx, int mode);
 
 /* ---- learned warm start ---------------------------------------------------------------
  * A fully convolutional network: `layers` 3 x 3 x 3 convolutions (periodic in x and y; in z
  * periodic, or zero beyond the end planes for a slit), in_channels -> hidden -> ... -> hidden
- * -> 1 channels, bias and ReLU on every layer but the last; FP32 parameters [layer][cout][cin]
- * [27] then [cout], tap k = (dz + 1) 9 + (dy + 1) 3 + (dx + 1).  It lives on the device
- * current at creation.  The warm start uses in_channels = 4 (scaled residual, the two last
- * scaled increments of the potential, wall mask). */
+ * -> 1 channels, bias and ReLU on every layer but the last; FP32 master parameters
+ * [layer][cout][cin][27] then [cout], tap k = (dz + 1) 9 + (dy + 1) 3 + (dx + 1).  Every
+ * convolution (forward, transposed and weight gradient) rounds its weights and inputs to BF16
+ * (nearest-even) and accumulates in FP32 (the layers of 16 or more channel pairs on the BF16
+ * matrix cores); Adam updates the FP32 parameters.  It lives on the device current at
+ * creation.  The warm start uses in_channels = 5 (scaled residual, its scaled coarse-grid
+ * solution, the two last scaled increments of the potential, wall mask). */
 
 /* Create a network, weights uniform in +-sqrt(6 / fan_in) (+-1 / sqrt(fan_in) for the last
  * layer) from a splitmix64 stream of `seed`, biases 0.  Errors: EINVAL for channels outside
@@ -310,7 +317,7 @@ const char *lbmix_net_last_error(const lbmix_net *net);
 void lbmix_net_destroy(lbmix_net *net);
 
 /* Network of the learned warm start (borrowed: it must outlive its use; NULL detaches it
- * and falls back to warm start 1).  Errors: EINVAL unless it takes 4 input channels and
+ * and falls back to warm start 1).  Errors: EINVAL unless it takes 5 input channels and
  * lives on the lattice's device. */
 int lbmix_set_warm_start_net(lbmix_ctx *ctx, lbmix_net *net);
 /* Advance the lattice `nsteps` steps with the direct Poisson solve, training `net` on the

@@ -52,15 +52,16 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, uint32_t n,
 // Warm-start glue on fluid nodes (double potential, float network data), s = *scale:
 //   finish_scale: *scale <- sqrt(*scale / N) (the root mean square of r from its square sum;
 //                 1 if that is 0);
-//   net_input: x0 = r / s, x1 = (p1 - p2) / s, x2 = (guess - p1) / s, x3 = plane_mask[plane]
-//              (1 next to a wall, else 0), with p1, p2 the two previous potentials;
+//   net_input: x0 = r / s, x1 = c / s (c: the coarse-grid solution of A c = r, prolonged),
+//              x2 = (p1 - p2) / s, x3 = (guess - p1) / s, x4 = plane_mask[plane] (1 next to a
+//              wall, else 0), with p1, p2 the two previous potentials;
 //   add_correction: psi[i] += alpha s y[i];
 //   correction_target: t[i] = (psi[i] - guess[i]) / (alpha s)  (alpha: output scale).
 hipError_t launch_finish_scale(double *scale, uint32_t N, hipStream_t stream);
-constexpr int WS_CHANNELS = 4;   // input channels of the warm-start network
-hipError_t launch_net_input(const double *r, const double *p1, const double *p2, const double *guess,
-                            const double *scale, float *x, uint32_t nxy, uint32_t nzf, const float *plane_mask,
-                            hipStream_t stream);
+constexpr int WS_CHANNELS = 5;   // input channels of the warm-start network
+hipError_t launch_net_input(const double *r, const double *coarse, const double *p1, const double *p2,
+                            const double *guess, const double *scale, float *x, uint32_t nxy, uint32_t nzf,
+                            const float *plane_mask, hipStream_t stream);
 hipError_t launch_add_correction(double *psi, const float *y, const double *scale, double alpha, uint32_t N,
                                  hipStream_t stream);
 hipError_t launch_correction_target(const double *psi, const double *guess, const double *scale, double alpha, float *t,

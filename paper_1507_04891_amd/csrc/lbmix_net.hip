@@ -1,10 +1,12 @@
 // gfx950 kernels of the learned warm start of the Poisson solve: 3 x 3 x 3 convolutions with
 // bias and ReLU (forward, transposed for the input gradient, weight gradient), mean-square
-// loss, Adam, and the glue between the FP64 potential and the FP32 network.  The network
-// works on lattices of a few hundred thousand nodes with at most 16 channels.  Convolutions
-// with at least 16 channel pairs run on the FP32 matrix cores (channels zero-padded to 16);
-// smaller ones use one thread per node that accumulates every output channel, with the
-// weights of the layer in LDS (read by all lanes at once).
+// loss, Adam, and the glue between the FP64 potential and the network.  The network works on
+// lattices of a few hundred thousand nodes with at most 16 channels.  Every convolution takes
+// its weights and its inputs rounded to BF16 (nearest-even) and accumulates in FP32; the
+// master parameters, the activations in memory and Adam stay FP32.  Convolutions with at
+// least 16 channel pairs run on the BF16 matrix cores (channels zero-padded to 16); smaller
+// ones use one thread per node that accumulates every output channel, with the weights of the
+// layer in LDS (read by all lanes at once).
 #include "lbmix_net.h"
 
 namespace lbmix {
@@ -29,11 +31,16 @@ __device__ __forceinline__ int64_t tap(int k, uint32_t x, uint32_t y, uint32_t z
 
 constexpr int NET_BLOCK = 256;
 
+// FP32 value rounded to BF16 (nearest-even) and back: the operands of every product.
+__device__ __forceinline__ float bf16r(float v) { return (float)(__bf16)v; }
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
     __shared__ float sw[NET_MAXC * NET_MAXC * NET_K];
     __shared__ float sb[NET_MAXC];
     const int nw = a.cout * a.cin * NET_K;
-    for (int i = threadIdx.x; i < nw; i += NET_BLOCK) sw[i] = a.w[i];
+    for (int i = threadIdx.x; i < nw; i += NET_BLOCK) sw[i] = bf16r(a.w[i]);
     if ((int)threadIdx.x < a.cout) sb[threadIdx.x] = a.b ? a.b[threadIdx.x] : 0.0f;
     __syncthreads();
     const uint32_t v = blockIdx.x * NET_BLOCK + threadIdx.x;
@@ -46,7 +53,7 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
         const int64_t nb = tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls);
         if (nb < 0) continue;
         for (int ci = 0; ci < a.cin; ++ci) {
-            const float xv = a.x[(size_t)ci * a.N + nb];
+            const float xv = bf16r(a.x[(size_t)ci * a.N + nb]);
             const float *wk = sw + ci * NET_K + k;
 #pragma unroll
             for (int co = 0; co < NET_MAXC; ++co)
@@ -59,20 +66,27 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3(const ConvArgs a) {
     }
 }
 
-// The same convolution on the FP32 matrix cores, channels zero-padded to 16: a dense
+// The same convolution on the BF16 matrix cores, channels zero-padded to 16: a dense
 // contraction y[co][v] = sum_{k, ci} w[co][ci][k] x[ci][v + offset_k] with K = 27 x 16.
-// Each wave computes tiles of 16 consecutive nodes (one 16 x 16 v_mfma_f32_16x16x4f32 output,
-// rows co, columns the nodes) in 108 steps of 4 (tap k, channels 4c..4c+3): lane l supplies
-// w[co = l mod 16][4c + l/16][k] from LDS and x[4c + l/16][neighbour of node l mod 16].  The
-// output rows 4 (l / 16) + r, r < 4, of column l mod 16 come back in the lane.
+// Each wave computes tiles of 16 consecutive nodes (one 16 x 16 v_mfma_f32_16x16x16_bf16
+// output, rows co, columns the nodes) in 27 steps, one per tap k, each over all 16 channels:
+// lane l supplies w[co = l mod 16][ci = 4 (l / 16) + q][k], q < 4, from LDS and
+// x[ci = 4 (l / 16) + q][neighbour of node l mod 16], both as four BF16 values.  The output
+// rows 4 (l / 16) + r, r < 4, of column l mod 16 come back in the lane (FP32).
 typedef float f32x4m __attribute__((ext_vector_type(4)));
 constexpr int MFMA_C = 16;
 
 __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
-    __shared__ float sw[MFMA_C * MFMA_C * NET_K];   // [co][ci][k], zero beyond cout, cin
-    for (int i = threadIdx.x; i < MFMA_C * MFMA_C * NET_K; i += NET_BLOCK) {
-        const int co = i / (MFMA_C * NET_K), ci = (i / NET_K) % MFMA_C, k = i % NET_K;
-        sw[i] = (co < a.cout && ci < a.cin) ? a.w[(co * a.cin + ci) * NET_K + k] : 0.0f;
+    __shared__ bf16x4 sw[MFMA_C * NET_K * 4];   // [co][k][g]: channels 4 g .. 4 g + 3, zero beyond cout, cin
+    for (int i = threadIdx.x; i < MFMA_C * NET_K * 4; i += NET_BLOCK) {
+        const int co = i / (NET_K * 4), k = (i / 4) % NET_K, g = i % 4;
+        bf16x4 v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int ci = 4 * g + q;
+            v[q] = (__bf16)((co < a.cout && ci < a.cin) ? a.w[(co * a.cin + ci) * NET_K + k] : 0.0f);
+        }
+        sw[i] = v;
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -91,15 +105,14 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
 #pragma unroll 3
         for (int k = 0; k < NET_K; ++k) {
             const int64_t nb = live ? tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls) : -1;
-            float bx[4], aw[4];
+            bf16x4 bx;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const int ci = 4 * c + lk;
-                bx[c] = (nb >= 0 && ci < a.cin) ? a.x[(size_t)ci * a.N + nb] : 0.0f;
-                aw[c] = sw[(li * MFMA_C + ci) * NET_K + k];
+            for (int q = 0; q < 4; ++q) {
+                const int ci = 4 * lk + q;
+                bx[q] = (__bf16)((nb >= 0 && ci < a.cin) ? a.x[(size_t)ci * a.N + nb] : 0.0f);
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aw[c], bx[c], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, sw[(li * NET_K + k) * 4 + lk]),
+                                                            __builtin_bit_cast(s16x4, bx), acc, 0, 0, 0);
         }
         if (live) {
 #pragma unroll
@@ -111,13 +124,13 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_mfma(const ConvArgs a) {
     }
 }
 
-// Weight gradients on the FP32 matrix cores, channels zero-padded to 16: for every tap k the 16 x 16
-// product gw_k[co][ci] = sum_v g[co][v] x[ci][v + offset_k] is a contraction over nodes.  Each
-// wave takes WG_CHUNK consecutive nodes, four per step (lane l: node l / 16 of the step,
-// channel l mod 16 of both operands), and keeps the 27 tap products in its registers, plus a
-// 28th with x = 1 whose column 0 is the bias gradient sum_v g[co][v]; the per-wave partial
-// products go to part[wave][k][co][ci] and are summed in FP64, in a fixed order, by
-// conv3_wgrad_sum.
+// Weight gradients on the BF16 matrix cores, channels zero-padded to 16: for every tap k the
+// 16 x 16 product gw_k[co][ci] = sum_v g[co][v] x[ci][v + offset_k] is a contraction over
+// nodes.  Each wave takes WG_CHUNK consecutive nodes, 16 per step (lane l: nodes 4 (l / 16) + q,
+// q < 4, of the step, channel l mod 16 of both operands, as BF16), and keeps the 27 tap
+// products in its registers (FP32), plus a 28th with x = 1 whose column 0 is the bias gradient
+// sum_v g[co][v]; the per-wave partial products go to part[wave][k][co][ci] and are summed in
+// FP64, in a fixed order, by conv3_wgrad_sum.
 constexpr uint32_t WG_CHUNK = 256;
 constexpr int WG_SLOTS = NET_K + 1;   // 27 taps and the bias
 
@@ -128,19 +141,34 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad_mfma(const ConvArgs a, 
     f32x4m acc[WG_SLOTS];
 #pragma unroll
     for (int k = 0; k < WG_SLOTS; ++k) acc[k] = f32x4m{0.0f, 0.0f, 0.0f, 0.0f};
-    for (uint32_t v0 = v_begin; v0 < v_begin + WG_CHUNK && v0 < a.N; v0 += 4) {
-        const uint32_t v = v0 + lk;
-        const bool live = v < a.N;
-        const uint32_t vv = live ? v : 0;
-        const uint32_t x = vv % a.nx, y = (vv / a.nx) % a.ny, z = vv / (a.nx * a.ny);
-        const float gv = (live && li < a.cout) ? g[(size_t)li * a.N + v] : 0.0f;   // A: g[co = li][node lk]
+    for (uint32_t v0 = v_begin; v0 < v_begin + WG_CHUNK && v0 < a.N; v0 += 16) {
+        uint32_t px[4], py[4], pz[4];
+        bool live[4];
+        bf16x4 gv, one;   // A: g[co = li][node 4 lk + q]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t v = v0 + 4 * lk + q;
+            live[q] = v < a.N;
+            const uint32_t vv = live[q] ? v : 0;
+            px[q] = vv % a.nx;
+            py[q] = (vv / a.nx) % a.ny;
+            pz[q] = vv / (a.nx * a.ny);
+            gv[q] = (__bf16)((live[q] && li < a.cout) ? g[(size_t)li * a.N + v] : 0.0f);
+            one[q] = (__bf16)(live[q] ? 1.0f : 0.0f);
+        }
 #pragma unroll
         for (int k = 0; k < NET_K; ++k) {
-            const int64_t nb = live ? tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls) : -1;
-            const float xv = (nb >= 0 && li < a.cin) ? a.x[(size_t)li * a.N + nb] : 0.0f;   // B: x[ci = li] at node lk
-            acc[k] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, xv, acc[k], 0, 0, 0);
+            bf16x4 xv;   // B: x[ci = li] at the neighbours of the same nodes
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t nb = live[q] ? tap(k, px[q], py[q], pz[q], a.nx, a.ny, a.nz, a.zwalls) : -1;
+                xv[q] = (__bf16)((nb >= 0 && li < a.cin) ? a.x[(size_t)li * a.N + nb] : 0.0f);
+            }
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, gv),
+                                                               __builtin_bit_cast(s16x4, xv), acc[k], 0, 0, 0);
         }
-        acc[NET_K] = __builtin_amdgcn_mfma_f32_16x16x4f32(gv, live ? 1.0f : 0.0f, acc[NET_K], 0, 0, 0);
+        acc[NET_K] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s16x4, gv),
+                                                               __builtin_bit_cast(s16x4, one), acc[NET_K], 0, 0, 0);
     }
     float *out = part + (size_t)wave * WG_SLOTS * MFMA_C * MFMA_C;
 #pragma unroll
@@ -185,7 +213,8 @@ __global__ __launch_bounds__(NET_BLOCK) void relu_mask(float *g, const float *y,
 }
 
 // One work-group per weight (co, ci, k), or per bias when k == NET_K: the sum over all nodes
-// in a fixed order (strided per thread, then a tree), accumulated in FP64.
+// of the BF16-rounded operands in a fixed order (strided per thread, then a tree), accumulated
+// in FP64.
 __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad(const ConvArgs a, const float *g, float *gw, float *gb) {
     __shared__ double red[NET_BLOCK];
     const int idx = blockIdx.x;
@@ -198,11 +227,11 @@ __global__ __launch_bounds__(NET_BLOCK) void conv3_wgrad(const ConvArgs a, const
     double s = 0.0;
     for (uint32_t v = threadIdx.x; v < a.N; v += NET_BLOCK) {
         if (bias) {
-            s += gc[v];
+            s += bf16r(gc[v]);
         } else {
             const uint32_t x = v % a.nx, y = (v / a.nx) % a.ny, z = v / (a.nx * a.ny);
             const int64_t nb = tap(k, x, y, z, a.nx, a.ny, a.nz, a.zwalls);
-            if (nb >= 0) s += (double)gc[v] * (double)xc[nb];
+            if (nb >= 0) s += (double)bf16r(gc[v]) * (double)bf16r(xc[nb]);
         }
     }
     red[threadIdx.x] = s;
@@ -256,17 +285,18 @@ __global__ void finish_scale(double *s, uint32_t N) {
     }
 }
 
-__global__ __launch_bounds__(NET_BLOCK) void net_input(const double *r, const double *p1, const double *p2,
-                                                       const double *guess, const double *scale, float *x,
-                                                       uint32_t nxy, uint32_t nzf, const float *mask) {
+__global__ __launch_bounds__(NET_BLOCK) void net_input(const double *r, const double *coarse, const double *p1,
+                                                       const double *p2, const double *guess, const double *scale,
+                                                       float *x, uint32_t nxy, uint32_t nzf, const float *mask) {
     const uint32_t i = blockIdx.x * NET_BLOCK + threadIdx.x;
     const uint32_t N = nxy * nzf;
     if (i >= N) return;
     const double inv = 1.0 / *scale, a = p1[i];
     x[i] = (float)(r[i] * inv);
-    x[N + i] = (float)((a - p2[i]) * inv);
-    x[2 * N + i] = (float)((guess[i] - a) * inv);
-    x[3 * N + i] = mask ? mask[i / nxy] : 0.0f;
+    x[N + i] = (float)(coarse[i] * inv);
+    x[2 * N + i] = (float)((a - p2[i]) * inv);
+    x[3 * N + i] = (float)((guess[i] - a) * inv);
+    x[4 * N + i] = mask ? mask[i / nxy] : 0.0f;
 }
 
 __global__ __launch_bounds__(NET_BLOCK) void add_correction(double *psi, const float *y, const double *scale,
@@ -350,11 +380,11 @@ hipError_t launch_finish_scale(double *scale, uint32_t N, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_net_input(const double *r, const double *p1, const double *p2, const double *guess,
-                            const double *scale, float *x, uint32_t nxy, uint32_t nzf, const float *plane_mask,
-                            hipStream_t stream) {
-    hipLaunchKernelGGL(net_input, grid_of(nxy * nzf), dim3(NET_BLOCK), 0, stream, r, p1, p2, guess, scale, x, nxy, nzf,
-                       plane_mask);
+hipError_t launch_net_input(const double *r, const double *coarse, const double *p1, const double *p2,
+                            const double *guess, const double *scale, float *x, uint32_t nxy, uint32_t nzf,
+                            const float *plane_mask, hipStream_t stream) {
+    hipLaunchKernelGGL(net_input, grid_of(nxy * nzf), dim3(NET_BLOCK), 0, stream, r, coarse, p1, p2, guess, scale, x,
+                       nxy, nzf, plane_mask);
     return hipGetLastError();
 }
 

@@ -70,6 +70,7 @@ struct lbmix_ctx {
     int warm_start = 0;               // 0 previous potential, 1 extrapolation in time, 2 learned
     lbmix_net *ws_net = nullptr;      // borrowed network of the learned warm start
     double *ws_r = nullptr, *ws_guess = nullptr, *ws_scale = nullptr;   // residual, guess, rms (device)
+    double *ws_c = nullptr;           // coarse-grid solution of A c = r, prolonged to the fluid
     float *ws_x = nullptr, *ws_y = nullptr, *ws_t = nullptr, *ws_mask = nullptr;
     double *psi_prev = nullptr;       // two previous solutions (warm_start 1)
     int have_prev = 0;
@@ -892,6 +893,7 @@ int ensure_ws_buffers(lbmix_ctx *c) {
     const size_t N = c->Nf;
     int rc;
     if ((rc = c->hip(hipMalloc((void **)&c->ws_r, N * sizeof(double)), "hipMalloc(warm start)")) ||
+        (rc = c->hip(hipMalloc((void **)&c->ws_c, N * sizeof(double)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_guess, N * sizeof(double)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_scale, sizeof(double)), "hipMalloc(warm start)")) ||
         (rc = c->hip(hipMalloc((void **)&c->ws_x, WS_CHANNELS * N * sizeof(float)), "hipMalloc(warm start)")) ||
@@ -909,18 +911,76 @@ int ensure_ws_buffers(lbmix_ctx *c) {
                   "copy mask");
 }
 
-// Network input after the extrapolation (history complete): the residual of the guess, the
-// last two increments of the potential (psi(t-1) - psi(t-2), psi(t-2) - psi(t-3) = guess -
-// psi(t-1)), all over s = rms(r), and the wall mask.
+// The coarse-grid part of A^-1 r for the network's input, which a 3 x 3 x 3 network of a few
+// layers cannot form itself (the inverse of the operator is global): r restricted down the
+// multigrid hierarchy, the coarse end solved as in a V-cycle, the result interpolated back to
+// the fluid nodes without smoothing on the way up (into ws_c).
+int coarse_correction(lbmix_ctx *c) {
+    int rc;
+    if ((rc = mg_build(c))) return rc;
+    const int nl = (int)c->mg.size();
+    if ((rc = c->hip(hipMemsetAsync(c->ws_c, 0, (size_t)c->Nf * sizeof(double), c->stream), "hipMemset(ws_c)")))
+        return rc;
+    if (nl < 2) return LBMIX_OK;
+    std::vector<MGLevel> lev(c->mg);
+    lev[0].e = c->ws_c;
+    lev[0].r = c->ws_r;
+    // the levels from lb down are solved together in one work-group (as in the V-cycle); a
+    // channel stack relaxes z lines down to one column per channel, where that is exact
+    int lb = nl;
+    if (!c->mg_lines) {
+        for (int l = 1; l < nl; ++l)
+            if ((size_t)lev[l].nx * lev[l].ny * lev[l].nz <= kBottomCells) { lb = l; break; }
+        size_t cells = 0;
+        for (int l = lb; l < nl; ++l) cells += (size_t)lev[l].nx * lev[l].ny * lev[l].nz;
+        if (lb < nl && (nl - lb > MG_MAX_BOTTOM || cells > (size_t)MG_BOTTOM_LDS)) lb = nl;
+    }
+    const int top = lb < nl ? lb : nl - 1;   // the first level not on the way down
+    for (int l = 0; l < top; ++l)
+        if ((rc = c->hip(launch_mg_restrict(lev[l], lev[l + 1], c->stream), "mg_restrict"))) return rc;
+    if (lb < nl) {
+        MGBottom bb{};
+        bb.n = nl - lb;
+        for (int l = lb; l < nl; ++l) bb.lev[l - lb] = lev[l];
+        const MGLevel &B = lev[nl - 1];
+        bb.coarse_sweeps = std::max(20, 4 * (int)std::max(B.nx, std::max(B.ny, B.nz)));
+        bb.coarse_inv = c->mg_cinv;
+        if ((rc = c->hip(launch_mg_bottom(bb, c->stream), "mg_bottom"))) return rc;
+    } else {
+        const MGLevel &B = lev[nl - 1];
+        const bool exact = c->mg_lines && B.nx == 1 && B.ny == 1;
+        const int count = exact ? 1 : std::max(20, 4 * (int)std::max(B.nx, std::max(B.ny, B.nz)));
+        for (int k = 0; k < count; ++k)
+            for (int col = 0; col < 2; ++col) {
+                if (c->mg_lines) {
+                    if ((rc = c->hip(launch_mg_line_rhs(B, col, c->stream), "mg_line_rhs")) ||
+                        (rc = c->hip(launch_mg_line_solve(B, col, c->mg_idn[nl - 1], c->mg_idn_last[nl - 1], c->d_first,
+                                                          (uint32_t)c->nch, c->stream),
+                                     "mg_line_solve")))
+                        return rc;
+                } else if ((rc = c->hip(launch_mg_smooth(B, col, c->stream), "mg_smooth"))) {
+                    return rc;
+                }
+            }
+    }
+    for (int l = top - 1; l >= 0; --l)
+        if ((rc = c->hip(launch_mg_prolong(lev[l], lev[l + 1], c->stream), "mg_prolong"))) return rc;
+    return LBMIX_OK;
+}
+
+// Network input after the extrapolation (history complete): the residual of the guess, its
+// coarse-grid solution, the last two increments of the potential (psi(t-1) - psi(t-2),
+// psi(t-2) - psi(t-3) = guess - psi(t-1)), all over s = rms(r), and the wall mask.
 int net_sample_input(lbmix_ctx *c, const PoissonArgs &pa) {
     int rc = ensure_ws_buffers(c);
     if (rc) return rc;
     uint32_t nb = 0;
     if ((rc = c->hip(launch_residual_field(pa, c->ws_r, c->partials, &nb, c->stream), "residual_field")) ||
         (rc = c->hip(launch_finalize(c->partials, nb, 1, c->ws_scale, 0, 0.0, 0.0, 1.0, c->stream), "finalize")) ||
-        (rc = c->hip(launch_finish_scale(c->ws_scale, c->Nf, c->stream), "finish_scale")))
+        (rc = c->hip(launch_finish_scale(c->ws_scale, c->Nf, c->stream), "finish_scale")) ||
+        (rc = coarse_correction(c)))
         return rc;
-    return c->hip(launch_net_input(c->ws_r, c->psi_prev, c->psi_prev + c->Nf, c->psi, c->ws_scale, c->ws_x,
+    return c->hip(launch_net_input(c->ws_r, c->ws_c, c->psi_prev, c->psi_prev + c->Nf, c->psi, c->ws_scale, c->ws_x,
                                    (uint32_t)c->nx * c->ny, (uint32_t)c->nzf, c->ws_mask, c->stream),
                   "net_input");
 }
@@ -2022,7 +2082,7 @@ void lbmix_destroy(lbmix_ctx *c) {
         if (c->mg_b) (void)hipFree(c->mg_b);
         if (c->mg_cinv) (void)hipFree(c->mg_cinv);
         if (c->psi_prev) (void)hipFree(c->psi_prev);
-        for (void *p : {(void *)c->ws_r, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
+        for (void *p : {(void *)c->ws_r, (void *)c->ws_c, (void *)c->ws_guess, (void *)c->ws_scale, (void *)c->ws_x, (void *)c->ws_y,
                         (void *)c->ws_t, (void *)c->ws_mask})
             if (p) (void)hipFree(p);
         for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_piv_end, c->sp_pmid,
