@@ -89,7 +89,7 @@ def test_channel_stack_validation_without_device(L):
     assert L.lbmix_set_channel(h, 0, 0.5, 0, 0) == -1              # tau_drag in (0, 1/2]
     assert L.lbmix_set_channel(h, 0, 0.6, -1e-4, -2e-4) == 0
     assert L.lbmix_set_channel(h, 1, 0.0, 0, 0) == 0               # the context's drag
-    assert L.lbmix_set_poisson_method(h, 1) == -1                  # multigrid: one lattice only
+    assert L.lbmix_set_poisson_method(h, 1) == 0                   # multigrid: z-line relaxation per channel
     assert L.lbmix_set_poisson_method(h, 2) == 0
     L.lbmix_destroy(h)
     assert L.lbmix_create(ctypes.byref(h), 8, 8, 10, 1, 2, None) == 0
