@@ -217,10 +217,14 @@ struct lbmix_ctx {
                 a.cwo[s][k] = kW[rep] * (1.0 / tau_v) * (double)scale[s][rep];
                 a.cwf[s][k] = (float)a.cw[s][k];
                 a.cwof[s][k] = (float)a.cwo[s][k];
+                a.inv_scale_k[s][k] = (double)inv_scale[s][rep];
             }
+            a.rho_bar_f[s] = (float)a.rho_bar[s];
         }
         a.omega_v = 1.0 / tau_v;
         a.omega_d = omega_drag();
+        a.omega_v_f = (float)a.omega_v;
+        a.omega_d_f = (float)a.omega_d;
         a.pair_drag = pair_ns >= 3 ? 1 : 0;
         a.forcing = forcing;
         for (int s = 0; s < MAXS; ++s)

@@ -43,7 +43,12 @@ struct StepArgs {
     // w_k omega_visc scale_k, in FP64 and FP32
     double cw[MAXS][3], cwo[MAXS][3];
     float cwf[MAXS][3], cwof[MAXS][3];
+    double inv_scale_k[MAXS][3];     // inv_scale of weight class k, in FP64
     double omega_v, omega_d;
+    // the same parameters in FP32 for the FP32-arithmetic kernels (the scalar unit has no
+    // floating-point conversion, so converting them in the kernel takes vector instructions)
+    float rho_bar_f[MAXS];
+    float omega_v_f, omega_d_f;
     int pair_drag;                   // 1: drag frequency per pair (three or more species)
     double omega_pair[MAXS][MAXS];   // symmetric; the diagonal is not used
     int forcing;                     // 0: forcing of the Appendix; 1: the Guo-type variant

@@ -45,6 +45,25 @@ __host__ __device__ constexpr int cz(int p) {
     return t[p];
 }
 __host__ __device__ constexpr int opp(int p) { return p == 0 ? 0 : ((p & 1) ? p + 1 : p - 1); }
+// c_p . (x, y, z) with the zero components left out: IEEE arithmetic does not fold a product
+// by zero away (0 * inf is NaN), so the plain three-term form costs instructions that compute
+// nothing.  A D3Q19 direction has one or two non-zero components, so the result takes at most
+// one addition and is the same number.
+template <int P, class C>
+__device__ __forceinline__ C cdot(C x, C y, C z) {
+    constexpr int X = cx(P), Y = cy(P), Z = cz(P);
+    static_assert(X != 0 || Y != 0 || Z != 0, "rest direction");
+    C r = C(0);
+    bool first = true;
+    auto add = [&](int c, C v) {
+        r = first ? (c > 0 ? v : -v) : (c > 0 ? r + v : r - v);
+        first = false;
+    };
+    if constexpr (X != 0) add(X, x);
+    if constexpr (Y != 0) add(Y, y);
+    if constexpr (Z != 0) add(Z, z);
+    return r;
+}
 template <class C>
 __host__ __device__ constexpr C wgt(int p) {
     return p == 0 ? C(1) / C(3) : (p < 7 ? C(1) / C(18) : C(1) / C(36));
@@ -99,8 +118,9 @@ template <> struct Codec<float> {
     __device__ static S encode(C v, float, uint32_t = 0) { return v; }
 };
 // Counter-based 32-bit hash (the "lowbias32" integer mixer: xor-shift / multiply rounds
-// with the published constants 0x7feb352d and 0x846ca68b).  Two of its values seed, once per
-// node and step, a Marsaglia xorshift64 stream (shifts 13, 7, 17, a full-period triple of his
+// with the published constants 0x7feb352d and 0x846ca68b) of the node and step seeds the high
+// half, and the node index mixed with the step seed the low half, of a Marsaglia xorshift64
+// stream per node and step (shifts 13, 7, 17, a full-period triple of his
 // "Xorshift RNGs") that supplies the random bits of stochastic rounding: each 64-bit draw gives
 // the 32-bit words of two directions (its high, then its low half), and a word's high and low
 // halves go to the two species of a pair.  The 64-bit shifts are single instructions on
@@ -449,6 +469,12 @@ void stream_collide(const StepArgs a) {
 
     // inverse storage scale of each species and weight class (1 in the unscaled forms)
     auto isc = [&](int s, int k) -> C { return CD::kScaled ? C(a.inv_scale[s][kClassRep[k]]) : C(1); };
+    auto iscd = [&](int s, int k) -> double { return CD::kScaled ? a.inv_scale_k[s][k] : 1.0; };
+    // a parameter in the arithmetic type (FP32 kernels take the host's FP32 copy)
+    auto par = [](double d, float f) -> C {
+        if constexpr (sizeof(C) == sizeof(float)) return f;
+        else return C(d);
+    };
 
     // 1. pull streaming with bounce-back: one vector load of all species per direction; the
     //    values stay in stored units (h = d * scale)
@@ -518,7 +544,7 @@ void stream_collide(const StepArgs a) {
             jy[s] = my;
             jz[s] = mz;
             dnh[s] = (CD::kWide == 1 && wide) ? m0h : double(m0);
-            n[s] = C(a.rho_bar[s]) + dn[s];
+            n[s] = par(a.rho_bar[s], a.rho_bar_f[s]) + dn[s];
             ntot += n[s];
             sjx += jx[s];
             sjy += jy[s];
@@ -547,10 +573,9 @@ void stream_collide(const StepArgs a) {
         dnh[s] = double(dn[s]);
         if constexpr (CD::kWide == 2) {
             if (wide)
-                dnh[s] = (double(v[0]) * double(isc(s, 0)) + double(m1) * double(isc(s, 1))) +
-                         double(m2) * double(isc(s, 2));
+                dnh[s] = (double(v[0]) * iscd(s, 0) + double(m1) * iscd(s, 1)) + double(m2) * iscd(s, 2);
         }
-        n[s] = C(a.rho_bar[s]) + dn[s];
+        n[s] = par(a.rho_bar[s], a.rho_bar_f[s]) + dn[s];
         ntot += n[s];
         sjx += jx[s];
         sjy += jy[s];
@@ -593,7 +618,7 @@ void stream_collide(const StepArgs a) {
     //    F_s = -od (u_s + a_s/2 - (u + sum n a / 2 ntot)) + a_s (or per pair, or the
     //    Guo-type variant), then the coefficients of the collision that are common to
     //    every direction
-    const C ov = C(a.omega_v), od = C(SLIT ? a.planes[z].omega_d : a.omega_d);
+    const C ov = par(a.omega_v, a.omega_v_f), od = SLIT ? C(a.planes[z].omega_d) : par(a.omega_d, a.omega_d_f);
     C uax[NS], uay[NS], uaz[NS], Fx[NS], Fy[NS], Fz[NS];
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -673,13 +698,15 @@ void stream_collide(const StepArgs a) {
     // class's storage scale):
     //   f*_p = (1 - ov) d_p + W_k [base + 4.5 ov n (c.u_s)^2 + 9 n (c.F)(c.u)]
     //          +- 3 W_k n (ov c.u_s + c.F) + W_k ov dn
-    // The last term is split hi + lo: lo joins the symmetric part B_k, hi is added last, so the
-    // stored value rounds like the FP64 sum (the other terms are far below hi, or carry their
-    // own FP32 rounding).
+    // With the FP64 carry the last term is split hi + lo (hi its FP32 rounding, lo the rest).
     //   The 16-bit forms (bound by instruction issue) take the weight into per-class
-    //   coefficients here; the others (bound by HBM) multiply by the constant weight where a
-    //   direction is collided, which keeps this block, and the time before a wave's first
-    //   store, short.
+    //   coefficients here and fold the whole term into the symmetric part, B_k + lo + hi, once
+    //   per class: that saves an add per direction and species, and over 8 rounding streams the
+    //   diffusivity at Sc = 100 came out the same as with hi added last (the stored value is
+    //   rounded to 11 or 8 bits afterwards).  The others (bound by HBM, stored in FP32) add lo
+    //   and then hi last, so the stored value rounds like the FP64 sum, and multiply by the
+    //   constant weight where a direction is collided, which keeps this block, and the time
+    //   before a wave's first store, short.
     constexpr bool kF64 = sizeof(C) == 8;
     constexpr bool kPre = CD::kPacked;
     C B[NS][3], O[NS][3], N9[NS][3], M3[NS][3], bhi[NS][3], blo[NS][3];
@@ -701,10 +728,10 @@ void stream_collide(const StepArgs a) {
                 const double big = a.cwo[s][k] * dnh[s];                  // w_k ov scale_k dn
                 bhi[s][k] = C(big);
                 blo[s][k] = C(big - double(bhi[s][k]));
-                if constexpr (kPre) B[s][k] += blo[s][k];
             } else {
                 bhi[s][k] = (kF64 ? C(a.cwo[s][k]) : C(a.cwof[s][k])) * dn[s];
             }
+            if constexpr (kPre) B[s][k] = (B[s][k] + blo[s][k]) + bhi[s][k];
         }
     }
 
@@ -715,7 +742,7 @@ void stream_collide(const StepArgs a) {
     auto collide_store = [&](auto sr_tag) {
         constexpr bool SR = decltype(sr_tag)::value;
         const uint32_t seed = a.step_dev ? step_seed(a.round_seed, *a.step_dev + 1ull) : a.seed;
-        uint64_t rs = SR ? ((uint64_t(mix32(own ^ seed)) << 32) | uint64_t(mix32(own ^ seed ^ 0x9e3779b9u)) | 1ull)
+        uint64_t rs = SR ? ((uint64_t(mix32(own ^ seed)) << 32) | uint64_t(own ^ (seed * 0x9e3779b9u)) | 1ull)
                          : 0ull;
         uint32_t word = 0u, spare = 0u;
         bool have_spare = false;
@@ -763,7 +790,7 @@ void stream_collide(const StepArgs a) {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 if constexpr (kPre)
-                    v0[s] = (keep * hc(s, 0) + B[s][0]) + bhi[s][0];
+                    v0[s] = keep * hc(s, 0) + B[s][0];
                 else
                     v0[s] = ((keep * hc(s, 0) + wgt<C>(0) * B[s][0]) + blo[s][0]) + bhi[s][0];
             }
@@ -773,17 +800,17 @@ void stream_collide(const StepArgs a) {
             constexpr int p = 2 * decltype(kc)::value + 1;   // 1, 3, ..., 17
             constexpr int pb = p + 1;
             constexpr int k = wclass(p);
-            const C cub = C(cx(p)) * ux + C(cy(p)) * uy + C(cz(p)) * uz;
+            const C cub = cdot<p>(ux, uy, uz);
             C vp[NS], vb[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                const C cu = C(cx(p)) * uax[s] + C(cy(p)) * uay[s] + C(cz(p)) * uaz[s];
-                const C cF = C(cx(p)) * Fx[s] + C(cy(p)) * Fy[s] + C(cz(p)) * Fz[s];
+                const C cu = cdot<p>(uax[s], uay[s], uaz[s]);
+                const C cF = cdot<p>(Fx[s], Fy[s], Fz[s]);
                 if constexpr (kPre) {
                     const C sym = (B[s][k] + O[s][k] * (cu * cu)) + N9[s][k] * (cF * cub);
                     const C anti = M3[s][k] * (ov * cu + cF);
-                    vp[s] = ((keep * hc(s, p) + sym) + anti) + bhi[s][k];
-                    vb[s] = ((keep * hc(s, pb) + sym) - anti) + bhi[s][k];
+                    vp[s] = (keep * hc(s, p) + sym) + anti;
+                    vb[s] = (keep * hc(s, pb) + sym) - anti;
                 } else {
                     constexpr C w = wgt<C>(p);
                     const C sym = w * (B[s][k] + O[s][k] * cu * cu + N9[s][k] * cF * cub);
@@ -809,7 +836,7 @@ void stream_collide(const StepArgs a) {
     for (int s = 0; s < NS; ++s) v[s] = active ? dnh[s] : 0.0;
     const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     const uint32_t nb = gridDim.x * gridDim.y * gridDim.z;
-    block_sum_store<NS>(v, a.partials, nb, bid);
+    block_sum_store_dpp<NS>(v, a.partials, nb, bid);
 }
 
 
