@@ -558,16 +558,31 @@ def bench_precision(args):
     name = lambda st, sr, wd=True: st + ("" if sr is None else (" SR" if sr else " RNE")) + ("" if wd else " narrow")
     out = {"workload": "D: binary sine 128x64x64 (amp 1e-3); nu: shear wave 128x64x64, tau 0.8; "
                        "mobility: charged slit 16x16x34, lambda_D 4, sigma -1e-4, E_x 1e-5, Sc 100"}
+    def diffusivity(w, st, sr, wd, seed, t1, t2):
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=seed, wide=wd)
+        lat.step(t1)
+        a1 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
+        lat.step(t2 - t1)
+        a2 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
+        return -math.log(a2 / a1) / (t2 - t1) / k ** 2 if a2 / a1 > 0 else None
+
+    def mobility(w, st, sr, wd, seed):
+        lat = P.from_workload(w, storage=st, stochastic=sr, seed=seed, poisson=dict(method="direct"), wide=wd)
+        lat.step(28000)
+        acc = None
+        for _ in range(20):
+            lat.step(100)
+            pr = lat.zprofiles()
+            acc = pr if acc is None else acc + pr
+        pr = acc / 20
+        rho = pr[:, 0, 1:-1].sum(0)
+        return float(pr[:, 1, 1:-1].sum(0)[16] / rho[16] / 1e-5)
+
+    sine = {}
     for sc, t1, t2 in [(10.0, 300, 6300), (100.0, 2000, 22000)]:
-        w = WL.binary_sine(L, 64, 64, amp=1e-3, tau_visc=1.0, sc=sc)
+        sine[sc] = WL.binary_sine(L, 64, 64, amp=1e-3, tau_visc=1.0, sc=sc), t1, t2
         for st, sr, wd in forms:
-            lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, wide=wd)
-            lat.step(t1)
-            a1 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
-            lat.step(t2 - t1)
-            a2 = float(((lat.moments(0)[0] - 0.5) * basis).sum())
-            out[f"D Sc={sc:g} {name(st, sr, wd)}"] = -math.log(a2 / a1) / (t2 - t1) / k ** 2 if a2 / a1 > 0 else None
-            del lat
+            out[f"D Sc={sc:g} {name(st, sr, wd)}"] = diffusivity(sine[sc][0], st, sr, wd, 7, t1, t2)
             print(f"D Sc={sc:g} {name(st, sr, wd)} done", file=sys.stderr, flush=True)
     shape = (64, 64, L)
     u = np.zeros((3,) + shape)
@@ -582,22 +597,23 @@ def bench_precision(args):
         lat.step(3000)
         out[f"nu {name(st, sr, wd)}"] = -math.log(amp() / a1) / 3000 / k ** 2
         del lat
-    w = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
+    slit = WL.charged_slit(nx=16, ny=16, nz=34, n_ion=1e-3, debye_length=4.0, sigma=-1e-4, Ex=1e-5, sc=100.0)
     for st, sr, wd in forms:
-        lat = P.from_workload(w, storage=st, stochastic=sr, seed=7, poisson=dict(method="direct"), wide=wd)
-        lat.step(28000)
-        acc = None
-        for _ in range(20):
-            lat.step(100)
-            pr = lat.zprofiles()
-            acc = pr if acc is None else acc + pr
-        pr = acc / 20
-        rho = pr[:, 0, 1:-1].sum(0)
-        out[f"mobility {name(st, sr, wd)}"] = float(pr[:, 1, 1:-1].sum(0)[16] / rho[16] / 1e-5)
-        del lat
+        out[f"mobility {name(st, sr, wd)}"] = mobility(slit, st, sr, wd, 7)
         print(f"mobility {name(st, sr, wd)} done", file=sys.stderr, flush=True)
+    # spread over rounding streams of the stochastically rounded 16-bit forms: relative errors
+    # against FP64 for 8 seeds, their mean and sample standard deviation
+    seeds = list(range(7, 15))
+    w, t1, t2 = sine[100.0]
+    for st in ("f16s", "bf16s"):
+        errs = {"D Sc=100": [diffusivity(w, st, True, True, s, t1, t2) / out["D Sc=100 f64"] - 1 for s in seeds],
+                "mobility": [mobility(slit, st, True, True, s) / out["mobility f64"] - 1 for s in seeds]}
+        for q, e in errs.items():
+            out[f"streams {q} {st} SR"] = {"seeds": seeds, "err": e, "mean": float(np.mean(e)),
+                                           "std": float(np.std(e, ddof=1))}
+        print(f"streams {st} done", file=sys.stderr, flush=True)
     for key in list(out):
-        if key == "workload" or " f64" in key or out[key] is None:
+        if key == "workload" or " f64" in key or key.startswith("streams") or out[key] is None:
             continue
         ref = out[key.split(" ")[0] + (" " + key.split(" ")[1] if key.startswith("D") else "") + " f64"]
         out["err " + key] = out[key] / ref - 1.0
