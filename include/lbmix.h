@@ -398,6 +398,18 @@ int lbmix_get_potential(lbmix_ctx *ctx, double *psi_out);
  * Synchronises. */
 int lbmix_get_mass_totals(lbmix_ctx *ctx, double *totals);
 
+/* FP64 totals sum_x n^alpha(x) of every species, host [nspecies], of the state the last
+ * stream-collide launch read (the populations after streaming, before the collision; streaming
+ * moves or reflects every population, so this is the mass of the state before that step),
+ * from the per-work-group FP64 partials the fused step writes (continuity, eq. `continuityb`:
+ * a mass monitor that needs no extra pass over the populations).  The shifted forms' shift is
+ * added back.  With the FP64 carry of the density deviation (lbmix_set_arithmetic mode 1) the
+ * FP32 forms sum every stored value in FP64 and the 16-bit forms each weight class in FP32;
+ * in mode 0 each node's deviation is an FP32 sum.  Fixed summation order (bitwise
+ * reproducible).  Synchronises.  Errors: EINVAL for a null output, ESTATE before the first
+ * step; a non-finite total latches ENONFINITE. */
+int lbmix_get_step_mass(lbmix_ctx *ctx, double *totals);
+
 /* Plane averages over x and y of the pre-collision moments at the current time, host
  * [nspecies][4][nz]: n, j_x, j_y, j_z per plane (wall planes 0), FP64 in a fixed order.
  * These give the channel observables of Sec. IV: mass flow, electric current and its

@@ -7,8 +7,8 @@ mass-diffusion (omega_drag) time scales, interspecies drag, and the electrostati
 a lattice Poisson solve with charged walls.  :mod:`.lbmix` is its ctypes binding.
 """
 from .lbmix import (  # noqa: F401
-    Lattice, Net, LbmixError, load_library, from_workload, device_copy, STORAGE, GEOMETRY, ELEMENT_BYTES, EXPORTS,
+    Lattice, Net, MetricsLog, LbmixError, load_library, from_workload, device_copy, STORAGE, GEOMETRY, ELEMENT_BYTES, EXPORTS,
     OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENOCONV, ENONFINITE,
 )
 
-__all__ = ["Lattice", "Net", "LbmixError", "load_library", "from_workload", "device_copy"]
+__all__ = ["Lattice", "Net", "MetricsLog", "LbmixError", "load_library", "from_workload", "device_copy"]

@@ -89,6 +89,7 @@ struct lbmix_ctx {
     size_t partials_cap = 0;
     double *step_partials = nullptr;  // mass partials of the last stream-collide
     uint32_t step_nb = 0;             // capacity in blocks (the largest candidate launch)
+    uint32_t part_nb = 0;             // blocks of the last stream-collide launch (0: none yet)
     uint32_t blk_x = 0, blk_y = 0;    // launch shape of stream_collide (0: default)
     double *dred = nullptr;           // device results of reductions (16 doubles)
     double *hred = nullptr;           // pinned host mirror
@@ -188,6 +189,12 @@ struct lbmix_ctx {
         uint32_t m = g.x * g.y * g.z;
         for (auto &sh : step_shapes()) {
             g = step_grid(nx, ny, nzf, &b, sh.first, sh.second);
+            m = std::max(m, g.x * g.y * g.z);
+        }
+        for (bool sr : {false, true}) {   // the default shapes of either rounding
+            uint32_t bx, by;
+            step_shape(st, sr, ns, (uint32_t)nx, 0, 0, &bx, &by);
+            g = step_grid(nx, ny, nzf, &b, bx, by);
             m = std::max(m, g.x * g.y * g.z);
         }
         return m;
@@ -436,6 +443,12 @@ constexpr int kPre0 = 1, kPost0 = 1, kPre = 2, kPost = 2;
 // e_down) = g with Ld its lateral diagonal: one forward recurrence from the first plane of a
 // channel, shared by every channel before its last plane (idn[k], k < longest - 1), and the
 // last plane of each channel (idn_last[c]; 0 where the line is singular, which pins that plane).
+// One stream-collide launch; remembers how many work-groups wrote mass partials.
+hipError_t collide(lbmix_ctx *c, const StepArgs &a, bool field, bool charged, hipStream_t st) {
+    c->part_nb = stream_collide_blocks(c->st, c->ns, a);
+    return launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, st);
+}
+
 int mg_line_pivots(lbmix_ctx *c, const MGLevel &L) {
     const double Ld = (L.nx > 1 ? 2.0 * L.ax : 0.0) + (L.ny > 1 ? 2.0 * L.ay : 0.0), az = L.az;
     int longest = 1;
@@ -1150,7 +1163,7 @@ int capture_step(lbmix_ctx *c, int par) {
     }
     StepArgs a = c->args();
     a.step_dev = c->step_dev;
-    int r1 = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->cap_stream), "stream_collide");
+    int r1 = c->hip(collide(c, a, field, charged, c->cap_stream), "stream_collide");
     if (!r1 && charged) {
         c->cur = par ^ 1;   // the solve sees the state the step writes (q is written by the step)
         r1 = spec_solve(c, c->pargs());
@@ -1515,7 +1528,7 @@ int lbmix_train_warm_start(lbmix_ctx *c, lbmix_net *net, int nsteps, float lr, d
     const bool field = c->field();
     for (int k = 0; k < nsteps; ++k) {
         const StepArgs a = c->args();
-        if ((rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, true, a, c->stream), "stream_collide")))
+        if ((rc = c->hip(collide(c, a, field, true, c->stream), "stream_collide")))
             return rc;
         c->cur ^= 1;
         c->steps++;
@@ -1684,7 +1697,7 @@ int lbmix_step(lbmix_ctx *c, int nsteps) {
     }
     for (int k = 0; k < nsteps; ++k) {
         const StepArgs a = c->args();
-        rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
+        rc = c->hip(collide(c, a, field, charged, c->stream), "stream_collide");
         if (rc) return rc;
         c->cur ^= 1;
         c->steps++;
@@ -1734,10 +1747,10 @@ int lbmix_autotune(lbmix_ctx *c, int reps) {
             StepArgs a = c->args();
             a.block_x = cand[i].first;
             a.block_y = cand[i].second;
-            rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream), "stream_collide");
+            rc = c->hip(collide(c, a, field, charged, c->stream), "stream_collide");
             if (!rc) rc = c->hip(hipEventRecord(e0, c->stream), "hipEventRecord");
             for (int k = 0; !rc && k < reps; ++k)
-                rc = c->hip(launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, c->stream),
+                rc = c->hip(collide(c, a, field, charged, c->stream),
                             "stream_collide");
             if (!rc) rc = c->hip(hipEventRecord(e1, c->stream), "hipEventRecord");
             if (!rc) rc = c->hip(hipEventSynchronize(e1), "hipEventSynchronize");
@@ -1868,6 +1881,30 @@ int lbmix_get_mass_totals(lbmix_ctx *c, double *totals) {
     bool finite = true;
     for (int s = 0; s < c->ns; ++s) {
         totals[s] = c->hred[s];
+        finite = finite && std::isfinite(totals[s]);
+    }
+    if (!finite) {
+        c->latched = LBMIX_ENONFINITE;
+        return c->fail(LBMIX_ENONFINITE, "non-finite mass total");
+    }
+    return LBMIX_OK;
+}
+
+int lbmix_get_step_mass(lbmix_ctx *c, double *totals) {
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (!totals) return c->fail(LBMIX_EINVAL, "null output");
+    if (c->part_nb == 0) return c->fail(LBMIX_ESTATE, "no step has run");
+    Guard g(c);
+    if ((rc = c->hip(launch_finalize(c->step_partials, c->part_nb, c->ns, c->dred + 8, 0, 0, 0, 1, c->stream),
+                     "finalize")))
+        return rc;
+    if ((rc = c->hip(hipMemcpyAsync(c->hred, c->dred + 8, c->ns * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy")))
+        return rc;
+    if ((rc = c->hip(hipStreamSynchronize(c->stream), "hipStreamSynchronize"))) return rc;
+    bool finite = true;
+    for (int s = 0; s < c->ns; ++s) {
+        totals[s] = c->hred[s] + c->rho_bar(s) * (double)c->Nf;
         finite = finite && std::isfinite(totals[s]);
     }
     if (!finite) {

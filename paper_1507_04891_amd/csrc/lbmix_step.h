@@ -77,12 +77,17 @@ dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx = 0, uint32_t by = 0);
 
 // The work-group shape launch_stream_collide uses: the set one (bx_set, by_set), or 0 x 0 for
-// step_grid's default, except one row of up to 256 nodes for FP32 with stochastic rounding and
-// at most two species (its register budget allows three waves per SIMD).
+// step_grid's default, except where the register budget allows three waves per SIMD: one row
+// of up to 256 nodes for FP32 with stochastic rounding and at most two species, and 128
+// threads (128 nodes of a row, or 128 / nx whole rows of a narrow plane) for three species in
+// 16 bits.
 void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set, uint32_t by_set, uint32_t *bx,
                 uint32_t *by);
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,
                                  const StepArgs &a, hipStream_t stream);
+// Work-groups of the launch launch_stream_collide makes for these arguments (the length of each
+// species' row of FP64 mass partials it writes).
+uint32_t stream_collide_blocks(Store st, int ns, const StepArgs &a);
 
 // Per-step rounding seed: a splitmix64 finaliser of seed + golden-ratio increment x step,
 // folded to 32 bits (step = completed steps + 1).

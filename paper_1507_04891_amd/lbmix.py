@@ -31,7 +31,7 @@ EXPORTS = (
     "lbmix_set_electrostatics",
     "lbmix_set_poisson", "lbmix_set_poisson_method", "lbmix_set_poisson_warm_start", "lbmix_set_rounding",
     "lbmix_set_storage_range", "lbmix_set_arithmetic", "lbmix_set_state", "lbmix_autotune", "lbmix_set_step_graph", "lbmix_step", "lbmix_get_moments", "lbmix_get_moments_device",
-    "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals",
+    "lbmix_get_populations", "lbmix_get_potential", "lbmix_get_mass_totals", "lbmix_get_step_mass",
     "lbmix_get_zprofiles", "lbmix_get_stats", "lbmix_sync", "lbmix_device_copy", "lbmix_save", "lbmix_load",
     "lbmix_last_error", "lbmix_destroy",
     "lbmix_net_create", "lbmix_net_num_params", "lbmix_net_get_params", "lbmix_net_set_params",
@@ -100,6 +100,7 @@ def load_library():
         "lbmix_get_populations": ([vp, ctypes.c_int, dp], ctypes.c_int),
         "lbmix_get_potential": ([vp, dp], ctypes.c_int),
         "lbmix_get_mass_totals": ([vp, dp], ctypes.c_int),
+        "lbmix_get_step_mass": ([vp, dp], ctypes.c_int),
         "lbmix_get_zprofiles": ([vp, dp], ctypes.c_int),
         "lbmix_get_stats": ([vp, ctypes.POINTER(Stats)], ctypes.c_int),
         "lbmix_sync": ([vp], ctypes.c_int),
@@ -348,6 +349,23 @@ class Lattice:
         self._check(self._L.lbmix_get_mass_totals(self._h, _dp(out)))
         return out
 
+    def step_mass(self):
+        """Per-species mass of the state the last step read, from the step's own FP64 partials."""
+        out = np.empty(self.nspecies)
+        self._check(self._L.lbmix_get_step_mass(self._h, _dp(out)))
+        return out
+
+    def metrics(self):
+        """One record of the run's monitors: steps taken, the Poisson solver's work and last
+        residual, and (after the first step) the per-species mass of the state the last step
+        read, from the step's own partials (no extra pass over the populations)."""
+        st = self.stats()
+        rec = {"steps": st["steps"], "poisson_solves": st["poisson_solves"],
+               "poisson_sweeps": st["total_sweeps"], "last_residual": st["last_residual"]}
+        if st["steps"] > 0:
+            rec["mass"] = [float(m) for m in self.step_mass()]
+        return rec
+
     def zprofiles(self):
         out = np.empty((self.nspecies, 4, self.nz))
         self._check(self._L.lbmix_get_zprofiles(self._h, _dp(out)))
@@ -363,6 +381,32 @@ class Lattice:
 
     def load(self, path):
         self._check(self._L.lbmix_load(self._h, str(path).encode()))
+
+
+class MetricsLog:
+    """Appends Lattice.metrics() records, one JSON object per line, with the wall time and
+    species-site updates per second since the previous record."""
+
+    def __init__(self, path):
+        self._f = open(path, "a")
+        self._last = None
+
+    def write(self, lat, **extra):
+        import json
+        import time
+        rec = lat.metrics()
+        now = time.perf_counter()
+        if self._last is not None and rec["steps"] > self._last[1]:
+            sites = lat.nspecies * lat.stats()["fluid_nodes"]
+            rec["glups"] = (rec["steps"] - self._last[1]) * sites / (now - self._last[0]) / 1e9
+        self._last = (now, rec["steps"])
+        rec.update(extra)
+        self._f.write(json.dumps(rec) + "\n")
+        self._f.flush()
+        return rec
+
+    def close(self):
+        self._f.close()
 
 
 class Net:

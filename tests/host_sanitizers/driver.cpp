@@ -63,6 +63,8 @@ int main(int argc, char **argv) {
     std::vector<double> buf(8 * 6 * 10 * 19, 0.0);
     EXPECT(lbmix_get_moments(c, 0, buf.data(), nullptr) == LBMIX_ESTATE);
     EXPECT(lbmix_get_mass_totals(c, buf.data()) == LBMIX_ESTATE);
+    EXPECT(lbmix_get_step_mass(c, buf.data()) == LBMIX_ESTATE);
+    EXPECT(lbmix_get_step_mass(nullptr, buf.data()) == LBMIX_EINVAL);
     EXPECT(lbmix_save(c, scratch) == LBMIX_ESTATE);
     EXPECT(std::strlen(lbmix_last_error(c)) > 0);
     lbmix_stats st;
