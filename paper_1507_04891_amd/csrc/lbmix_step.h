@@ -77,10 +77,10 @@ dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx = 0, uint32_t by = 0);
 
 // The work-group shape launch_stream_collide uses: the set one (bx_set, by_set), or 0 x 0 for
-// step_grid's default, except where the register budget allows three waves per SIMD: one row
-// of up to 256 nodes for FP32 with stochastic rounding and at most two species, and 128
-// threads (128 nodes of a row, or 128 / nx whole rows of a narrow plane) for three species in
-// 16 bits.
+// step_grid's default, except: one row of up to 256 nodes for FP32 with stochastic rounding
+// and at most two species (three waves per SIMD) and for one or two 16-bit species (rows of at
+// least 64 nodes), and 128 threads (128 nodes of a row, or 128 / nx whole rows of a narrow
+// plane) for three species in 16 bits (three waves per SIMD).
 void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set, uint32_t by_set, uint32_t *bx,
                 uint32_t *by);
 hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool charged,

@@ -342,9 +342,11 @@ __device__ __forceinline__ S *slot(S *base, int arr, uint32_t plane, uint32_t in
 
 // The same for a byte offset already formed within the plane.  The empty asm makes the offset
 // a fresh 32-bit value where the access is, so the access keeps the scalar-base form (a
-// 64-bit scalar address plus the 32-bit lane offset) instead of a 64-bit vector address.
+// 64-bit scalar address plus the 32-bit lane offset) instead of a 64-bit vector address.  The
+// caller's variable itself is renewed (passed by reference), so the next access takes the new
+// value and no register copy of the old one is needed.
 template <int NS, class S>
-__device__ __forceinline__ S *slot_at(S *base, int arr, uint32_t plane, uint32_t byte_off, uint32_t N) {
+__device__ __forceinline__ S *slot_at(S *base, int arr, uint32_t plane, uint32_t &byte_off, uint32_t N) {
     S *start = base + ((size_t)arr * N + plane) * NS;
     asm volatile("" : "+v"(byte_off));
     using B = std::conditional_t<std::is_const_v<S>, const char, char>;
@@ -746,6 +748,10 @@ void stream_collide(const StepArgs a) {
                          : 0ull;
         uint32_t word = 0u, spare = 0u;
         bool have_spare = false;
+        // byte offsets of this node in a plane of the output (the second for the separate
+        // third-species array of the split 16-bit layout)
+        uint32_t soff = own_in * (uint32_t)((kSplit<S, NS> ? 2 : NS) * sizeof(S));
+        uint32_t soff1 = own_in * (uint32_t)sizeof(S);
         auto rbits = [&](int s) -> uint32_t {     // the conversions use the high bits
             if constexpr (!SR) return 0u;
             if ((s & 1) == 0) {
@@ -778,11 +784,10 @@ void stream_collide(const StepArgs a) {
             }
             if constexpr (kSplit<S, NS>) {
                 const S pair[2] = {o[0], o[1]};
-                VecIO<S, 2>::store(slot_at<2>(fout, p, pl.p0, own_in * (uint32_t)(2 * sizeof(S)), a.N), pair);
-                __builtin_nontemporal_store(o[2], slot_at<1>(fout + (size_t)2 * Q * a.N, p, pl.p0,
-                                                             own_in * (uint32_t)sizeof(S), a.N));
+                VecIO<S, 2>::store(slot_at<2>(fout, p, pl.p0, soff, a.N), pair);
+                __builtin_nontemporal_store(o[2], slot_at<1>(fout + (size_t)2 * Q * a.N, p, pl.p0, soff1, a.N));
             } else {
-                VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, own_in * (uint32_t)(NS * sizeof(S)), a.N), o);
+                VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, soff, a.N), o);
             }
         };
         {
