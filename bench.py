@@ -634,8 +634,8 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the other configurations (slits, channels, 512^3)")
     ap.add_argument("--no-copy-ceiling", action="store_true")
-    ap.add_argument("--config-steps", type=int, default=20, help="timed steps of each other configuration")
-    ap.add_argument("--config-warmup", type=int, default=5)
+    ap.add_argument("--config-steps", type=int, default=50, help="timed steps of each other configuration")
+    ap.add_argument("--config-warmup", type=int, default=10)
     ap.add_argument("--graph", action="store_true", help="replay steps as captured HIP graphs")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library pick the work-group shape of the step (default: its default shape)")

@@ -171,7 +171,7 @@ struct lbmix_ctx {
     std::vector<std::pair<uint32_t, uint32_t>> step_shapes() const {
         std::vector<std::pair<uint32_t, uint32_t>> v;
         if (nx >= 64) {
-            const uint32_t cap = std::min<uint32_t>(BLOCK, ((nx + 63) / 64) * 64);
+            const uint32_t cap = std::min<uint32_t>(STEP_BLOCK, ((nx + 63) / 64) * 64);
             for (uint32_t bx = 64; bx <= cap; bx *= 2)
                 for (uint32_t by = 1; bx * by <= (uint32_t)STEP_BLOCK; by *= 2)
                     if (by <= (uint32_t)ny || by == 1) v.push_back({bx, by});
