@@ -1987,7 +1987,7 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 5;
+    h.version = 6;   // 6: three 16-bit species split within each plane
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
     h.nch = c->nch;
     h.pair_ns = c->pair_ns;
@@ -2040,7 +2040,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 5;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 6;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
          h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
     constexpr int kPerChan = 4 + MAXS;

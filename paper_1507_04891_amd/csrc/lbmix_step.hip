@@ -28,9 +28,10 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
         const double cu = cx(p) * ux + cy(p) * uy + cz(p) * uz;
         const double dev = wgt<double>(p) * (dn + n * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
         int arr;
-        uint32_t node;
-        pl.template src<p>(arr, node);
-        f[elem_at<S>(s, arr, node, a.N, a.ns)] = CD::template encode<false>(typename CD::C(dev), a.scale[s][arr]);
+        uint32_t plane, inplane;
+        pl.template src<p>(arr, plane, inplane);
+        f[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)] =
+            CD::template encode<false>(typename CD::C(dev), a.scale[s][arr]);
     });
 }
 
@@ -60,9 +61,10 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
-        uint32_t node;
-        pl.template src<p>(arr, node);
-        const double dv = double(CD::decode(fin[elem_at<S>(s, arr, node, a.N, a.ns)], a.inv_scale[s][arr]));
+        uint32_t plane, inplane;
+        pl.template src<p>(arr, plane, inplane);
+        const double dv =
+            double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)], a.inv_scale[s][arr]));
         if constexpr (MODE == 1) {
             out0[(size_t)p * Nfull + fi] = dv + wgt<double>(p) * a.rho_bar[s];
         } else {
@@ -96,9 +98,9 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
         static_for<Q>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             int arr;
-            uint32_t node;
-            pl.template src<p>(arr, node);
-            m0 += double(CD::decode(fin[elem_at<S>(s, arr, node, a.N, a.ns)], a.inv_scale[s][arr]));
+            uint32_t plane, inplane;
+            pl.template src<p>(arr, plane, inplane);
+            m0 += double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)], a.inv_scale[s][arr]));
         });
         qq += a.valence[s] * m0;
     }

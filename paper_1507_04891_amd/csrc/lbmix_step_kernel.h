@@ -317,17 +317,22 @@ __device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int n
 }
 
 // Three species in 2-byte elements would make 6-byte records that no single access fits, so
-// that layout is split: species 0 and 1 interleaved as above with NS = 2 (one 4-byte access per
-// direction and node), species 2 in a region of its own after them (one 2-byte access).
+// that layout is split within each plane of a slot: the plane's block of 3 nx ny elements holds
+// species 0 and 1 interleaved as above with NS = 2 (one 4-byte access per direction and node),
+// then species 2 (one 2-byte access).  Both accesses of a direction share the block's address.
 template <class S, int NS>
 constexpr bool kSplit = sizeof(S) == 2 && NS == 3;
 
-// Element index of species s, slot arr, node, for ns species of element type S.
+// Element index of species s, slot arr, node plane + inplane (plane: the node offset of its
+// z-plane, nxy nodes per plane), for ns species of element type S.
 template <class S>
-__device__ __forceinline__ size_t elem_at(int s, int arr, uint32_t node, uint32_t N, int ns) {
-    if (sizeof(S) == 2 && ns == 3)
-        return s < 2 ? ((size_t)arr * N + node) * 2 + s : (size_t)2 * Q * N + (size_t)arr * N + node;
-    return ((size_t)arr * N + node) * ns + s;
+__device__ __forceinline__ size_t elem_at(int s, int arr, uint32_t plane, uint32_t inplane, uint32_t N, int ns,
+                                          uint32_t nxy) {
+    if (sizeof(S) == 2 && ns == 3) {
+        const size_t block = ((size_t)arr * N + plane) * 3;
+        return s < 2 ? block + 2 * (size_t)inplane + s : block + 2 * (size_t)nxy + inplane;
+    }
+    return ((size_t)arr * N + plane + inplane) * ns + s;
 }
 
 // The elements of direction slot arr at node plane + inplane in the fused step's layout: the
@@ -351,6 +356,19 @@ __device__ __forceinline__ S *slot_at(S *base, int arr, uint32_t plane, uint32_t
     asm volatile("" : "+v"(byte_off));
     using B = std::conditional_t<std::is_const_v<S>, const char, char>;
     return reinterpret_cast<S *>(reinterpret_cast<B *>(start) + byte_off);
+}
+
+// An element at a 32-bit byte offset from a uniform address (loads), and the same with the
+// offset renewed as in slot_at (stores).
+template <class S>
+__device__ __forceinline__ S *byte_at(S *start, uint32_t byte_off) {
+    using B = std::conditional_t<std::is_const_v<S>, const char, char>;
+    return reinterpret_cast<S *>(reinterpret_cast<B *>(start) + byte_off);
+}
+template <class S>
+__device__ __forceinline__ S *byte_at_fresh(S *start, uint32_t &byte_off) {
+    asm volatile("" : "+v"(byte_off));
+    return byte_at(start, byte_off);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -464,6 +482,7 @@ void stream_collide(const StepArgs a) {
     const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, z, a.nx, a.ny, a.nzf, walls);
     const uint32_t own = pl.own();
     const uint32_t own_in = pl.own_inplane();
+    const uint32_t nxy4 = a.nx * a.ny * 4u;   // bytes of a plane's pairs in the split 16-bit layout
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
     // FP64 carry of the density deviation (uniform; see step 2)
@@ -488,11 +507,12 @@ void stream_collide(const StepArgs a) {
         pl.template src<p>(arr, plane, inplane);
         S raw[NS];
         if constexpr (kSplit<S, NS>) {
+            const S *block = fin + ((size_t)arr * a.N + plane) * 3;
             S pair[2];
-            VecIO<S, 2>::load(slot<2>(fin, arr, plane, inplane, a.N), pair);
+            VecIO<S, 2>::load(byte_at(block, inplane * 4u), pair);
             raw[0] = pair[0];
             raw[1] = pair[1];
-            raw[2] = __builtin_nontemporal_load(slot<1>(fin + (size_t)2 * Q * a.N, arr, plane, inplane, a.N));
+            raw[2] = __builtin_nontemporal_load(byte_at(block, nxy4 + inplane * 2u));
         } else {
             VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
         }
@@ -751,7 +771,7 @@ void stream_collide(const StepArgs a) {
         // byte offsets of this node in a plane of the output (the second for the separate
         // third-species array of the split 16-bit layout)
         uint32_t soff = own_in * (uint32_t)((kSplit<S, NS> ? 2 : NS) * sizeof(S));
-        uint32_t soff1 = own_in * (uint32_t)sizeof(S);
+        uint32_t soff1 = nxy4 + own_in * (uint32_t)sizeof(S);
         auto rbits = [&](int s) -> uint32_t {     // the conversions use the high bits
             if constexpr (!SR) return 0u;
             if ((s & 1) == 0) {
@@ -784,8 +804,9 @@ void stream_collide(const StepArgs a) {
             }
             if constexpr (kSplit<S, NS>) {
                 const S pair[2] = {o[0], o[1]};
-                VecIO<S, 2>::store(slot_at<2>(fout, p, pl.p0, soff, a.N), pair);
-                __builtin_nontemporal_store(o[2], slot_at<1>(fout + (size_t)2 * Q * a.N, p, pl.p0, soff1, a.N));
+                S *block = fout + ((size_t)p * a.N + pl.p0) * 3;
+                VecIO<S, 2>::store(byte_at_fresh(block, soff), pair);
+                __builtin_nontemporal_store(o[2], byte_at_fresh(block, soff1));
             } else {
                 VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, soff, a.N), o);
             }
