@@ -117,6 +117,23 @@ dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block) {
     return dim3((nx + bx - 1) / bx, ny, nz);
 }
 
+// Width of a work-group's rows for a plane nx >= 64 nodes wide, at most cap (a multiple of
+// 64): 256 where it divides nx (measured best for 256^3 and 512^3), else the widest multiple
+// of 64 that leaves the fewest idle lanes at the end of a row (a row of 320 nodes in one
+// work-group of 320, not in 256 + 256 with 192 idle).
+static uint32_t row_width(uint32_t nx, uint32_t cap) {
+    if (cap >= 256 && nx % 256 == 0) return 256;
+    uint32_t best = 64, waste = ~0u;
+    for (uint32_t w = 64; w <= cap; w += 64) {
+        const uint32_t idle = (nx + w - 1) / w * w - nx;
+        if (idle <= waste) {
+            best = w;
+            waste = idle;
+        }
+    }
+    return best;
+}
+
 dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx, uint32_t by) {
     if (bx > 0 && by > 0 && bx * by <= (uint32_t)STEP_BLOCK) {
         *block = dim3(bx, by, 1);
@@ -126,10 +143,12 @@ dim3 step_grid(uint32_t nx, uint32_t ny, uint32_t nzf, dim3 *block, uint32_t bx,
         bx = nx;
         by = STEP_BLOCK / nx;
         if (by > ny) by = ny;
-    } else {
+    } else if (nx <= (uint32_t)BLOCK) {
         bx = ((nx + 63) / 64) * 64;
-        if (bx > BLOCK) bx = BLOCK;
         by = STEP_BLOCK / BLOCK;   // rows per work-group (two rows of 256 measured best)
+    } else {
+        bx = row_width(nx, STEP_BLOCK);
+        by = STEP_BLOCK / bx;
     }
     *block = dim3(bx, by, 1);
     return dim3((nx + bx - 1) / bx, (ny + by - 1) / by, nzf);
@@ -143,7 +162,7 @@ void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set,
     // FP32 with stochastic rounding (FP64 arithmetic, 135-143 VGPRs for one or two species): three
     // waves per SIMD need work-groups of one row (four waves, one per SIMD)
     if (st == Store::F32 && stochastic && ns <= 2 && nx >= 64) {
-        *bx = ((nx + 63) / 64) * 64 < (uint32_t)BLOCK ? ((nx + 63) / 64) * 64 : (uint32_t)BLOCK;
+        *bx = nx <= (uint32_t)BLOCK ? ((nx + 63) / 64) * 64 : row_width(nx, BLOCK);
         *by = 1;
     }
     // one or two 16-bit species (at most 128 VGPRs: four waves per SIMD): one row of up to 256
@@ -151,7 +170,7 @@ void step_shape(Store st, bool stochastic, int ns, uint32_t nx, uint32_t bx_set,
     // (whose mass partial the others wait for) holds fewer (measured: 512^3 f16s 3.86 -> 3.62
     // ms per step, 256^3 0.445 -> 0.441)
     if ((st == Store::F16 || st == Store::BF16) && ns <= 2 && nx >= 64) {
-        *bx = ((nx + 63) / 64) * 64 < (uint32_t)BLOCK ? ((nx + 63) / 64) * 64 : (uint32_t)BLOCK;
+        *bx = nx <= (uint32_t)BLOCK ? ((nx + 63) / 64) * 64 : row_width(nx, STEP_BLOCK);
         *by = 1;
     }
     // three 16-bit species (149 VGPRs: three waves per SIMD): 128-thread work-groups, six per
