@@ -858,3 +858,31 @@ def test_channel_stack_checkpoint_restart_is_bitwise(P):
     for s in range(3):
         np.testing.assert_array_equal(a.populations(s), b.populations(s))
     np.testing.assert_array_equal(a.potential(), b.potential())
+
+
+@pytest.mark.parametrize("nx", [320, 480])
+def test_wide_rows_default_launch(P, oracle_mod, nx):
+    """Planes wider than 256 nodes: rows of 320 nodes run as one 320-thread work-group, rows
+    of 480 as one of 512 with 32 idle lanes; the FP64-arithmetic FP32 form takes rows of 64
+    (320) or 256 (480), the 16-bit forms one row per work-group.  FP64 at the FP64 bar, the
+    FP64-arithmetic FP32 form at the FP32 bar, FP16 within 2 k units in the last place."""
+    w = WL.random_state(nx, 3, 4, 2, seed=17, dn=0.05, du=0.02)
+    k = 5
+    o = oracle_for(oracle_mod, w)
+    o.step(k)
+    lat = gpu_for(P, w, "f64")
+    lat.step(k)
+    compare_fp64(lat, o, w)
+    m = fluid(w)
+    sr = P.from_workload(w, storage="f32s", stochastic=True, seed=3)
+    sr.step(k)
+    for s in range(2):
+        assert rel_max(sr.moments(s)[0], o.moments(s)[0], m) <= 1e-5, s
+    h = P.from_workload(w, storage="f16s", seed=3)
+    h.step(k)
+    for s in range(2):
+        fo = o.populations(s)
+        dev = np.abs(fo - (WQ * w.rho0[s])[:, None, None, None]).max()
+        assert np.abs(h.populations(s) - fo).max() <= 2 * k * 2.0 ** -11 * dev, s
+    for lat_ in (lat, sr, h):
+        assert lat_.stats()["block_x"] in (64, 256, 320, 512)
