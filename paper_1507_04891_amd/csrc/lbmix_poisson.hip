@@ -223,10 +223,13 @@ __global__ __launch_bounds__(BLOCK) void mg_smooth(const MGLevel L, int colour) 
 // neighbours (the other colour) held fixed.  First the right-hand sides g = (lateral terms) - r
 // of the line equations (Ld + az n_z) e - az (e_up + e_down) = g, written over e (the line's
 // own values are not needed), then one thread per line and channel eliminates and substitutes.
+// (one thread per cell of the colour: rows of even length hold nx / 2 of them)
 __global__ __launch_bounds__(BLOCK) void mg_line_rhs(const MGLevel L, int colour) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= L.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t rowcells = (L.nx % 2 == 0) ? L.nx / 2 : L.nx;
+    if (t >= rowcells * L.ny * L.nz) return;
+    const uint32_t row = t / rowcells, y = row % L.ny, z = row / L.ny;
+    const uint32_t x = (L.nx % 2 == 0) ? 2 * (t % rowcells) + ((y + (uint32_t)colour) & 1u) : t % rowcells;
     if (((x + y) & 1u) != (uint32_t)colour) return;
     double s = 0.0;
     if (L.nx > 1) {
@@ -245,11 +248,16 @@ constexpr uint32_t LINE_CHUNK = 8;   // planes whose loads a line thread keeps i
 
 __global__ __launch_bounds__(BLOCK) void mg_line_solve(const MGLevel L, int colour, const double *idn,
                                                       const double *idn_last, const uint32_t *first, uint32_t nch) {
+    // thread u takes the u-th column of the colour (rows of even length hold nx / 2 of them)
     const uint32_t ncol = L.nx * L.ny;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t rowcols = (L.nx % 2 == 0) ? L.nx / 2 : L.nx;
+    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t c = blockIdx.y;
-    if (t >= ncol || c >= nch) return;
-    if (((t % L.nx + t / L.nx) & 1u) != (uint32_t)colour) return;
+    if (u >= rowcols * L.ny || c >= nch) return;
+    const uint32_t y = u / rowcols;
+    const uint32_t x = (L.nx % 2 == 0) ? 2 * (u % rowcols) + ((y + (uint32_t)colour) & 1u) : u % rowcols;
+    if (((x + y) & 1u) != (uint32_t)colour) return;
+    const uint32_t t = y * L.nx + x;
     const uint32_t W = first[c + 1] - first[c];   // >= 1
     double *e = L.e + (size_t)first[c] * ncol + t;   // plane k of the line: e[k * ncol]
     const double az = L.az;
@@ -291,10 +299,11 @@ __global__ __launch_bounds__(BLOCK) void mg_line_solve(const MGLevel L, int colo
 }
 
 // one thread per coarse cell: average of the fine residuals of its children
+// (one thread per cell over the whole level, so that narrow levels leave no lanes idle)
 __global__ __launch_bounds__(BLOCK) void mg_restrict(const MGLevel F, const MGLevel C) {
-    const uint32_t X = blockIdx.x * blockDim.x + threadIdx.x;
-    if (X >= C.nx) return;
-    const uint32_t Y = blockIdx.y, Z = blockIdx.z;
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C.nx * C.ny * C.nz) return;
+    const uint32_t X = c % C.nx, Y = (c / C.nx) % C.ny, Z = c / (C.nx * C.ny);
     double acc = 0.0;
     for (int k = 0; k < F.fz; ++k)
         for (int j = 0; j < F.fy; ++j)
@@ -323,9 +332,9 @@ __device__ inline void lin1(uint32_t f, int factor, uint32_t nc, bool periodic, 
 }
 
 __global__ __launch_bounds__(BLOCK) void mg_prolong(const MGLevel F, const MGLevel C) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= F.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F.nx * F.ny * F.nz) return;
+    const uint32_t x = f % F.nx, y = (f / F.nx) % F.ny, z = f / (F.nx * F.ny);
     uint32_t xa, xb, ya, yb, za, zb;
     double wx, wy, wz;
     lin1(x, F.fx, C.nx, true, xa, xb, wx);
@@ -1089,26 +1098,23 @@ hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream) {
     return hipGetLastError();
 }
 hipError_t launch_mg_restrict(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(C.nx, C.ny, C.nz, &b);
-    hipLaunchKernelGGL(mg_restrict, g, b, 0, stream, F, C);
+    const uint32_t n = C.nx * C.ny * C.nz;
+    hipLaunchKernelGGL(mg_restrict, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, F, C);
     return hipGetLastError();
 }
 hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(F.nx, F.ny, F.nz, &b);
-    hipLaunchKernelGGL(mg_prolong, g, b, 0, stream, F, C);
+    const uint32_t n = F.nx * F.ny * F.nz;
+    hipLaunchKernelGGL(mg_prolong, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, F, C);
     return hipGetLastError();
 }
 hipError_t launch_mg_line_rhs(const MGLevel &L, int colour, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(L.nx, L.ny, L.nz, &b);
-    hipLaunchKernelGGL(mg_line_rhs, g, b, 0, stream, L, colour);
+    const uint32_t n = ((L.nx % 2 == 0) ? L.nx / 2 : L.nx) * L.ny * L.nz;
+    hipLaunchKernelGGL(mg_line_rhs, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, L, colour);
     return hipGetLastError();
 }
 hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *idn_last,
                                 const uint32_t *first, uint32_t nch, hipStream_t stream) {
-    const uint32_t ncol = L.nx * L.ny;
+    const uint32_t ncol = ((L.nx % 2 == 0) ? L.nx / 2 : L.nx) * L.ny;   // columns of one colour
     hipLaunchKernelGGL(mg_line_solve, dim3((ncol + BLOCK - 1) / BLOCK, nch), dim3(BLOCK), 0, stream, L, colour, idn,
                        idn_last, first, nch);
     return hipGetLastError();
