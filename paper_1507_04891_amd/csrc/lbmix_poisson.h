@@ -89,11 +89,12 @@ hipError_t launch_mg_prolong(const MGLevel &F, const MGLevel &C, hipStream_t str
 // Line relaxation along z of a channel-stack level, colour (x + y) mod 2 of the columns:
 // launch_mg_line_rhs writes g = (lateral neighbour terms) - r into e of the cells of that
 // colour; launch_mg_line_solve then solves the tridiagonal z-system of every line of that colour
-// in every channel (planes [first[c], first[c + 1]), c < nch), with the inverse pivots idn[k]
-// of the planes k < W - 1 of a channel of W planes (one recurrence, shared by the channels)
-// and idn_last[c] of its last plane (0 pins the last plane of a singular line to 0).
+// in every channel (planes [first[c], first[c + 1]), c < nch) from both ends towards the
+// middle plane W / 2 of a channel of W planes, with the inverse pivots idn[j] of the j-th
+// step from either end (one recurrence, shared by the channels) and pmid[c] of the middle
+// plane (0 pins the middle plane of a singular line to 0).
 hipError_t launch_mg_line_rhs(const MGLevel &L, int colour, hipStream_t stream);
-hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *idn_last,
+hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *pmid,
                                 const uint32_t *first, uint32_t nch, hipStream_t stream);
 // The levels of `b`, solved by one work-group in LDS: V-cycle (2 pre-, 2 post-sweeps) whose
 // coarsest level gets b.coarse_sweeps red-black sweeps; e of b.lev[0] starts at 0 and is

@@ -246,55 +246,74 @@ __global__ __launch_bounds__(BLOCK) void mg_line_rhs(const MGLevel L, int colour
 
 constexpr uint32_t LINE_CHUNK = 8;   // planes whose loads a line thread keeps in flight together
 
+// Two threads per line, in the same work-group (threads h and h + LINE_HALF): the first
+// eliminates from the channel's first plane towards its middle plane mid = W / 2, the second
+// from its last plane (the rows are symmetric, so both take the pivots idn[j] of the j-th step
+// from their end); the first then solves the middle plane from both sides (pivot pmid[c]; 0
+// pins the middle plane of a singular line to 0), and both substitute back outwards.  Half
+// the serial steps of an elimination from one end.
+constexpr uint32_t LINE_HALF = BLOCK / 2;
+
 __global__ __launch_bounds__(BLOCK) void mg_line_solve(const MGLevel L, int colour, const double *idn,
-                                                      const double *idn_last, const uint32_t *first, uint32_t nch) {
-    // thread u takes the u-th column of the colour (rows of even length hold nx / 2 of them)
+                                                      const double *pmid, const uint32_t *first, uint32_t nch) {
+    // line u is the u-th column of the colour (rows of even length hold nx / 2 of them)
     const uint32_t ncol = L.nx * L.ny;
     const uint32_t rowcols = (L.nx % 2 == 0) ? L.nx / 2 : L.nx;
-    const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t c = blockIdx.y;
-    if (u >= rowcols * L.ny || c >= nch) return;
+    const bool bottom = threadIdx.x >= LINE_HALF;
+    const uint32_t u = blockIdx.x * LINE_HALF + threadIdx.x % LINE_HALF;
+    const uint32_t c = blockIdx.y;   // uniform: the whole work-group is in one channel
+    if (c >= nch) return;
     const uint32_t y = u / rowcols;
     const uint32_t x = (L.nx % 2 == 0) ? 2 * (u % rowcols) + ((y + (uint32_t)colour) & 1u) : u % rowcols;
-    if (((x + y) & 1u) != (uint32_t)colour) return;
-    const uint32_t t = y * L.nx + x;
-    const uint32_t W = first[c + 1] - first[c];   // >= 1
-    double *e = L.e + (size_t)first[c] * ncol + t;   // plane k of the line: e[k * ncol]
+    const bool act = u < rowcols * L.ny && ((x + y) & 1u) == (uint32_t)colour;
+    const uint32_t W = first[c + 1] - first[c];   // >= 1, uniform
+    const uint32_t mid = W / 2;
+    const uint32_t steps = bottom ? W - 1 - mid : mid;
+    double *e = L.e + (size_t)first[c] * ncol + (act ? y * L.nx + x : 0);
+    auto at = [&](uint32_t j) -> size_t { return (size_t)(bottom ? W - 1 - j : j) * ncol; };   // j-th step
     const double az = L.az;
-    // forward elimination: d_k = (g_k + az d_{k-1}) idn[k], then the last plane
-    double d = 0.0;
-    uint32_t k = 0;
-    for (; k + LINE_CHUNK < W; k += LINE_CHUNK) {
-        double g[LINE_CHUNK];
+    if (act) {   // elimination towards the middle: d_j = (g_j + az d_{j-1}) idn[j]
+        double d = 0.0;
+        uint32_t j = 0;
+        for (; j + LINE_CHUNK <= steps; j += LINE_CHUNK) {
+            double g[LINE_CHUNK];
 #pragma unroll
-        for (uint32_t j = 0; j < LINE_CHUNK; ++j) g[j] = e[(size_t)(k + j) * ncol];
+            for (uint32_t q = 0; q < LINE_CHUNK; ++q) g[q] = e[at(j + q)];
 #pragma unroll
-        for (uint32_t j = 0; j < LINE_CHUNK; ++j) {
-            d = (g[j] + az * d) * idn[k + j];
-            e[(size_t)(k + j) * ncol] = d;
+            for (uint32_t q = 0; q < LINE_CHUNK; ++q) {
+                d = (g[q] + az * d) * idn[j + q];
+                e[at(j + q)] = d;
+            }
+        }
+        for (; j < steps; ++j) {
+            d = (e[at(j)] + az * d) * idn[j];
+            e[at(j)] = d;
         }
     }
-    for (; k + 1 < W; ++k) {
-        d = (e[(size_t)k * ncol] + az * d) * idn[k];
-        e[(size_t)k * ncol] = d;
+    __syncthreads();
+    if (act && !bottom) {   // the middle plane from both neighbours
+        const double up = mid >= 1 ? e[(size_t)(mid - 1) * ncol] : 0.0;
+        const double down = mid + 1 < W ? e[(size_t)(mid + 1) * ncol] : 0.0;
+        e[(size_t)mid * ncol] = (e[(size_t)mid * ncol] + az * (up + down)) * pmid[c];
     }
-    d = (e[(size_t)(W - 1) * ncol] + az * d) * idn_last[c];
-    e[(size_t)(W - 1) * ncol] = d;
-    // back substitution: e_k = d_k + az idn[k] e_{k+1}
-    int kk = (int)W - 2;
-    for (; kk + 1 >= (int)LINE_CHUNK; kk -= (int)LINE_CHUNK) {
-        double v[LINE_CHUNK];
+    __syncthreads();
+    if (act) {   // back substitution outwards: x_j = d_j + az idn[j] x_{j+1}
+        double v = e[(size_t)mid * ncol];
+        int j = (int)steps - 1;
+        for (; j + 1 >= (int)LINE_CHUNK; j -= (int)LINE_CHUNK) {
+            double dv[LINE_CHUNK];
 #pragma unroll
-        for (uint32_t j = 0; j < LINE_CHUNK; ++j) v[j] = e[(size_t)(kk - (int)j) * ncol];
+            for (uint32_t q = 0; q < LINE_CHUNK; ++q) dv[q] = e[at((uint32_t)(j - (int)q))];
 #pragma unroll
-        for (uint32_t j = 0; j < LINE_CHUNK; ++j) {
-            d = v[j] + az * idn[kk - (int)j] * d;
-            e[(size_t)(kk - (int)j) * ncol] = d;
+            for (uint32_t q = 0; q < LINE_CHUNK; ++q) {
+                v = dv[q] + az * idn[j - (int)q] * v;
+                e[at((uint32_t)(j - (int)q))] = v;
+            }
         }
-    }
-    for (; kk >= 0; --kk) {
-        d = e[(size_t)kk * ncol] + az * idn[kk] * d;
-        e[(size_t)kk * ncol] = d;
+        for (; j >= 0; --j) {
+            v = e[at((uint32_t)j)] + az * idn[j] * v;
+            e[at((uint32_t)j)] = v;
+        }
     }
 }
 
@@ -1112,11 +1131,11 @@ hipError_t launch_mg_line_rhs(const MGLevel &L, int colour, hipStream_t stream) 
     hipLaunchKernelGGL(mg_line_rhs, dim3((n + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, stream, L, colour);
     return hipGetLastError();
 }
-hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *idn_last,
+hipError_t launch_mg_line_solve(const MGLevel &L, int colour, const double *idn, const double *pmid,
                                 const uint32_t *first, uint32_t nch, hipStream_t stream) {
     const uint32_t ncol = ((L.nx % 2 == 0) ? L.nx / 2 : L.nx) * L.ny;   // columns of one colour
-    hipLaunchKernelGGL(mg_line_solve, dim3((ncol + BLOCK - 1) / BLOCK, nch), dim3(BLOCK), 0, stream, L, colour, idn,
-                       idn_last, first, nch);
+    hipLaunchKernelGGL(mg_line_solve, dim3((ncol + LINE_HALF - 1) / LINE_HALF, nch), dim3(BLOCK), 0, stream, L, colour,
+                       idn, pmid, first, nch);
     return hipGetLastError();
 }
 hipError_t launch_mg_bottom(const MGBottom &b, hipStream_t stream) {

@@ -98,7 +98,7 @@ struct lbmix_ctx {
     // multigrid: level 0 is (psi, b); coarser levels own their arrays
     std::vector<MGLevel> mg;
     bool mg_lines = false;            // channel stack: lateral coarsening, z-line relaxation
-    std::vector<double *> mg_idn, mg_idn_last;   // per level: inverse pivots of the z lines
+    std::vector<double *> mg_idn, mg_pmid;   // per level: pivots of the z lines
     double *mg_b = nullptr;
     double *mg_cinv = nullptr;        // exact inverse of the coarsest level (<= 64 cells)
     hipStream_t cap_stream = nullptr;  // capture-only stream (graphs replay on `stream`)
@@ -439,16 +439,17 @@ int residual(lbmix_ctx *c, const PoissonArgs &pa) {
 // one), two on the coarser grid levels
 constexpr int kPre0 = 1, kPost0 = 1, kPre = 2, kPost = 2;
 
-// Inverse pivots of the z-line systems of a channel-stack level, (Ld + az n_z) e - az (e_up +
-// e_down) = g with Ld its lateral diagonal: one forward recurrence from the first plane of a
-// channel, shared by every channel before its last plane (idn[k], k < longest - 1), and the
-// last plane of each channel (idn_last[c]; 0 where the line is singular, which pins that plane).
 // One stream-collide launch; remembers how many work-groups wrote mass partials.
 hipError_t collide(lbmix_ctx *c, const StepArgs &a, bool field, bool charged, hipStream_t st) {
     c->part_nb = stream_collide_blocks(c->st, c->ns, a);
     return launch_stream_collide(c->st, c->ns, c->slit, field, charged, a, st);
 }
 
+// Pivots of the z-line systems of a channel-stack level, (Ld + az n_z) e - az (e_up + e_down)
+// = g with Ld its lateral diagonal, eliminated from both ends of a channel towards its middle
+// plane mid = W / 2: one recurrence from an end, shared by every channel and both ends (idn[k],
+// k < longest - 1), and the middle plane of each channel (pmid[c]; 0 where the line is
+// singular, which pins that plane).
 int mg_line_pivots(lbmix_ctx *c, const MGLevel &L) {
     const double Ld = (L.nx > 1 ? 2.0 * L.ax : 0.0) + (L.ny > 1 ? 2.0 * L.ay : 0.0), az = L.az;
     int longest = 1;
@@ -459,8 +460,10 @@ int mg_line_pivots(lbmix_ctx *c, const MGLevel &L) {
         idn[k] = 1.0 / denom[k];
     }
     for (int ch = 0; ch < c->nch; ++ch) {
-        const int W = c->ch_width[ch];
-        const double d = W == 1 ? Ld : (Ld + az) - az * az / denom[W - 2];
+        const int W = c->ch_width[ch], mid = W / 2;
+        double d = Ld;
+        if (mid >= 1) d += az - az * az * idn[mid - 1];
+        if (mid + 1 < W) d += az - az * az * idn[W - 2 - mid];
         last[ch] = d > 1e-12 * (Ld + 2.0 * az) ? 1.0 / d : 0.0;
     }
     double *di = nullptr, *dl = nullptr;
@@ -468,7 +471,7 @@ int mg_line_pivots(lbmix_ctx *c, const MGLevel &L) {
     if ((rc = c->hip(hipMalloc((void **)&di, idn.size() * sizeof(double)), "hipMalloc(mg)"))) return rc;
     c->mg_idn.push_back(di);
     if ((rc = c->hip(hipMalloc((void **)&dl, last.size() * sizeof(double)), "hipMalloc(mg)"))) return rc;
-    c->mg_idn_last.push_back(dl);
+    c->mg_pmid.push_back(dl);
     if ((rc = c->hip(hipMemcpy(di, idn.data(), idn.size() * sizeof(double), hipMemcpyHostToDevice), "copy pivots")))
         return rc;
     return c->hip(hipMemcpy(dl, last.data(), last.size() * sizeof(double), hipMemcpyHostToDevice), "copy pivots");
@@ -606,7 +609,7 @@ int mg_line_vcycle(lbmix_ctx *c, const PoissonArgs &pa, hipStream_t st) {
         for (int col = 0; col < 2; ++col) {
             int r = c->hip(launch_mg_line_rhs(c->mg[l], col, st), "mg_line_rhs");
             if (r) return r;
-            if ((r = c->hip(launch_mg_line_solve(c->mg[l], col, c->mg_idn[l], c->mg_idn_last[l], c->d_first,
+            if ((r = c->hip(launch_mg_line_solve(c->mg[l], col, c->mg_idn[l], c->mg_pmid[l], c->d_first,
                                                  (uint32_t)c->nch, st),
                             "mg_line_solve")))
                 return r;
@@ -971,7 +974,7 @@ int coarse_correction(lbmix_ctx *c) {
             for (int col = 0; col < 2; ++col) {
                 if (c->mg_lines) {
                     if ((rc = c->hip(launch_mg_line_rhs(B, col, c->stream), "mg_line_rhs")) ||
-                        (rc = c->hip(launch_mg_line_solve(B, col, c->mg_idn[nl - 1], c->mg_idn_last[nl - 1], c->d_first,
+                        (rc = c->hip(launch_mg_line_solve(B, col, c->mg_idn[nl - 1], c->mg_pmid[nl - 1], c->d_first,
                                                           (uint32_t)c->nch, c->stream),
                                      "mg_line_solve")))
                         return rc;
@@ -2135,7 +2138,7 @@ void lbmix_destroy(lbmix_ctx *c) {
                         (void *)c->d_psums})
             if (p) (void)hipFree(p);
         for (double *p : c->mg_idn) (void)hipFree(p);
-        for (double *p : c->mg_idn_last) (void)hipFree(p);
+        for (double *p : c->mg_pmid) (void)hipFree(p);
         for (size_t l = 1; l < c->mg.size(); ++l) {
             (void)hipFree(c->mg[l].e);
             (void)hipFree(c->mg[l].r);
