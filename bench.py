@@ -365,8 +365,8 @@ def bench_warmstart(args):
     (5 -> 16 -> 16 -> 16 -> 1, 3 x 3 x 3, BF16 operands with FP32 accumulation; inputs: the
     residual of the extrapolated guess, its coarse-grid solution, two potential increments and
     the wall mask) for --train-steps steps on exact corrections of the extrapolated guess, then
-    time multigrid to 1e-8 per step from the previous potential, the extrapolation and the
-    learned guess (the direct solve alongside).  Prints one JSON line."""
+    time multigrid and red-black SOR to 1e-8 per step from the previous potential, the
+    extrapolation and the learned guess (the direct solve alongside).  Prints one JSON line."""
     import torch
 
     import paper_1507_04891_amd as P
@@ -387,7 +387,9 @@ def bench_warmstart(args):
            "output_scale": net.output_scale(),
            "loss_first50": float(losses[3:53].mean()), "loss_last50": float(losses[-50:].mean())}
     for name, method, warm in [("direct", "direct", "previous"), ("previous", "multigrid", "previous"),
-                               ("extrapolated", "multigrid", "extrapolated"), ("learned", "multigrid", "learned")]:
+                               ("extrapolated", "multigrid", "extrapolated"), ("learned", "multigrid", "learned"),
+                               ("sor previous", "sor", "previous"), ("sor extrapolated", "sor", "extrapolated"),
+                               ("sor learned", "sor", "learned")]:
         lat = P.from_workload(w, storage=args.storage, stream=stream,
                               poisson=dict(method=method, rel_tol=1e-8, max_sweeps=100000))
         if warm == "learned":

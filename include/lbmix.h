@@ -159,10 +159,13 @@ int lbmix_set_schmidt(lbmix_ctx *ctx, double sc);
 int lbmix_set_step_graph(lbmix_ctx *ctx, int enable);
 
 /* Time `reps` launches of the fused stream-collide step for each candidate work-group shape
- * (64 to 512 threads: rows of 64, 128 or 256 nodes times 1 to 8 rows; for planes narrower
- * than 64 nodes, whole rows filling 64 to 512 threads) on the current state, twice, and keep
- * the fastest for the following steps if it beats the default shape by more than 1.5 %
- * (lbmix_stats reports the shape in use).  The state does not advance:
+ * (64 to 512 threads: rows of 64, 128, 256 or, in planes at least 512 nodes wide, 512 nodes
+ * times 1 to 8 rows; for planes narrower than 64 nodes, whole rows filling 64 to 512 threads)
+ * on the current state, twice, and keep the fastest for the following steps if it beats the
+ * default shape by more than 1.5 % (lbmix_stats reports the shape in use).  The default
+ * shape: rows of up to 256 nodes, two per work-group; one row for one or two 16-bit species
+ * and for FP32 with stochastic rounding; 128 threads for three 16-bit species; in planes
+ * wider than 256 nodes, rows of the width that leaves the fewest idle lanes.  The state does not advance:
  * the launches write the buffer the next step overwrites.  Results do not depend on the
  * shape.  Call after lbmix_set_state.  Errors: ESTATE without a state; EINVAL for reps < 1. */
 int lbmix_autotune(lbmix_ctx *ctx, int reps);
