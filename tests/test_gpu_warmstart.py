@@ -176,9 +176,9 @@ def test_learned_warm_start_gain_on_the_section4_slit(P):
     network (5 -> 16 -> 16 -> 16 -> 1, BF16 operands) is trained for 300 steps on the exact
     corrections of the extrapolated guess after 200 steps of developed flow; then multigrid
     to a relative residual of 1e-8 is run for 200 + 50 steps from each warm start and its
-    V-cycles per step over the last 50 are counted.  Measured on MI355X (600 training steps,
-    100 counted steps): previous potential 3.84, extrapolation 1.15, learned 5.81 cycles per
-    step.  The extrapolation beats the previous potential, and the learned correction, whose
+    V-cycles per step over the last 50 are counted.  Measured on MI355X by the warm-start
+    bench (600 training steps, 100 counted steps): previous potential 3.84, extrapolation
+    1.15, learned 5.8 to 6.1 cycles per step (two runs).  The extrapolation beats the previous potential, and the learned correction, whose
     error is above that of the extrapolation it corrects, makes multigrid work harder: the
     network gains nothing over the extrapolation, and multigrid still reaches the tolerance
     from its guess."""
