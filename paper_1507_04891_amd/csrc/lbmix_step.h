@@ -27,6 +27,47 @@ struct PlaneInfo {
     uint32_t zloc;        // index of the plane in its own channel's lattice (walls counted)
 };
 
+// Division by a fixed divisor d >= 1 as a multiply-high, an add and a shift (the round-up
+// method of Granlund and Montgomery): m = floor(2^32 (2^s - d) / d) + 1 with s = ceil(log2 d).
+// Exact for every n < 2^31.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+inline FastDiv fast_div(uint32_t d) {
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    return FastDiv{d, (uint32_t)((((1ull << 32) * ((1ull << s) - d)) / d) + 1), s};
+}
+__host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    const uint32_t t = (uint32_t)(((unsigned long long)n * f.m) >> 32);
+    return (t + n) >> f.s;
+}
+
+// Tile order of the charged step.  The hardware deals the work-groups of a launch to the eight
+// XCDs in turn (linear id b to XCD b mod 8), each XCD with its own L2, so in dispatch order the
+// rows y - 1, y and y + 1 of a plane sit in three L2s and each row of the potential, which the
+// gradient reads at the six neighbours of a node, is fetched three times.  When a plane has a
+// multiple of 8 work-groups, the XCD of a work-group is set by its index j within the plane, and
+// the j-th work-group takes tile (j mod 8) P/8 + j/8 of the P in the plane instead: each XCD
+// works on a band of consecutive rows of every plane, and the chip still works through the
+// planes in order.  Any order is correct; this one only changes which L2 serves which tile.
+struct TileOrder {
+    uint32_t band;        // 1: bands of rows per XCD; 0: dispatch order
+    uint32_t per_xcd;     // work-groups of a plane per XCD (P / 8)
+    FastDiv per_row;      // work-groups along x
+};
+__host__ __device__ inline void xcd_tile(uint32_t bx, uint32_t by, const TileOrder &t, uint32_t gx, uint32_t &tx,
+                                         uint32_t &ty) {
+    const uint32_t j = bx + gx * by;
+    const uint32_t tile = (j & 7u) * t.per_xcd + (j >> 3);
+    ty = fdiv(tile, t.per_row);
+    tx = tile - ty * gx;
+}
+inline TileOrder tile_order(uint32_t gx, uint32_t gy) {
+    const uint32_t p = gx * gy;
+    return TileOrder{p % 8 == 0 ? 1u : 0u, p / 8, fast_div(gx)};
+}
+
 // Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
 // over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
 // storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
@@ -68,6 +109,7 @@ struct StepArgs {
     const unsigned long long *step_dev;  // non-null (captured steps): seed from the step count
     unsigned long long round_seed;       // ... here, as the host derives it
     uint32_t block_x, block_y;       // launch shape of stream_collide (0: the default shape)
+    TileOrder tiles;                 // filled by launch_stream_collide (charged step)
 };
 
 dim3 node_grid(uint32_t nx, uint32_t ny, uint32_t nz, dim3 *block);

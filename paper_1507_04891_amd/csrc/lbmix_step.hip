@@ -202,13 +202,15 @@ hipError_t launch_stream_collide(Store st, int ns, bool slit, bool field, bool c
     uint32_t bx, by;
     step_shape(st, a.stochastic != 0, ns, a.nx, a.block_x, a.block_y, &bx, &by);
     const dim3 g = step_grid(a.nx, a.ny, a.nzf, &b, bx, by);
+    StepArgs t = a;
+    t.tiles = tile_order(g.x, g.y);
     switch (st) {
-        case Store::F64: return stream_collide_store<double>(ns, slit, field, charged, a, g, b, stream);
+        case Store::F64: return stream_collide_store<double>(ns, slit, field, charged, t, g, b, stream);
         case Store::F32:
-            return a.stochastic ? stream_collide_store<F32X>(ns, slit, field, charged, a, g, b, stream)
-                                : stream_collide_store<float>(ns, slit, field, charged, a, g, b, stream);
-        case Store::BF16: return stream_collide_store<BF16>(ns, slit, field, charged, a, g, b, stream);
-        case Store::F16: return stream_collide_store<F16>(ns, slit, field, charged, a, g, b, stream);
+            return t.stochastic ? stream_collide_store<F32X>(ns, slit, field, charged, t, g, b, stream)
+                                : stream_collide_store<float>(ns, slit, field, charged, t, g, b, stream);
+        case Store::BF16: return stream_collide_store<BF16>(ns, slit, field, charged, t, g, b, stream);
+        case Store::F16: return stream_collide_store<F16>(ns, slit, field, charged, t, g, b, stream);
     }
     return hipErrorInvalidValue;
 }

@@ -474,8 +474,13 @@ void stream_collide(const StepArgs a) {
     using C = typename CD::C;
     using S = typename CD::S;
     using H = std::conditional_t<CD::kHold, S, C>;   // how the loaded values are held
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t y = blockIdx.y * blockDim.y + threadIdx.y;   // uniform per wave if nx >= 64
+    // tile of this work-group: dispatch order, or for the charged step (which reads the potential
+    // around each node) bands of rows per XCD
+    uint32_t tx = blockIdx.x, ty = blockIdx.y;
+    if constexpr (CHARGED)
+        if (a.tiles.band) xcd_tile(blockIdx.x, blockIdx.y, a.tiles, gridDim.x, tx, ty);
+    const uint32_t x = tx * blockDim.x + threadIdx.x;
+    const uint32_t y = ty * blockDim.y + threadIdx.y;   // uniform per wave if nx >= 64
     const bool active = x < a.nx && y < a.ny;
     const uint32_t z = blockIdx.z;
     const uint32_t walls = SLIT ? a.planes[z].walls : 0u;   // uniform per work-group
