@@ -152,6 +152,28 @@ constexpr uint32_t TRI_LDS_MAX = 2048;
 // inverse of its condensed diagonal from pmid[s][mode] (0 for the singular mode).
 hipError_t launch_tridiag_lds(const double *b, const double *piv, const double *pmid, double *out, uint32_t nmodes,
                               const uint32_t *seg, uint32_t nseg, uint32_t longest, hipStream_t stream);
+// The same transforms by fast Fourier transforms, for sequences of a power-of-two length n
+// (FFT_MIN <= n <= FFT_MAX) along one axis: the coefficients in the real Fourier basis of
+// every sequence (forward), or the sequences from their coefficients (inverse).  Sequence s
+// of the batch (s < nseq) lies in plane s / 2^log2pp, at index j = s mod 2^log2pp, and its
+// element x at in[plane * s_plane + j * s_seq + x * s_el]; one of s_seq and s_el is 1 (cols:
+// s_seq == 1, the sequences of a plane side by side; else s_el == 1, each sequence
+// contiguous).  log2pp >= 1.  Forward with rhs: the sequences are those of
+// b = -K (q + lump_plane), read from q (lumps from planes, which may be null).  tw holds
+// exp(-2 pi i t / n) for t < n as (real, imaginary) pairs.  in and out must not overlap.
+constexpr uint32_t FFT_MIN = 8, FFT_MAX = 1024;
+struct FftPass {
+    const double *in;
+    double *out;
+    const double *tw;
+    uint32_t n, log2n, nseq, log2pp;
+    size_t s_plane;
+    uint32_t s_seq, s_el;
+    int rhs;
+    double rhs_K;
+    const PlaneInfo *planes;
+};
+hipError_t launch_fft_pass(const FftPass &f, bool cols, bool inverse, hipStream_t stream);
 // a <- -a / (mux[x] + muy[y] + muz[z]), 0 where the sum is 0.
 hipError_t launch_spectral_scale(double *a, const double *mux, const double *muy, const double *muz, uint32_t nx,
                                  uint32_t ny, uint32_t N, hipStream_t stream);

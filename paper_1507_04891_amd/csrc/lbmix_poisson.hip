@@ -1032,6 +1032,234 @@ __global__ __launch_bounds__(256) void spec_xy_half(const SpecXY a) {
     }
 }
 
+// ---- the transforms by fast Fourier transforms (power-of-two extents) ---------------------
+// Two real sequences a and b of length n are transformed together as z = a + i b.  With
+// Z[f] = sum_x z[x] exp(-2 pi i f x / n), their spectra are A[f] = (Z[f] + conj Z[n - f]) / 2
+// and B[f] = (Z[f] - conj Z[n - f]) / 2i, and a sequence's coefficients in the real Fourier
+// basis are A[0] / sqrt(n), sqrt(2/n) Re A[f] (cosine of frequency f, 0 < f < n/2),
+// -sqrt(2/n) Im A[f] (sine) and A[n/2] / sqrt(n) (the alternating vector).  The inverse
+// builds the Hermitian spectra A and B from the coefficients, W = A + i B, and takes
+// a + i b = conj(DFT(conj W)) / n.
+// The DFT runs as Stockham (self-sorting) passes of radix 8, and one of radix 2 or 4 when
+// log2 n is not a multiple of 3.  A pass of radix R after passes whose radices multiply to
+// p maps, for i < n/R and k = i mod p, the R values u_j = X[i + j n/R] exp(-2 pi i j k / (R p))
+// through an R-point DFT U to Y[(i - k) R + k + j p] = U_j; after the last pass Y is the DFT
+// in natural order.  A pass reads every value into registers before the work-group's barrier
+// and writes after it, so one LDS buffer serves as X and Y.  About 5 log2 n flops per value
+// against 2n for the product with the dense basis, and three LDS round trips for n = 128
+// where radix-2 stages take seven.  In LDS, value x of pair c sits at c (n + n/8 + 1) + x + x/8
+// (fft_at) and twiddle m at m + m/8: the strides of 8 values of the first pass and of n values
+// across pairs then fall on different banks.
+constexpr uint32_t FFT_BLOCK = 256;
+constexpr uint32_t FFT_SPAN = 1024;   // complex values of a work-group (2^10): FFT_SPAN / n pairs of sequences
+constexpr uint32_t FFT_LDS = FFT_SPAN + FFT_SPAN / 8 + FFT_SPAN / FFT_MIN;   // with the padding
+__device__ __forceinline__ uint32_t fft_at(uint32_t c, uint32_t x, uint32_t S) { return c * S + x + (x >> 3); }
+__device__ __forceinline__ uint32_t tw_at(uint32_t m) { return m + (m >> 3); }
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 w) {
+    return make_double2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+__device__ __forceinline__ double2 mul_mi(double2 a) { return make_double2(a.y, -a.x); }   // a (-i)
+
+// In-register DFTs (exponent sign -) of 2, 4 and 8 points.
+__device__ __forceinline__ void dft(double2 (&u)[2]) {
+    const double2 a = u[0];
+    u[0] = cadd(a, u[1]);
+    u[1] = csub(a, u[1]);
+}
+__device__ __forceinline__ void dft(double2 (&u)[4]) {
+    const double2 t0 = cadd(u[0], u[2]), t1 = csub(u[0], u[2]), t2 = cadd(u[1], u[3]), t3 = mul_mi(csub(u[1], u[3]));
+    u[0] = cadd(t0, t2);
+    u[2] = csub(t0, t2);
+    u[1] = cadd(t1, t3);
+    u[3] = csub(t1, t3);
+}
+__device__ __forceinline__ void dft(double2 (&u)[8]) {
+    double2 e[4] = {u[0], u[2], u[4], u[6]}, o[4] = {u[1], u[3], u[5], u[7]};
+    dft(e);
+    dft(o);
+    constexpr double h = 0.70710678118654752440;   // 1 / sqrt(2)
+    o[1] = make_double2((o[1].x + o[1].y) * h, (o[1].y - o[1].x) * h);    // exp(-i pi / 4)
+    o[2] = mul_mi(o[2]);                                                    // exp(-i pi / 2)
+    o[3] = make_double2((o[3].y - o[3].x) * h, -(o[3].x + o[3].y) * h);   // exp(-3 i pi / 4)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        u[k] = cadd(e[k], o[k]);
+        u[k + 4] = csub(e[k], o[k]);
+    }
+}
+
+// One radix-R pass over the FFT_SPAN / n sequences of length n = 2^L in B (pair stride S),
+// after passes whose radices multiply to p = 2^lp; tw[tw_at(m)] = exp(-2 pi i m / n), m < n.
+template <int R>
+__device__ __forceinline__ void fft_radix(double2 *B, const double2 *tw, uint32_t t, uint32_t L, uint32_t lp,
+                                          uint32_t S) {
+    constexpr uint32_t LR = R == 8 ? 3 : R == 4 ? 2 : 1;
+    constexpr uint32_t NBF = FFT_SPAN / R, PER = (NBF + FFT_BLOCK - 1) / FFT_BLOCK;
+    const uint32_t lm = L - LR, pm = (1u << lp) - 1;   // n / R = 2^lm butterflies per sequence
+    double2 u[PER][R];
+    uint32_t dst[PER];
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        const uint32_t e = t + q * FFT_BLOCK;
+        if (e >= NBF) continue;
+        const uint32_t c = e >> lm, i = e & ((1u << lm) - 1), k = i & pm;
+        u[q][0] = B[fft_at(c, i, S)];
+#pragma unroll
+        for (int j = 1; j < R; ++j) u[q][j] = cmul(B[fft_at(c, i + (j << lm), S)], tw[tw_at((j * k) << (lm - lp))]);
+        dft(u[q]);
+        dst[q] = (c << 16) | (((i - k) << LR) + k);   // pair, position of output 0
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        if (t + q * FFT_BLOCK >= NBF) continue;
+#pragma unroll
+        for (int j = 0; j < R; ++j) B[fft_at(dst[q] >> 16, (dst[q] & 0xffffu) + (j << lp), S)] = u[q][j];
+    }
+    __syncthreads();
+}
+
+template <bool COLS, bool INV>
+__global__ __launch_bounds__(FFT_BLOCK) void fft_pass(const FftPass f) {
+    // per thread: NE elements in and out, NC complex values of the pre and post steps; each
+    // step reads all of its values before the barrier and writes after it
+    constexpr uint32_t NE = 2 * FFT_SPAN / FFT_BLOCK, NC = FFT_SPAN / FFT_BLOCK;
+    __shared__ double2 buf[FFT_LDS];
+    extern __shared__ double2 tw[];   // n twiddles (padded)
+    const uint32_t t = threadIdx.x, n = f.n, L = f.log2n, half = n >> 1, S = n + (n >> 3) + 1;
+    const uint32_t nreal = 2 * (FFT_SPAN >> L);   // real sequences of this work-group (pairs of them)
+    const uint32_t s0 = blockIdx.x * nreal;
+    const uint32_t ppm = (1u << f.log2pp) - 1;
+    // element e of the work-group's block of nreal x n values: its sequence r and position x,
+    // consecutive e along the unit stride in memory
+    auto where = [&](uint32_t e, uint32_t &r, uint32_t &x) {
+        if (COLS) {   // nreal = 2^(11 - L)
+            r = e & (nreal - 1);
+            x = e >> (11 - L);
+        } else {
+            r = e >> L;
+            x = e & (n - 1);
+        }
+    };
+    auto addr = [&](uint32_t s, uint32_t x) -> size_t {
+        return (size_t)(s >> f.log2pp) * f.s_plane + (size_t)(s & ppm) * f.s_seq + (size_t)x * f.s_el;
+    };
+    auto slot = [&](uint32_t r, uint32_t x) -> double * {   // sequence r's part of pair r / 2
+        return reinterpret_cast<double *>(&buf[fft_at(r >> 1, x, S)]) + (r & 1);
+    };
+    {
+        // sequences past the batch read the last one (a valid address) and load 0
+        double v[NE], lump[NE];
+#pragma unroll
+        for (uint32_t u = 0; u < NE; ++u) {
+            uint32_t r, x;
+            where(t + u * FFT_BLOCK, r, x);
+            v[u] = f.in[addr(min(s0 + r, f.nseq - 1), x)];
+        }
+        if (f.rhs && f.planes) {
+#pragma unroll
+            for (uint32_t u = 0; u < NE; ++u) {
+                uint32_t r, x;
+                where(t + u * FFT_BLOCK, r, x);
+                lump[u] = f.planes[min(s0 + r, f.nseq - 1) >> f.log2pp].lump;
+            }
+        } else {
+#pragma unroll
+            for (uint32_t u = 0; u < NE; ++u) lump[u] = 0.0;
+        }
+        for (uint32_t i = t; i < n; i += FFT_BLOCK) tw[tw_at(i)] = make_double2(f.tw[2 * i], f.tw[2 * i + 1]);
+#pragma unroll
+        for (uint32_t u = 0; u < NE; ++u) {
+            uint32_t r, x;
+            where(t + u * FFT_BLOCK, r, x);
+            const double b = f.rhs ? -f.rhs_K * (v[u] + lump[u]) : v[u];
+            *slot(r, x) = s0 + r < f.nseq ? b : 0.0;
+        }
+    }
+    __syncthreads();
+    if (INV) {   // conj W from the coefficients of each pair
+        const double rn = sqrt((double)n), rh = sqrt(0.5 * (double)n);
+        double2 w[NC];
+#pragma unroll
+        for (uint32_t u = 0; u < NC; ++u) {
+            const uint32_t e = t + u * FFT_BLOCK, c = e >> L, fq = e & (n - 1);
+            double ar, ai = 0.0, br, bi = 0.0;   // A[fq], B[fq]
+            if (fq == 0) {
+                const double2 c0 = buf[fft_at(c, 0, S)];
+                ar = c0.x * rn;
+                br = c0.y * rn;
+            } else if (fq == half) {
+                const double2 cn = buf[fft_at(c, n - 1, S)];
+                ar = cn.x * rn;
+                br = cn.y * rn;
+            } else {   // A[g] = sqrt(n/2) (c[2g-1] - i c[2g]), A[n-g] = conj A[g]
+                const uint32_t g = fq < half ? fq : n - fq;
+                const double sg = fq < half ? -rh : rh;
+                const double2 cc = buf[fft_at(c, 2 * g - 1, S)], cs = buf[fft_at(c, 2 * g, S)];
+                ar = rh * cc.x;
+                ai = sg * cs.x;
+                br = rh * cc.y;
+                bi = sg * cs.y;
+            }
+            w[u] = make_double2(ar - bi, -(ai + br));   // conj(A + i B)
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t u = 0; u < NC; ++u) {
+            const uint32_t e = t + u * FFT_BLOCK;
+            buf[fft_at(e >> L, e & (n - 1), S)] = w[u];
+        }
+        __syncthreads();
+    }
+    uint32_t lp = 0;
+    for (; lp + 3 <= L; lp += 3) fft_radix<8>(buf, tw, t, L, lp, S);
+    if (L - lp == 2) fft_radix<4>(buf, tw, t, L, lp, S);
+    else if (L - lp == 1) fft_radix<2>(buf, tw, t, L, lp, S);
+    if (!INV) {   // the coefficients of each pair from Z
+        const double r1 = 1.0 / sqrt((double)n), r2 = sqrt(2.0 / (double)n);
+        double2 o[NC];
+#pragma unroll
+        for (uint32_t u = 0; u < NC; ++u) {
+            const uint32_t e = t + u * FFT_BLOCK, c = e >> L, k = e & (n - 1), fq = (k + 1) >> 1;
+            const double2 zf = buf[fft_at(c, fq, S)], zm = buf[fft_at(c, (n - fq) & (n - 1), S)];
+            const double are = 0.5 * (zf.x + zm.x), aim = 0.5 * (zf.y - zm.y);
+            const double bre = 0.5 * (zf.y + zm.y), bim = 0.5 * (zm.x - zf.x);
+            if (k == 0 || 2 * fq == n)
+                o[u] = make_double2(are * r1, bre * r1);
+            else if (k & 1)
+                o[u] = make_double2(are * r2, bre * r2);
+            else
+                o[u] = make_double2(-aim * r2, -bim * r2);
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t u = 0; u < NC; ++u) {
+            const uint32_t e = t + u * FFT_BLOCK;
+            buf[fft_at(e >> L, e & (n - 1), S)] = o[u];
+        }
+        __syncthreads();
+    }
+    const double inv_n = 1.0 / (double)n;
+    double o[NE];
+#pragma unroll
+    for (uint32_t u = 0; u < NE; ++u) {
+        uint32_t r, x;
+        where(t + u * FFT_BLOCK, r, x);
+        const double y = *slot(r, x);
+        o[u] = INV ? ((r & 1) ? -y * inv_n : y * inv_n) : y;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < NE; ++u) {
+        uint32_t r, x;
+        where(t + u * FFT_BLOCK, r, x);
+        const uint32_t s = s0 + r;
+        if (s < f.nseq) f.out[addr(s, x)] = o[u];
+    }
+}
+
 // a <- -a / (mu_x + mu_y + mu_z) in the transformed basis of a periodic box (0 for the
 // constant mode)
 __global__ __launch_bounds__(BLOCK) void spectral_scale(double *a, const double *mux, const double *muy,
@@ -1209,6 +1437,23 @@ hipError_t launch_spec_xy(const SpecXY &a, bool forward, hipStream_t stream) {
             hipLaunchKernelGGL((spec_xy<true, 64>), g, dim3(256), 0, stream, a);
         else
             hipLaunchKernelGGL((spec_xy<false, 64>), g, dim3(256), 0, stream, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_pass(const FftPass &f, bool cols, bool inverse, hipStream_t stream) {
+    if (f.n < FFT_MIN || f.n > FFT_MAX || (1u << f.log2n) != f.n || f.log2pp < 1 || f.log2pp > 31 || !f.tw)
+        return hipErrorInvalidValue;
+    if (cols ? f.s_seq != 1 : f.s_el != 1) return hipErrorInvalidValue;
+    const uint32_t nreal = 2 * (FFT_SPAN >> f.log2n);
+    const dim3 g((f.nseq + nreal - 1) / nreal);
+    const size_t lds = (size_t)(f.n + f.n / 8) * sizeof(double2);
+    if (cols) {
+        if (inverse) hipLaunchKernelGGL((fft_pass<true, true>), g, dim3(FFT_BLOCK), lds, stream, f);
+        else hipLaunchKernelGGL((fft_pass<true, false>), g, dim3(FFT_BLOCK), lds, stream, f);
+    } else {
+        if (inverse) hipLaunchKernelGGL((fft_pass<false, true>), g, dim3(FFT_BLOCK), lds, stream, f);
+        else hipLaunchKernelGGL((fft_pass<false, false>), g, dim3(FFT_BLOCK), lds, stream, f);
     }
     return hipGetLastError();
 }

@@ -114,6 +114,7 @@ struct lbmix_ctx {
     // pivots of the z systems (slit), segment bounds, two work arrays
     double *sp_tx = nullptr, *sp_ty = nullptr, *sp_tz = nullptr, *sp_mu = nullptr;
     double *sp_txp = nullptr, *sp_typ = nullptr;   // x and y bases zero-padded to 64 x 65 (planes up to 64)
+    double *sp_fx = nullptr, *sp_fy = nullptr, *sp_fz = nullptr;   // FFT twiddles along x, y, z (power-of-two extents)
     double *sp_piv = nullptr, *sp_piv_end = nullptr, *sp_pmid = nullptr, *sp_a = nullptr, *sp_b = nullptr;
     uint32_t *sp_seg = nullptr;
     float scale[MAXS][Q], inv_scale[MAXS][Q];
@@ -732,6 +733,24 @@ void periodic_basis(int n, std::vector<double> &T, std::vector<double> &mu) {
     }
 }
 
+// Extents the FFT passes take (powers of two), and their twiddles exp(-2 pi i t / n), t < n,
+// as (real, imaginary) pairs.
+bool fft_extent(int n) { return n >= (int)FFT_MIN && n <= (int)FFT_MAX && (n & (n - 1)) == 0; }
+std::vector<double> fft_twiddles(int n) {
+    std::vector<double> w(2 * (size_t)n);
+    for (int t = 0; t < n; ++t) {
+        const double ang = 2.0 * kPi * t / n;
+        w[2 * t] = std::cos(ang);
+        w[2 * t + 1] = -std::sin(ang);
+    }
+    return w;
+}
+int log2_exact(uint32_t n) {
+    int l = 0;
+    while ((1u << l) < n) ++l;
+    return l;
+}
+
 int upload(lbmix_ctx *c, double **dst, const std::vector<double> &v) {
     int rc = c->hip(hipMalloc((void **)dst, v.size() * sizeof(double)), "hipMalloc(direct solve)");
     if (rc) return rc;
@@ -745,6 +764,12 @@ int spec_build(lbmix_ctx *c) {
     periodic_basis(c->ny, ty, muy);
     int rc;
     if ((rc = upload(c, &c->sp_tx, tx)) || (rc = upload(c, &c->sp_ty, ty))) return rc;
+    // FFT passes replace the products along x and y for planes larger than 64 x 64 with both
+    // extents powers of two, and along z in a periodic box of more than 64 planes
+    if (fft_extent(c->nx) && fft_extent(c->ny) && !(c->nx <= 64 && c->ny <= 64))
+        if ((rc = upload(c, &c->sp_fx, fft_twiddles(c->nx))) || (rc = upload(c, &c->sp_fy, fft_twiddles(c->ny))))
+            return rc;
+    if (!c->slit && c->nzf > 64 && fft_extent(c->nzf) && (rc = upload(c, &c->sp_fz, fft_twiddles(c->nzf)))) return rc;
     if (c->nx <= (int)SPEC_PAD && c->ny <= (int)SPEC_PAD) {
         auto pad = [](const std::vector<double> &b, int n) {
             std::vector<double> p((size_t)SPEC_PAD * (SPEC_PAD + 1), 0.0);
@@ -838,9 +863,42 @@ int spec_left(lbmix_ctx *c, const double *T, uint32_t n, uint32_t inner, uint32_
     return c->hip(launch_gemm_f64(g, !inverse, true, c->stream), what);
 }
 
+// Transform along x (rows, from q when `from_q`) or y (columns of each plane) by the FFT pass.
+int fft_x(lbmix_ctx *c, const double *in, double *out, bool inverse, bool from_q = false) {
+    FftPass f{};
+    f.in = in; f.out = out; f.tw = c->sp_fx;
+    f.n = (uint32_t)c->nx; f.log2n = (uint32_t)log2_exact(f.n);
+    f.nseq = (uint32_t)c->ny * c->nzf; f.log2pp = (uint32_t)log2_exact((uint32_t)c->ny);
+    f.s_plane = (size_t)c->nx * c->ny; f.s_seq = (uint32_t)c->nx; f.s_el = 1;
+    if (from_q) {
+        f.rhs = 1;
+        f.rhs_K = 4.0 * kPi * c->lB;
+        f.planes = c->slit ? c->d_planes : nullptr;
+    }
+    return c->hip(launch_fft_pass(f, false, inverse, c->stream), "fft(x)");
+}
+int fft_y(lbmix_ctx *c, const double *in, double *out, bool inverse) {
+    FftPass f{};
+    f.in = in; f.out = out; f.tw = c->sp_fy;
+    f.n = (uint32_t)c->ny; f.log2n = (uint32_t)log2_exact(f.n);
+    f.nseq = (uint32_t)c->nx * c->nzf; f.log2pp = (uint32_t)log2_exact((uint32_t)c->nx);
+    f.s_plane = (size_t)c->nx * c->ny; f.s_seq = 1; f.s_el = (uint32_t)c->nx;
+    return c->hip(launch_fft_pass(f, true, inverse, c->stream), "fft(y)");
+}
+int fft_z(lbmix_ctx *c, const double *in, double *out, bool inverse) {   // periodic box
+    FftPass f{};
+    const uint32_t nxy = (uint32_t)c->nx * c->ny;
+    f.in = in; f.out = out; f.tw = c->sp_fz;
+    f.n = (uint32_t)c->nzf; f.log2n = (uint32_t)log2_exact(f.n);
+    f.nseq = nxy; f.log2pp = (uint32_t)log2_exact(nxy);
+    f.s_plane = 0; f.s_seq = 1; f.s_el = nxy;
+    return c->hip(launch_fft_pass(f, true, inverse, c->stream), "fft(z)");
+}
+
 // The direct solve.  Planes of at most 64 x 64 nodes are transformed per plane (in
-// registers up to 32 x 32, in LDS above), larger planes by the batched products; both read
-// q and form b = -K (q + lump) as they load it.  The projection onto zero channel mean acts
+// registers up to 32 x 32, in LDS above); larger planes by FFT passes along x and y when
+// both extents are powers of two, else by the batched products.  Each reads q and forms
+// b = -K (q + lump) as it loads it.  The projection onto zero channel mean acts
 // on the constant mode only and is applied there: by the z elimination of a slit or stack,
 // by the spectral scale of a periodic box.
 int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
@@ -856,6 +914,8 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
     if (in_lds) {
         xy.q = c->q; xy.in = nullptr; xy.out = a;
         if ((rc = c->hip(launch_spec_xy(xy, true, c->stream), "spec_xy"))) return rc;
+    } else if (c->sp_fx) {
+        if ((rc = fft_x(c, c->q, b, false, true)) || (rc = fft_y(c, b, a, false))) return rc;
     } else {
         // b = -K (q + lump) formed by the x product as it loads q; its projection onto zero
         // channel mean acts on the constant mode only, which the z solve projects
@@ -873,16 +933,22 @@ int spec_solve(lbmix_ctx *c, const PoissonArgs &pa) {
             rc = c->hip(launch_tridiag_z(a, c->sp_piv, c->sp_piv_end, b, nxy, c->sp_seg, c->nch, c->stream), "tridiag_z");
         if (rc) return rc;
     } else {
-        if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, a, b, false, "gemm(z)"))) return rc;
+        if ((rc = c->sp_fz ? fft_z(c, a, b, false) : spec_left(c, c->sp_tz, c->nzf, nxy, 1, a, b, false, "gemm(z)")))
+            return rc;
         if ((rc = c->hip(launch_spectral_scale(b, c->sp_mu, c->sp_mu + c->nx, c->sp_mu + c->nx + c->ny, c->nx,
                                                c->ny, c->Nf, c->stream), "spectral_scale")))
             return rc;
-        if ((rc = spec_left(c, c->sp_tz, c->nzf, nxy, 1, b, a, true, "gemm(z)"))) return rc;
+        if ((rc = c->sp_fz ? fft_z(c, b, a, true) : spec_left(c, c->sp_tz, c->nzf, nxy, 1, b, a, true, "gemm(z)")))
+            return rc;
         std::swap(a, b);
     }
     if (in_lds) {
         xy.q = nullptr; xy.in = b; xy.out = c->psi;
         return c->hip(launch_spec_xy(xy, false, c->stream), "spec_xy");
+    }
+    if (c->sp_fx) {
+        if ((rc = fft_y(c, b, a, true))) return rc;
+        return fft_x(c, a, c->psi, true);
     }
     if ((rc = spec_left(c, c->sp_ty, c->ny, c->nx, c->nzf, b, a, true, "gemm(y)"))) return rc;
     return spec_x(c, a, c->psi, true);
@@ -2130,7 +2196,7 @@ void lbmix_destroy(lbmix_ctx *c) {
                         (void *)c->ws_t, (void *)c->ws_mask})
             if (p) (void)hipFree(p);
         for (double *p : {c->sp_tx, c->sp_ty, c->sp_txp, c->sp_typ, c->sp_tz, c->sp_mu, c->sp_piv, c->sp_piv_end, c->sp_pmid,
-                          c->sp_a, c->sp_b})
+                          c->sp_a, c->sp_b, c->sp_fx, c->sp_fy, c->sp_fz})
             if (p) (void)hipFree(p);
         if (c->sp_seg) (void)hipFree(c->sp_seg);
         if (c->step_dev) (void)hipFree(c->step_dev);

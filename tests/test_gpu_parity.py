@@ -370,7 +370,12 @@ DIRECT_CASES = [("slit", (16, 8, 34)), ("periodic", (16, 8, 12)), ("slit", (7, 5
                 ("slit", (40, 36, 300)), ("periodic", (12, 10, 1100)), ("slit", (6, 4, 1100)),
                 ("slit", (2, 2, 2100)),
                 # planes between 32 and 64 wide, fewer than 256: split in halves
-                ("slit", (40, 36, 34)), ("periodic", (48, 33, 10))]
+                ("slit", (40, 36, 34)), ("periodic", (48, 33, 10)),
+                # power-of-two planes wider than 64: FFT passes along x and y (8 to 1024 points,
+                # work-groups that span planes, a partial last work-group), and along z in a box
+                # of more than 64 planes
+                ("slit", (128, 128, 10)), ("slit", (256, 8, 6)), ("periodic", (8, 1024, 3)),
+                ("periodic", (128, 8, 128)), ("slit", (16, 512, 5))]
 
 
 def charged_case(geometry, dims):
@@ -689,7 +694,8 @@ def test_full_size_ternary_slit_128x128x258_sixteen_bit(P, oracle_mod, storage):
         assert err > 0.0
 
 
-@pytest.mark.parametrize("case", ["binary_f32s", "slit_direct_f32s", "slit_batched_f32s", "channels_bf16s"])
+@pytest.mark.parametrize("case", ["binary_f32s", "slit_direct_f32s", "slit_batched_f32s", "slit_fft_f32s",
+                                  "channels_bf16s"])
 def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
     """Captured steps (fused step + direct solve + step count) replay exactly the uncaptured
     sequence, including the stochastic-rounding stream of the 16-bit forms."""
@@ -700,6 +706,9 @@ def test_step_graph_is_bitwise_the_uncaptured_step(P, case):
         storage, poisson = "f32s", dict(method="direct")
     elif case == "slit_batched_f32s":   # planes wider than 64: the batched products
         w = WL.charged_slit(nx=70, ny=66, nz=12, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
+        storage, poisson = "f32s", dict(method="direct")
+    elif case == "slit_fft_f32s":   # power-of-two planes wider than 64: the FFT passes
+        w = WL.charged_slit(nx=128, ny=16, nz=12, n_ion=2e-3, debye_length=3.0, sigma=-3e-4, Ex=1e-4, sc=10.0)
         storage, poisson = "f32s", dict(method="direct")
     else:
         w, storage, poisson = WL.channel_stack(**SMALL_STACK), "bf16s", dict(method="direct")
