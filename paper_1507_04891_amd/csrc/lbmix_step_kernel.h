@@ -158,13 +158,14 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+// (only the low half is kept, so the register starts as a live value: no clearing move)
 __device__ inline uint16_t f32_to_bf16_sr(float f, uint32_t rnd) {
-    bf16x2 t = {};
+    bf16x2 t = __builtin_bit_cast(bf16x2, f);
     t = __builtin_amdgcn_cvt_sr_bf16_f32(t, f, rnd, false);
     return __builtin_bit_cast(uint16_t, t[0]);
 }
 __device__ inline uint16_t f32_to_f16_sr(float f, uint32_t rnd) {
-    f16x2 t = {};
+    f16x2 t = __builtin_bit_cast(f16x2, f);
     t = __builtin_amdgcn_cvt_sr_f16_f32(t, f, rnd, false);
     return __builtin_bit_cast(uint16_t, t[0]);
 }
@@ -795,14 +796,15 @@ void stream_collide(const StepArgs a) {
         auto put_all = [&](auto pc, const C (&v)[NS]) {
             constexpr int p = decltype(pc)::value;
             S o[NS];
-            if constexpr (SR && CD::kPacked && NS % 2 == 0) {
+            if constexpr (SR && CD::kPacked && NS >= 2) {   // pairs into packed words, an odd last one alone
 #pragma unroll
-                for (int s = 0; s < NS; s += 2) {
+                for (int s = 0; s + 1 < NS; s += 2) {
                     const uint32_t r0 = rbits(s), r1 = rbits(s + 1);
                     const u16x2 pr = put_pair_sr<CD>(v[s], v[s + 1], r0, r1);
                     o[s] = pr[0];
                     o[s + 1] = pr[1];
                 }
+                if constexpr (NS % 2 == 1) o[NS - 1] = CD::template put<SR>(v[NS - 1], rbits(NS - 1));
             } else {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) o[s] = CD::template put<SR>(v[s], rbits(s));
