@@ -104,8 +104,9 @@ int lbmix_version(void);
  * No device memory is allocated until the first lbmix_set_state.  Defaults: tau_visc = 1,
  * Schmidt number 1 (tau_drag = tau_visc), no charge, Poisson tolerance 1e-8.
  * Errors: EINVAL for non-positive extents, nz < 3 for a slit, an unknown geometry or
- * storage, a lattice of more than 2^31 - 1 nodes, or a plane of 2^32 / (4 x element bytes)
- * nodes or more (nx * ny >= 134 M for F64, 268 M for FP32, 537 M for the 16-bit forms). */
+ * storage, a lattice of more than 2^31 - 1 nodes, or a plane of 2^32 / (19 x 4 x element
+ * bytes) nodes or more (nx * ny >= 7.06 M for F64, 14.1 M for FP32, 28.3 M for the 16-bit
+ * forms: the fused step addresses the 19 populations of a plane with 32-bit offsets). */
 int lbmix_create(lbmix_ctx **out, int nx, int ny, int nz, int geometry, int storage,
                  void *hip_stream);
 

@@ -208,7 +208,8 @@ struct lbmix_ctx {
         a.nx = nx;
         a.ny = ny;
         a.nzf = nzf;
-        a.N = Nf;
+        a.blog = pop_block_log2((uint32_t)ny);
+        a.N = (uint32_t)nx << a.blog;
         a.ns = ns;
         a.q_rest = 0.0;
         for (int s = 0; s < MAXS; ++s) {
@@ -1364,9 +1365,9 @@ int create_ctx(lbmix_ctx **out, int nx, int ny, int geometry, const std::vector<
         nzf += w;
     }
     if ((double)nx * ny * nz > 2147483647.0) return LBMIX_EINVAL;
-    // the fused step addresses a plane of a population slot with 32-bit byte offsets
+    // the fused step addresses the populations of a plane (all slots) with 32-bit byte offsets
     const double ebytes = storage == LBMIX_F64 ? 8.0 : (storage <= LBMIX_F32_SHIFTED ? 4.0 : 2.0);
-    if ((double)nx * ny * MAXS * ebytes >= 4294967296.0) return LBMIX_EINVAL;
+    if ((double)nx * ny * Q * MAXS * ebytes >= 4294967296.0) return LBMIX_EINVAL;
     lbmix_ctx *c = new (std::nothrow) lbmix_ctx();
     if (!c) return LBMIX_ENOMEM;
     c->nx = nx;
@@ -2056,7 +2057,7 @@ int lbmix_save(lbmix_ctx *c, const char *path) {
     Header h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, 8);
-    h.version = 6;   // 6: three 16-bit species split within each plane
+    h.version = 7;   // 7: populations in blocks of rows of all slots per plane
     h.nx = c->nx; h.ny = c->ny; h.nz = c->nz; h.geometry = c->geometry; h.storage = c->storage; h.ns = c->ns;
     h.nch = c->nch;
     h.pair_ns = c->pair_ns;
@@ -2109,7 +2110,7 @@ int lbmix_load(lbmix_ctx *c, const char *path) {
     FILE *fp = std::fopen(path, "rb");
     if (!fp) return c->fail(LBMIX_EINVAL, "cannot open %s", path);
     Header h;
-    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 6;
+    bool ok = std::fread(&h, sizeof h, 1, fp) == 1 && std::memcmp(h.magic, kMagic, 8) == 0 && h.version == 7;
     ok = ok && h.nx == c->nx && h.ny == c->ny && h.nz == c->nz && h.geometry == c->geometry &&
          h.storage == c->storage && h.ns == c->ns && h.nch == c->nch;
     constexpr int kPerChan = 4 + MAXS;

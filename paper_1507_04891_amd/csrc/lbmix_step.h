@@ -27,6 +27,14 @@ struct PlaneInfo {
     uint32_t zloc;        // index of the plane in its own channel's lattice (walls counted)
 };
 
+// Rows of a block of the population layout: 8, or the largest power of two below it that
+// divides ny.
+inline uint32_t pop_block_log2(uint32_t ny) {
+    uint32_t l = 3;
+    while (l > 0 && ny % (1u << l) != 0) --l;
+    return l;
+}
+
 // Division by a fixed divisor d >= 1 as a multiply-high, an add and a shift (the round-up
 // method of Granlund and Montgomery): m = floor(2^32 (2^s - d) / d) + 1 with s = ceil(log2 d).
 // Exact for every n < 2^31.
@@ -68,14 +76,17 @@ inline TileOrder tile_order(uint32_t gx, uint32_t gy) {
     return TileOrder{p % 8 == 0 ? 1u : 0u, p / 8, fast_div(gx)};
 }
 
-// Arguments of the fused stream-collide launch.  Populations are stored [p][node][species]
-// over the fluid nodes only (node = x + nx * (y + ny * zf), zf the fluid plane), in the
-// storage type; a stored value is (f_p - w_p rho_bar) * scale_p.
+// Arguments of the fused stream-collide launch.  Populations are stored over the fluid
+// planes only, [zf][y / B][p][y mod B][x][species] with B = 2^blog rows per block (the
+// 16-bit three-species form splits each block of a slot into pairs and singles), in the
+// storage type; a stored value is (f_p - w_p rho_bar) * scale_p.  The potential and the
+// charge density are indexed by node = x + nx * (y + ny * zf).
 struct StepArgs {
     const void *fin;
     void *fout;
     uint32_t nx, ny, nzf;
-    uint32_t N;                      // nx * ny * nzf
+    uint32_t N;                      // slot stride of the populations: B nx nodes
+    uint32_t blog;                   // log2 B, B the rows of a block (B divides ny)
     int ns;                          // species count (element stride of the layout)
     double rho_bar[MAXS];            // storage shift per species (0: plain f)
     float scale[MAXS][Q];            // 16-bit forms: power-of-two scale (1 otherwise)

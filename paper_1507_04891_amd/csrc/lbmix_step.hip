@@ -15,7 +15,7 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
-    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u);
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u, a.blog);
     const size_t Nfull = (size_t)a.nx * a.ny * a.nzfull;
     const size_t fi = ((size_t)(SLIT ? a.planes[pl.z].zfull : pl.z) * a.ny + pl.y) * a.nx + x;
     const double n = nf[fi];
@@ -28,9 +28,9 @@ __global__ __launch_bounds__(BLOCK) void init_equilibrium(const StepArgs a, int 
         const double cu = cx(p) * ux + cy(p) * uy + cz(p) * uz;
         const double dev = wgt<double>(p) * (dn + n * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
         int arr;
-        uint32_t plane, inplane;
-        pl.template src<p>(arr, plane, inplane);
-        f[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)] =
+        uint32_t plane, inplane, blk;
+        pl.template src<p>(arr, plane, inplane, blk);
+        f[elem_at<S>(s, arr, plane, inplane, blk, a.N, a.ns)] =
             CD::template encode<false>(typename CD::C(dev), a.scale[s][arr]);
     });
 }
@@ -55,16 +55,16 @@ __global__ __launch_bounds__(BLOCK) void gather(const StepArgs a, int s, double 
         }
         return;
     }
-    const Pull pl(x, blockIdx.y, (uint32_t)zf, a.nx, a.ny, a.nzf, SLIT ? a.planes[zf].walls : 0u);
+    const Pull pl(x, blockIdx.y, (uint32_t)zf, a.nx, a.ny, a.nzf, SLIT ? a.planes[zf].walls : 0u, a.blog);
     const S *fin = static_cast<const S *>(a.fin);
     double m0 = 0, mx = 0, my = 0, mz = 0;
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
-        uint32_t plane, inplane;
-        pl.template src<p>(arr, plane, inplane);
+        uint32_t plane, inplane, blk;
+        pl.template src<p>(arr, plane, inplane, blk);
         const double dv =
-            double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)], a.inv_scale[s][arr]));
+            double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, blk, a.N, a.ns)], a.inv_scale[s][arr]));
         if constexpr (MODE == 1) {
             out0[(size_t)p * Nfull + fi] = dv + wgt<double>(p) * a.rho_bar[s];
         } else {
@@ -90,7 +90,7 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
     using S = typename CD::S;
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= a.nx) return;
-    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u);
+    const Pull pl(x, blockIdx.y, blockIdx.z, a.nx, a.ny, a.nzf, SLIT ? a.planes[blockIdx.z].walls : 0u, a.blog);
     const S *fin = static_cast<const S *>(a.fin);
     double qq = a.q_rest;
     for (int s = 0; s < ns; ++s) {
@@ -98,9 +98,9 @@ __global__ __launch_bounds__(BLOCK) void charge(const StepArgs a, int ns, double
         static_for<Q>([&](auto pc) {
             constexpr int p = decltype(pc)::value;
             int arr;
-            uint32_t plane, inplane;
-            pl.template src<p>(arr, plane, inplane);
-            m0 += double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, a.N, a.ns, a.nx * a.ny)], a.inv_scale[s][arr]));
+            uint32_t plane, inplane, blk;
+            pl.template src<p>(arr, plane, inplane, blk);
+            m0 += double(CD::decode(fin[elem_at<S>(s, arr, plane, inplane, blk, a.N, a.ns)], a.inv_scale[s][arr]));
         });
         qq += a.valence[s] * m0;
     }
@@ -278,12 +278,13 @@ hipError_t launch_set_step(unsigned long long *step, unsigned long long value, h
     return hipGetLastError();
 }
 
-// Plain device copy, 16-byte non-temporal loads and stores: each work-group copies 4 x 256
-// contiguous elements, each thread four of them 256 apart, all four loads issued before the
-// stores (6.1-6.2 TB/s for 2 GiB on MI355X, against 5.0 for a grid-stride loop over 8192
-// work-groups).
+// Plain device copy, 16-byte non-temporal loads and stores: each work-group copies 256
+// contiguous elements, one per thread.  Measured on one MI355X for 2 GiB: 6.41 TB/s, against
+// 6.00 and 6.17 with two and four elements per thread (all loads issued before the stores),
+// 4.10 with eight, 5.39-5.52 for grid-stride loops and 5.64 with plain (temporal) accesses;
+// reading alone reached 6.93 TB/s and writing alone 6.04.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-constexpr uint32_t COPY_PER_THREAD = 4;
+constexpr uint32_t COPY_PER_THREAD = 1;
 __global__ __launch_bounds__(BLOCK) void copy16(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, size_t n) {
     const size_t base = (size_t)blockIdx.x * (BLOCK * COPY_PER_THREAD) + threadIdx.x;
     u32x4 v[COPY_PER_THREAD];

@@ -318,20 +318,22 @@ __device__ __forceinline__ size_t elem(int arr, uint32_t node, uint32_t N, int n
 }
 
 // Three species in 2-byte elements would make 6-byte records that no single access fits, so
-// that layout is split within each plane of a slot: the plane's block of 3 nx ny elements holds
-// species 0 and 1 interleaved as above with NS = 2 (one 4-byte access per direction and node),
-// then species 2 (one 2-byte access).  Both accesses of a direction share the block's address.
+// that layout is split within each block of a slot: the block's 3 N elements hold species 0
+// and 1 interleaved as above with NS = 2 (one 4-byte access per direction and node), then
+// species 2 (one 2-byte access).  Both accesses of a direction share the plane's address.
 template <class S, int NS>
 constexpr bool kSplit = sizeof(S) == 2 && NS == 3;
 
-// Element index of species s, slot arr, node plane + inplane (plane: the node offset of its
-// z-plane, nxy nodes per plane), for ns species of element type S.
+// Element index of species s in slot arr at the population offsets plane + inplane (Pull::src),
+// blk the block part of inplane, N the slot stride (nodes of a block of one slot), for ns
+// species of element type S.  In the split 16-bit layout a block of one slot holds 3 N
+// elements: the pairs of species 0 and 1 (2 N), then species 2 (N).
 template <class S>
-__device__ __forceinline__ size_t elem_at(int s, int arr, uint32_t plane, uint32_t inplane, uint32_t N, int ns,
-                                          uint32_t nxy) {
+__host__ __device__ __forceinline__ size_t elem_at(int s, int arr, uint32_t plane, uint32_t inplane, uint32_t blk, uint32_t N,
+                                          int ns) {
     if (sizeof(S) == 2 && ns == 3) {
-        const size_t block = ((size_t)arr * N + plane) * 3;
-        return s < 2 ? block + 2 * (size_t)inplane + s : block + 2 * (size_t)nxy + inplane;
+        const size_t base = ((size_t)arr * N + plane) * 3;
+        return s < 2 ? base + blk + 2 * (size_t)inplane + s : base + 2 * (size_t)blk + 2 * (size_t)N + inplane;
     }
     return ((size_t)arr * N + plane + inplane) * ns + s;
 }
@@ -376,50 +378,71 @@ __device__ __forceinline__ S *byte_at_fresh(S *start, uint32_t &byte_off) {
 // Pull addressing shared by every kernel that reads a pre-collision state: the value of
 // direction p at node (x, y, z) comes from slot (p, node - c_p), or from slot (opp(p),
 // node) when node - c_p is a wall (half-way bounce-back at rest).
-
+//
+// The populations of a fluid plane are stored together, in blocks of B = 2^blog rows (B
+// divides ny): block y / B of plane z holds the 19 slots one after another, each B rows of nx
+// nodes.  The value of slot p at (x, y, z) is at the node offset z 19 nx ny (the plane) +
+// p B nx (the slot) + (y / B) 19 B nx + (y mod B) nx + x (the row and the node), times the
+// species per element.  A work-group's 19 read and 19 write streams then lie within a few
+// hundred kilobytes of each other instead of 19 slot arrays apart, which the memory system
+// serves faster (the same loads and stores: 5.85 against 5.42 TB/s at 256^3, with blocks of
+// 8 rows against whole slot arrays).
 struct Pull {
     uint32_t xs, xm, xp;       // x, x-1, x+1 with periodic wrap (per lane)
-    uint32_t r0, rm, rp;       // node offsets y nx of the rows y, y-1, y+1 (wrapped)
-    uint32_t p0, pm, pp;       // node offsets z nx ny of the planes z, z-1, z+1 (wrapped; uniform)
+    uint32_t r0, rm, rp;       // node index parts y nx of the rows y, y-1, y+1 (wrapped)
+    uint32_t p0, pm, pp;       // node index parts z nx ny of the planes z, z-1, z+1 (wrapped; uniform)
+    uint32_t w0, wm, wp;       // population row offsets of the rows y, y-1, y+1
+    uint32_t k0, km, kp;       // ... their block parts (y / B) 19 B nx
+    uint32_t q0, qm, qp;       // population plane offsets of the planes z, z-1, z+1 (uniform)
     uint32_t y, z;
     bool bb_lo, bb_hi;         // z - 1 / z + 1 is a wall (slit)
 
-    __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx, uint32_t ny, uint32_t nzf,
-                    uint32_t walls)
+    __host__ __device__ Pull(uint32_t x, uint32_t y_, uint32_t z_, uint32_t nx, uint32_t ny, uint32_t nzf,
+                             uint32_t walls, uint32_t blog)
         : xs(x), y(y_), z(z_) {
         xm = (x == 0) ? nx - 1 : x - 1;
         xp = (x + 1 == nx) ? 0 : x + 1;
+        const uint32_t ym = (y == 0) ? ny - 1 : y - 1, yq = (y + 1 == ny) ? 0 : y + 1;
         r0 = y * nx;
-        rm = (y == 0) ? (ny - 1) * nx : r0 - nx;
-        rp = (y + 1 == ny) ? 0 : r0 + nx;
+        rm = ym * nx;
+        rp = yq * nx;
         const uint32_t plane = nx * ny;
         p0 = z * plane;
         pm = (z == 0) ? (nzf - 1) * plane : p0 - plane;
         pp = (z + 1 == nzf) ? 0 : p0 + plane;
+        const uint32_t bmask = (1u << blog) - 1, bnodes = ((uint32_t)Q << blog) * nx;
+        k0 = (y >> blog) * bnodes;
+        km = (ym >> blog) * bnodes;
+        kp = (yq >> blog) * bnodes;
+        w0 = k0 + (y & bmask) * nx;
+        wm = km + (ym & bmask) * nx;
+        wp = kp + (yq & bmask) * nx;
+        const uint32_t qplane = (uint32_t)Q * plane;
+        q0 = z * qplane;
+        qm = (z == 0) ? (nzf - 1) * qplane : q0 - qplane;
+        qp = (z + 1 == nzf) ? 0 : q0 + qplane;
         bb_lo = (walls & 1u) != 0;
         bb_hi = (walls & 2u) != 0;
     }
-    __device__ uint32_t own() const { return p0 + r0 + xs; }
-    __device__ uint32_t own_inplane() const { return r0 + xs; }
-    // slot direction, plane offset (uniform) and in-plane offset (per lane) of the value that
-    // direction p pulls
+    // node index (the potential, the charge, the rounding streams)
+    __host__ __device__ uint32_t own() const { return p0 + r0 + xs; }
+    // population offsets of this node's own values: in-plane offset and its block part
+    __host__ __device__ uint32_t own_inplane() const { return w0 + xs; }
+    __host__ __device__ uint32_t own_blk() const { return k0; }
+    // slot direction, population plane offset (uniform), in-plane offset (per lane) and its
+    // block part of the value that direction p pulls
     template <int p>
-    __device__ void src(int &arr, uint32_t &plane, uint32_t &inplane) const {
+    __host__ __device__ void src(int &arr, uint32_t &plane, uint32_t &inplane, uint32_t &blk) const {
         constexpr int X = cx(p), Y = cy(p), Z = cz(p);
         const bool bb = (Z == 1 && bb_lo) || (Z == -1 && bb_hi);
         const uint32_t sx = X == 1 ? xm : (X == -1 ? xp : xs);
-        const uint32_t sy = Y == 1 ? rm : (Y == -1 ? rp : r0);
-        const uint32_t sz = Z == 1 ? pm : (Z == -1 ? pp : p0);
+        const uint32_t sy = Y == 1 ? wm : (Y == -1 ? wp : w0);
+        const uint32_t sk = Y == 1 ? km : (Y == -1 ? kp : k0);
+        const uint32_t sz = Z == 1 ? qm : (Z == -1 ? qp : q0);
         arr = bb ? opp(p) : p;
-        plane = bb ? p0 : sz;
-        inplane = bb ? r0 + xs : sy + sx;
-    }
-    // ... and as one node index
-    template <int p>
-    __device__ void src(int &arr, uint32_t &node) const {
-        uint32_t plane, inplane;
-        src<p>(arr, plane, inplane);
-        node = plane + inplane;
+        plane = bb ? q0 : sz;
+        inplane = bb ? w0 + xs : sy + sx;
+        blk = bb ? k0 : sk;
     }
 };
 
@@ -485,10 +508,10 @@ void stream_collide(const StepArgs a) {
     const bool active = x < a.nx && y < a.ny;
     const uint32_t z = blockIdx.z;
     const uint32_t walls = SLIT ? a.planes[z].walls : 0u;   // uniform per work-group
-    const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, z, a.nx, a.ny, a.nzf, walls);
+    const Pull pl(x < a.nx ? x : 0, y < a.ny ? y : 0, z, a.nx, a.ny, a.nzf, walls, a.blog);
     const uint32_t own = pl.own();
     const uint32_t own_in = pl.own_inplane();
-    const uint32_t nxy4 = a.nx * a.ny * 4u;   // bytes of a plane's pairs in the split 16-bit layout
+    const uint32_t n4 = a.N * 4u;   // bytes of a block's pairs in the split 16-bit layout
     const S *fin = static_cast<const S *>(a.fin);
     S *fout = static_cast<S *>(a.fout);
     // FP64 carry of the density deviation (uniform; see step 2)
@@ -509,16 +532,16 @@ void stream_collide(const StepArgs a) {
     static_for<Q>([&](auto pc) {
         constexpr int p = decltype(pc)::value;
         int arr;
-        uint32_t plane, inplane;
-        pl.template src<p>(arr, plane, inplane);
+        uint32_t plane, inplane, blk;
+        pl.template src<p>(arr, plane, inplane, blk);
         S raw[NS];
         if constexpr (kSplit<S, NS>) {
             const S *block = fin + ((size_t)arr * a.N + plane) * 3;
             S pair[2];
-            VecIO<S, 2>::load(byte_at(block, inplane * 4u), pair);
+            VecIO<S, 2>::load(byte_at(block, inplane * 4u + blk * 2u), pair);
             raw[0] = pair[0];
             raw[1] = pair[1];
-            raw[2] = __builtin_nontemporal_load(byte_at(block, nxy4 + inplane * 2u));
+            raw[2] = __builtin_nontemporal_load(byte_at(block, n4 + inplane * 2u + blk * 4u));
         } else {
             VecIO<S, NS>::load(slot<NS>(fin, arr, plane, inplane, a.N), raw);
         }
@@ -776,8 +799,8 @@ void stream_collide(const StepArgs a) {
         bool have_spare = false;
         // byte offsets of this node in a plane of the output (the second for the separate
         // third-species array of the split 16-bit layout)
-        uint32_t soff = own_in * (uint32_t)((kSplit<S, NS> ? 2 : NS) * sizeof(S));
-        uint32_t soff1 = nxy4 + own_in * (uint32_t)sizeof(S);
+        uint32_t soff = own_in * (uint32_t)((kSplit<S, NS> ? 2 : NS) * sizeof(S)) + (kSplit<S, NS> ? pl.own_blk() * 2u : 0u);
+        uint32_t soff1 = n4 + own_in * (uint32_t)sizeof(S) + pl.own_blk() * 4u;
         auto rbits = [&](int s) -> uint32_t {     // the conversions use the high bits
             if constexpr (!SR) return 0u;
             if ((s & 1) == 0) {
@@ -811,11 +834,11 @@ void stream_collide(const StepArgs a) {
             }
             if constexpr (kSplit<S, NS>) {
                 const S pair[2] = {o[0], o[1]};
-                S *block = fout + ((size_t)p * a.N + pl.p0) * 3;
+                S *block = fout + ((size_t)p * a.N + pl.q0) * 3;
                 VecIO<S, 2>::store(byte_at_fresh(block, soff), pair);
                 __builtin_nontemporal_store(o[2], byte_at_fresh(block, soff1));
             } else {
-                VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.p0, soff, a.N), o);
+                VecIO<S, NS>::store(slot_at<NS>(fout, p, pl.q0, soff, a.N), o);
             }
         };
         {

@@ -1,0 +1,82 @@
+// Host check of the population layout of the fused step: the element that the step stores for
+// every (node, slot, species) is a bijection onto the allocation, and the element that
+// direction p pulls at a node is the one stored for the upstream node (or, next to a wall,
+// the node's own value of the opposite slot).
+#include "lbmix_step_kernel.h"
+
+#include <cstdio>
+#include <type_traits>
+#include <vector>
+
+using namespace lbmix;
+
+template <int P, class F>
+static void for_p(F &&f) {
+    if constexpr (P > 0) {
+        for_p<P - 1>(f);
+        f(std::integral_constant<int, P - 1>{});
+    }
+}
+
+template <class S>
+static int check(uint32_t nx, uint32_t ny, uint32_t nzf, int ns, bool slit) {
+    const uint32_t blog = pop_block_log2(ny), N = nx << blog;
+    const size_t total = (size_t)Q * nx * ny * nzf * ns;
+    std::vector<unsigned char> seen(total, 0);
+    auto walls = [&](uint32_t z) -> uint32_t {
+        if (!slit) return 0u;
+        return (z == 0 ? 1u : 0u) | (z + 1 == nzf ? 2u : 0u);
+    };
+    auto stored = [&](uint32_t x, uint32_t y, uint32_t z, int arr, int s) -> size_t {
+        const Pull pl(x, y, z, nx, ny, nzf, walls(z), blog);
+        return elem_at<S>(s, arr, pl.q0, pl.own_inplane(), pl.own_blk(), N, ns);
+    };
+    int bad = 0;
+    for (uint32_t z = 0; z < nzf; ++z)
+        for (uint32_t y = 0; y < ny; ++y)
+            for (uint32_t x = 0; x < nx; ++x)
+                for (int p = 0; p < Q; ++p)
+                    for (int s = 0; s < ns; ++s) {
+                        const size_t e = stored(x, y, z, p, s);
+                        if (e >= total || seen[e]++) ++bad;
+                    }
+    for (size_t e = 0; e < total; ++e)
+        if (seen[e] != 1) ++bad;
+    for (uint32_t z = 0; z < nzf; ++z)
+        for (uint32_t y = 0; y < ny; ++y)
+            for (uint32_t x = 0; x < nx; ++x) {
+                const Pull pl(x, y, z, nx, ny, nzf, walls(z), blog);
+                for_p<Q>([&](auto pc) {
+                    constexpr int p = decltype(pc)::value;
+                    int arr;
+                    uint32_t plane, inplane, blk;
+                    pl.template src<p>(arr, plane, inplane, blk);
+                    const bool bb = (cz(p) == 1 && z == 0 && slit) || (cz(p) == -1 && z + 1 == nzf && slit);
+                    const uint32_t sx = (x + nx - cx(p)) % nx, sy = (y + ny - cy(p)) % ny, sz = (z + nzf - cz(p)) % nzf;
+                    for (int s = 0; s < ns; ++s) {
+                        const size_t got = elem_at<S>(s, arr, plane, inplane, blk, N, ns);
+                        const size_t want = bb ? stored(x, y, z, opp(p), s) : stored(sx, sy, sz, p, s);
+                        if (got != want) ++bad;
+                    }
+                });
+            }
+    if (bad) std::printf("FAIL %u x %u x %u, %d species of %zu bytes, slit %d: %d\n", nx, ny, nzf, ns, sizeof(S), slit, bad);
+    return bad;
+}
+
+int main() {
+    const uint32_t shapes[][3] = {{256, 8, 3}, {5, 7, 4}, {16, 12, 5}, {64, 2, 3}, {3, 24, 2}, {8, 6, 6},
+                                  {1, 1, 3}, {40, 36, 3}, {7, 16, 4}};
+    int bad = 0;
+    for (auto &sh : shapes)
+        for (int ns = 1; ns <= 4; ++ns)
+            for (bool slit : {false, true}) {
+                if (slit && sh[2] < 2) continue;
+                bad += check<double>(sh[0], sh[1], sh[2], ns, slit);
+                bad += check<float>(sh[0], sh[1], sh[2], ns, slit);
+                bad += check<uint16_t>(sh[0], sh[1], sh[2], ns, slit);
+            }
+    if (bad) return 1;
+    std::printf("layout checks passed\n");
+    return 0;
+}

@@ -1,0 +1,27 @@
+"""The population layout of the fused step on the host (tests/host_layout/check.cpp): for
+planes of every block height (1, 2, 4, 8 rows), one to four species and 2-, 4- and 8-byte
+elements, periodic and slit, the element stored for each (node, slot, species) is a bijection
+onto the allocation, and each pulled element is the one stored for the upstream node (or the
+node's own opposite slot next to a wall).  No GPU is needed."""
+import os
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+def test_population_layout_is_a_bijection_and_pulls_the_upstream_value():
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    with tempfile.TemporaryDirectory() as d:
+        exe = os.path.join(d, "check")
+        subprocess.run([HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "paper_1507_04891_amd", "csrc"),
+                        "-I", os.path.join(ROOT, "include"), "-o", exe,
+                        os.path.join(ROOT, "tests", "host_layout", "check.cpp")],
+                       check=True, capture_output=True, timeout=300)
+        r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+        assert r.returncode == 0, r.stdout[-2000:]
+        assert "layout checks passed" in r.stdout
