@@ -37,8 +37,13 @@ def test_version_and_create_validation(L):
     assert L.lbmix_create(ctypes.byref(h), 4, 4, 4, 2, 0, None) == -1     # geometry
     assert L.lbmix_create(ctypes.byref(h), 4, 4, 4, 0, 9, None) == -1     # storage
     assert L.lbmix_create(ctypes.byref(h), 2048, 2048, 1024, 0, 0, None) == -1   # > 2^31 nodes
-    assert L.lbmix_create(ctypes.byref(h), 16384, 8192, 1, 0, 0, None) == -1     # F64 plane >= 4 GiB / 4 species
-    assert L.lbmix_create(ctypes.byref(h), 16384, 8192, 1, 0, 4, None) == 0      # the same plane in FP16
+    # the 19 populations of a plane for 4 species must stay under 4 GiB: 7.06 M nodes in F64,
+    # 28.3 M in the 16-bit forms
+    assert L.lbmix_create(ctypes.byref(h), 4096, 2048, 1, 0, 0, None) == -1      # 8.4 M nodes, F64
+    assert L.lbmix_create(ctypes.byref(h), 4096, 2048, 1, 0, 4, None) == 0       # the same plane in FP16
+    L.lbmix_destroy(h)
+    assert L.lbmix_create(ctypes.byref(h), 4096, 8192, 1, 0, 4, None) == -1      # 33.6 M nodes, FP16
+    assert L.lbmix_create(ctypes.byref(h), 2048, 2048, 1, 0, 0, None) == 0       # 4.2 M nodes, F64
     L.lbmix_destroy(h)
     assert L.lbmix_create(ctypes.byref(h), 4, 4, 4, 0, 1, None) == 0
     L.lbmix_destroy(h)
