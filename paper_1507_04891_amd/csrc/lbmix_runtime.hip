@@ -208,7 +208,7 @@ struct lbmix_ctx {
         a.nx = nx;
         a.ny = ny;
         a.nzf = nzf;
-        a.blog = pop_block_log2((uint32_t)ny);
+        a.blog = pop_block_log2((uint32_t)nx, (uint32_t)ny, (uint32_t)ns, (uint32_t)esize);
         a.N = (uint32_t)nx << a.blog;
         a.ns = ns;
         a.q_rest = 0.0;

@@ -19,8 +19,8 @@ static void for_p(F &&f) {
 }
 
 template <class S>
-static int check(uint32_t nx, uint32_t ny, uint32_t nzf, int ns, bool slit) {
-    const uint32_t blog = pop_block_log2(ny), N = nx << blog;
+static int check(uint32_t nx, uint32_t ny, uint32_t nzf, int ns, bool slit, uint32_t blog) {
+    const uint32_t N = nx << blog;
     const size_t total = (size_t)Q * nx * ny * nzf * ns;
     std::vector<unsigned char> seen(total, 0);
     auto walls = [&](uint32_t z) -> uint32_t {
@@ -60,22 +60,36 @@ static int check(uint32_t nx, uint32_t ny, uint32_t nzf, int ns, bool slit) {
                     }
                 });
             }
-    if (bad) std::printf("FAIL %u x %u x %u, %d species of %zu bytes, slit %d: %d\n", nx, ny, nzf, ns, sizeof(S), slit, bad);
+    if (bad)
+        std::printf("FAIL %u x %u x %u, %d species of %zu bytes, slit %d, blocks of %u rows: %d\n", nx, ny, nzf, ns,
+                    sizeof(S), slit, 1u << blog, bad);
     return bad;
 }
 
 int main() {
     const uint32_t shapes[][3] = {{256, 8, 3}, {5, 7, 4}, {16, 12, 5}, {64, 2, 3}, {3, 24, 2}, {8, 6, 6},
-                                  {1, 1, 3}, {40, 36, 3}, {7, 16, 4}};
+                                  {1, 1, 3}, {40, 36, 3}, {7, 16, 4}, {4, 64, 3}, {2, 128, 2}};
     int bad = 0;
+    // every block height that divides ny (1 to 64 rows)
     for (auto &sh : shapes)
-        for (int ns = 1; ns <= 4; ++ns)
-            for (bool slit : {false, true}) {
-                if (slit && sh[2] < 2) continue;
-                bad += check<double>(sh[0], sh[1], sh[2], ns, slit);
-                bad += check<float>(sh[0], sh[1], sh[2], ns, slit);
-                bad += check<uint16_t>(sh[0], sh[1], sh[2], ns, slit);
-            }
+        for (uint32_t blog = 0; blog <= 6 && sh[1] % (1u << blog) == 0; ++blog)
+            for (int ns = 1; ns <= 4; ++ns)
+                for (bool slit : {false, true}) {
+                    if (slit && sh[2] < 2) continue;
+                    bad += check<double>(sh[0], sh[1], sh[2], ns, slit, blog);
+                    bad += check<float>(sh[0], sh[1], sh[2], ns, slit, blog);
+                    bad += check<uint16_t>(sh[0], sh[1], sh[2], ns, slit, blog);
+                }
+    // the block height chosen for a plane: a slot's block of about 32 KB that divides ny
+    const uint32_t cases[][5] = {{256, 256, 2, 4, 4}, {512, 512, 2, 4, 3}, {256, 256, 2, 2, 5}, {128, 128, 3, 2, 5},
+                                 {32, 32, 3, 2, 5}, {256, 256, 2, 8, 3}, {64, 6, 3, 4, 1}, {1000, 7, 2, 8, 0},
+                                 {8, 64, 1, 2, 6}};
+    for (auto &c : cases)
+        if (pop_block_log2(c[0], c[1], c[2], c[3]) != c[4]) {
+            std::printf("FAIL block rows of %u x %u, %u species of %u bytes: 2^%u\n", c[0], c[1], c[2], c[3],
+                        pop_block_log2(c[0], c[1], c[2], c[3]));
+            ++bad;
+        }
     if (bad) return 1;
     std::printf("layout checks passed\n");
     return 0;

@@ -1,8 +1,9 @@
 """The population layout of the fused step on the host (tests/host_layout/check.cpp): for
-planes of every block height (1, 2, 4, 8 rows), one to four species and 2-, 4- and 8-byte
+planes of every block height that divides ny (1 to 64 rows), one to four species and 2-, 4- and 8-byte
 elements, periodic and slit, the element stored for each (node, slot, species) is a bijection
 onto the allocation, and each pulled element is the one stored for the upstream node (or the
-node's own opposite slot next to a wall).  No GPU is needed."""
+node's own opposite slot next to a wall); and the block height the library picks.  No GPU is
+needed."""
 import os
 import subprocess
 import tempfile
