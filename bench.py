@@ -33,12 +33,38 @@ HBM_PEAK_GBS = 8000.0
 Q = 19
 
 
+def code_text(src: str) -> str:
+    """C++ source without its comments, whitespace runs folded to one space (string and
+    character literals kept as they are)."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources of the fused step kernel (its counters are void once they change)."""
+    """Hash of the code of the fused step kernel, comments and layout aside (its counters are
+    void once the code changes)."""
     h = hashlib.sha256()
     for name in ("lbmix_step_kernel.h", "lbmix_step.hip", "lbmix_step.h", "lbmix_device.h"):
-        with open(os.path.join(ROOT, "paper_1507_04891_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1507_04891_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

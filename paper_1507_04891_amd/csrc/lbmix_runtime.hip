@@ -1,6 +1,7 @@
 // Host runtime of the multicomponent lattice-Boltzmann library: the context behind the C ABI
 // of include/lbmix.h.  It owns the device memory (double-buffered populations over the
-// fluid nodes, stored [p][node][species], potential, charge density, reduction scratch), maps the physical parameters
+// fluid nodes, stored per plane in blocks of rows of all 19 slots, potential, charge density,
+// reduction scratch), maps the physical parameters
 // to relaxation frequencies (Sec. IV: nu = v_T^2 (1/omega_visc - 1/2),
 // D = v_T^2 (1/omega_drag - 1/2)) and sequences a time step: one fused stream-collide
 // launch, then for charged runs the Poisson solve of the new charge density, used by the
