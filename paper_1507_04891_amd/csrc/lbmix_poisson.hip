@@ -46,12 +46,19 @@ __device__ inline double rhs(const PoissonArgs &a, uint32_t i, uint32_t z) {
     return -a.K * a.q[i] - a.bmean[0];
 }
 
+// One thread per node of the colour: thread t of plane z takes row y = t / nxh and the node
+// x = 2 (t mod nxh) + ((y + zc + colour) mod 2) of that row's colour, nxh = ceil(nx / 2).  The
+// nodes of a colour are independent, so the order does not change the result.  (One thread
+// per node with the other colour's threads returning took 8.9 us per half-sweep on the
+// 64 x 64 x 128 slit: 8192 one-wave work-groups, half of each wave idle.)
 __global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colour) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    const uint32_t nxh = (a.nx + 1) / 2;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nxh * a.ny) return;
+    const uint32_t y = t / nxh, z = blockIdx.y;
     const uint32_t zc = a.slit ? a.planes[z].zloc : z;   // colour by the channel's own lattice
-    if (((x + y + zc) & 1u) != (uint32_t)colour) return;
+    const uint32_t x = 2 * (t - y * nxh) + ((y + zc + (uint32_t)colour) & 1u);
+    if (x >= a.nx) return;
     const uint32_t i = (z * a.ny + y) * a.nx + x;
     const Stencil st = neighbours(a, a.psi, x, y, z);
     const double b = rhs(a, i, z);
@@ -1298,9 +1305,9 @@ __global__ __launch_bounds__(BLOCK) void plane_sums(const double *n, const doubl
 // Launchers.
 
 hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, a.nzf, &b);
-    hipLaunchKernelGGL(sor_half, g, b, 0, stream, a, colour);
+    const uint32_t per_plane = (a.nx + 1) / 2 * a.ny;
+    const dim3 g((per_plane + BLOCK - 1) / BLOCK, a.nzf);
+    hipLaunchKernelGGL(sor_half, g, dim3(BLOCK), 0, stream, a, colour);
     return hipGetLastError();
 }
 
