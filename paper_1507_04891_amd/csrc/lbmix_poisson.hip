@@ -215,11 +215,14 @@ __device__ inline MGNb mg_nb(const MGLevel &L, const double *e, uint32_t x, uint
     return {s, dg};
 }
 
+// One thread per cell of the colour (x + y + z) mod 2, mapped as in sor_half.
 __global__ __launch_bounds__(BLOCK) void mg_smooth(const MGLevel L, int colour) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nxh = (L.nx + 1) / 2;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nxh * L.ny) return;
+    const uint32_t y = t / nxh, z = blockIdx.y;
+    const uint32_t x = 2 * (t - y * nxh) + ((y + z + (uint32_t)colour) & 1u);
     if (x >= L.nx) return;
-    const uint32_t y = blockIdx.y, z = blockIdx.z;
-    if (((x + y + z) & 1u) != (uint32_t)colour) return;
     const uint32_t i = (z * L.ny + y) * L.nx + x;
     const MGNb nb = mg_nb(L, L.e, x, y, z);
     if (nb.diag > 0.0) L.e[i] = (nb.sum - L.r[i]) / nb.diag;
@@ -1346,9 +1349,9 @@ hipError_t launch_make_rhs(const PoissonArgs &a, double *r, hipStream_t stream) 
     return hipGetLastError();
 }
 hipError_t launch_mg_smooth(const MGLevel &L, int colour, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(L.nx, L.ny, L.nz, &b);
-    hipLaunchKernelGGL(mg_smooth, g, b, 0, stream, L, colour);
+    const uint32_t per_plane = (L.nx + 1) / 2 * L.ny;
+    const dim3 g((per_plane + BLOCK - 1) / BLOCK, L.nz);
+    hipLaunchKernelGGL(mg_smooth, g, dim3(BLOCK), 0, stream, L, colour);
     return hipGetLastError();
 }
 hipError_t launch_mg_restrict(const MGLevel &F, const MGLevel &C, hipStream_t stream) {
