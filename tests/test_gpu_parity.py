@@ -457,10 +457,13 @@ SMALL_STACK = dict(nx=8, ny=6, widths=(5, 9, 1, 12), sigmas=(-1e-3, -4e-4, -2e-4
                    scs=(10.0, 100.0, 1000.0, 1.0), n_ion=2e-3, debye_length=3.0, lateral=0.3)
 
 
-def test_channel_stack_direct_fp64_matches_each_channel(P, oracle_mod):
+@pytest.mark.parametrize("lateral", [(8, 6), (128, 8)], ids=["8x6", "128x8_fft"])
+def test_channel_stack_direct_fp64_matches_each_channel(P, oracle_mod, lateral):
     """Four channels of widths 5, 9, 1, 12 (own drag and wall charge, lateral charge waves)
-    in one stacked lattice: every channel follows its own oracle slit at the FP64 bar."""
-    st = WL.channel_stack(**SMALL_STACK)
+    in one stacked lattice: every channel follows its own oracle slit at the FP64 bar.  The
+    128 x 8 planes take the FFT passes of the direct solve, the 8 x 6 planes the register
+    transforms."""
+    st = WL.channel_stack(**dict(SMALL_STACK, nx=lateral[0], ny=lateral[1]))
     lat = P.from_workload(st, storage="f64", poisson=dict(method="direct"))
     lat.step(25)
     for c in range(len(st.widths)):
