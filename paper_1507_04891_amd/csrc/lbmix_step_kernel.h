@@ -224,23 +224,21 @@ template <> struct Codec<F16> {
     __device__ static S encode(C v, float sc, uint32_t rnd = 0) { return put<SR>(v * sc, rnd); }
 };
 
-// FP32 storage, stochastically rounded from FP64 arithmetic: the nearest FP32 value f of v and
-// its neighbour g on the side of v are chosen with probabilities that make the expected stored
-// value v (to 2^-17 of a unit in the last place: 16 random bits, the high half of rnd).  The
-// residual v - f and the spacing g - f are exact in FP64.
+// FP32 storage, stochastically rounded from FP64 arithmetic, on the bit pattern of v: the 29
+// mantissa bits that FP32 drops are the fraction of the gap from |v| truncated to FP32 to the
+// next FP32 magnitude.  Adding 16 random bits (and half a step) at their top and truncating
+// them rounds the magnitude up with probability equal to that fraction, to 2^-17 of a unit in
+// the last place (the high half of rnd); a carry into the exponent gives the next binade's
+// first value, and the truncated value converts to FP32 exactly.  Below FP32's normal range
+// the conversion rounds to nearest; non-finite values are kept.  (Choosing between f and its
+// neighbour by comparing the FP64 residual with a random fraction of the spacing took about
+// 20 vector instructions per value, this about 7.)
 __device__ inline float f64_to_f32_sr(double v, uint32_t rnd) {
-    const float f = float(v);
-    const double r = v - double(f);
-    const uint32_t bits = __float_as_uint(f);
-    // the neighbour on the side of v: away from zero when r has the sign of f, else toward
-    // zero; from a zero, the smallest subnormal with the sign of r
-    const uint32_t gb = f == 0.0f ? (r > 0.0 ? 1u : 0x80000001u)
-                                  : (((f > 0.0f) == (r > 0.0)) ? bits + 1u : bits - 1u);
-    const float g = __uint_as_float(gb);
-    const double s = fabs(double(g) - double(f));
-    const double u = (double(rnd >> 16) + 0.5) * (1.0 / 65536.0);
-    // r == 0 keeps f; a non-finite f is kept as it is
-    return (fabs(r) > u * s && isfinite(f)) ? g : f;
+    unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    b += (unsigned long long)(((rnd >> 16) << 13) + 4096u);
+    b &= ~((1ull << 29) - 1ull);
+    const float f = float(__builtin_bit_cast(double, b));
+    return isfinite(v) ? f : float(v);
 }
 
 template <> struct Codec<F32X> {
