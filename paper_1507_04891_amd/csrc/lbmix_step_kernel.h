@@ -233,12 +233,12 @@ template <> struct Codec<F16> {
 // the conversion rounds to nearest; non-finite values are kept.  (Choosing between f and its
 // neighbour by comparing the FP64 residual with a random fraction of the spacing took about
 // 20 vector instructions per value, this about 7.)
-__device__ inline float f64_to_f32_sr(double v, uint32_t rnd) {
+__host__ __device__ inline float f64_to_f32_sr(double v, uint32_t rnd) {
     unsigned long long b = __builtin_bit_cast(unsigned long long, v);
     b += (unsigned long long)(((rnd >> 16) << 13) + 4096u);
     b &= ~((1ull << 29) - 1ull);
     const float f = float(__builtin_bit_cast(double, b));
-    return isfinite(v) ? f : float(v);
+    return __builtin_isfinite(v) ? f : float(v);
 }
 
 template <> struct Codec<F32X> {

@@ -1,9 +1,14 @@
-// Host check of the population layout of the fused step: the element that the step stores for
-// every (node, slot, species) is a bijection onto the allocation, and the element that
-// direction p pulls at a node is the one stored for the upstream node (or, next to a wall,
-// the node's own value of the opposite slot).
+// Host checks of the fused step's data handling:
+// - the population layout: the element that the step stores for every (node, slot, species)
+//   is a bijection onto the allocation, and the element that direction p pulls at a node is
+//   the one stored for the upstream node (or, next to a wall, the node's own value of the
+//   opposite slot);
+// - the stochastic rounding of FP64 values to FP32 stores: over all 2^16 random inputs the
+//   result is one of the two FP32 values that bracket the exact one, and their mean is the
+//   exact value to 2^-17 of the gap.
 #include "lbmix_step_kernel.h"
 
+#include <cmath>
 #include <cstdio>
 #include <type_traits>
 #include <vector>
@@ -66,6 +71,38 @@ static int check(uint32_t nx, uint32_t ny, uint32_t nzf, int ns, bool slit, uint
     return bad;
 }
 
+static int check_rounding() {
+    int bad = 0;
+    std::vector<double> vals = {0.0, -0.0, 1.0, -1.0, 0.1, -0.1, 1.5 + 1e-12, 3.0e-5, -7.25e-3, 123456.789,
+                                1.0 - 1e-17, 2.0 - 1e-12, 1e30, -4.2e-30, double(0.1f), std::nextafter(1.0, 2.0)};
+    unsigned long long x = 88172645463325252ull;   // xorshift64 for more values over 60 decades
+    for (int i = 0; i < 200; ++i) {
+        x ^= x << 13; x ^= x >> 7; x ^= x << 17;
+        const double m = 1.0 + double(x >> 11) * 0x1.0p-53, e = double(int(x % 121) - 60);
+        vals.push_back(((x >> 3) & 1 ? -m : m) * std::pow(10.0, e / 2.0));
+    }
+    for (double v : vals) {
+        const float n = float(v);   // nearest; the other bracketing value is its neighbour toward v
+        float lo = n, hi = n;
+        if (double(n) < v) hi = std::nextafter(n, INFINITY);
+        if (double(n) > v) lo = std::nextafter(n, -INFINITY);
+        double sum = 0.0;
+        for (uint32_t k = 0; k < 65536; ++k) {
+            const float f = f64_to_f32_sr(v, k << 16);
+            if (f != lo && f != hi) {
+                ++bad;
+                break;
+            }
+            sum += double(f);
+        }
+        const double gap = double(hi) - double(lo);
+        if (gap > 0.0 && std::fabs(sum / 65536.0 - v) > 0x1.0p-17 * gap * 1.0000001) ++bad;
+        if (gap == 0.0 && sum != 65536.0 * v) ++bad;
+    }
+    if (bad) std::printf("FAIL stochastic rounding: %d values\n", bad);
+    return bad;
+}
+
 int main() {
     const uint32_t shapes[][3] = {{256, 8, 3}, {5, 7, 4}, {16, 12, 5}, {64, 2, 3}, {3, 24, 2}, {8, 6, 6},
                                   {1, 1, 3}, {40, 36, 3}, {7, 16, 4}, {4, 64, 3}, {2, 128, 2}};
@@ -90,6 +127,7 @@ int main() {
                         pop_block_log2(c[0], c[1], c[2], c[3]));
             ++bad;
         }
+    bad += check_rounding();
     if (bad) return 1;
     std::printf("layout checks passed\n");
     return 0;
