@@ -68,13 +68,15 @@ __global__ __launch_bounds__(BLOCK) void sor_half(const PoissonArgs a, int colou
 
 constexpr uint32_t RES_PLANES = 8;   // fluid planes per work-group of the residual kernel
 
+// One thread per node of a plane (256 per work-group) and RES_PLANES planes.
 __global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *partials) {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
-    if (x < a.nx) {
-        const uint32_t y = blockIdx.y;
-        const uint32_t z1 = min(a.nzf, (blockIdx.z + 1) * RES_PLANES);
-        for (uint32_t z = blockIdx.z * RES_PLANES; z < z1; ++z) {
+    if (t < a.nx * a.ny) {
+        const uint32_t y = t / a.nx, x = t - y * a.nx;
+        const uint32_t z1 = min(a.nzf, (blockIdx.y + 1) * RES_PLANES);
+#pragma unroll 4
+        for (uint32_t z = blockIdx.y * RES_PLANES; z < z1; ++z) {
             const uint32_t i = (z * a.ny + y) * a.nx + x;
             const Stencil st = neighbours(a, a.psi, x, y, z);
             const double b = rhs(a, i, z);
@@ -84,8 +86,7 @@ __global__ __launch_bounds__(BLOCK) void residual(const PoissonArgs a, double *p
             v[2] += a.psi[i];
         }
     }
-    const uint32_t bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    block_sum_store<3>(v, partials, gridDim.x * gridDim.y * gridDim.z, bid);
+    block_sum_store<3>(v, partials, gridDim.x * gridDim.y, blockIdx.x + gridDim.x * blockIdx.y);
 }
 
 // r = b - A psi on every fluid node, and per-block partial sums of r^2.
@@ -1315,10 +1316,9 @@ hipError_t launch_sor(const PoissonArgs &a, int colour, hipStream_t stream) {
 }
 
 hipError_t launch_residual(const PoissonArgs &a, double *partials, uint32_t *nb, hipStream_t stream) {
-    dim3 b;
-    const dim3 g = node_grid(a.nx, a.ny, (a.nzf + RES_PLANES - 1) / RES_PLANES, &b);
-    *nb = g.x * g.y * g.z;
-    hipLaunchKernelGGL(residual, g, b, 0, stream, a, partials);
+    const dim3 g((a.nx * a.ny + BLOCK - 1) / BLOCK, (a.nzf + RES_PLANES - 1) / RES_PLANES);
+    *nb = g.x * g.y;
+    hipLaunchKernelGGL(residual, g, dim3(BLOCK), 0, stream, a, partials);
     return hipGetLastError();
 }
 
