@@ -235,10 +235,11 @@ int lbmix_set_poisson(lbmix_ctx *ctx, double rel_tol, int max_sweeps, int check_
  * lbmix_set_poisson caps (or, with rel_tol == 0, fixes) the number of V-cycles per solve and
  * lbmix_stats counts cycles in place of sweeps.  2 direct: the operator of eq. `Poisson` is
  * diagonalised along x and y by orthonormal real Fourier bases (planes of up to 64 x 64
- * nodes one at a time on the FP64 matrix cores, larger ones by batched FP64 products) and
- * solved exactly along z, by a tridiagonal elimination per (x, y) mode and channel in a
- * slit or stack (from both ends towards the middle plane), by a third
- * Fourier basis in a periodic box; its result is exact to rounding, takes any extents and
+ * nodes one at a time on the FP64 matrix cores; larger ones by fast Fourier transforms when
+ * both extents are powers of two up to 1024, else by batched FP64 products) and solved
+ * exactly along z, by a tridiagonal elimination per (x, y) mode and channel in a slit or
+ * stack (from both ends towards the middle plane), by a third Fourier basis in a periodic
+ * box (fast transforms for more than 64 planes of a power-of-two count); its result is exact to rounding, takes any extents and
  * needs no warm start (rel_tol and max_sweeps do not apply; lbmix_stats counts one sweep
  * per solve and reports the residual of every check_every-th solve).  On a stack of channels
  * (lbmix_create_channels), whose widths are arbitrary, multigrid keeps every plane on every
